@@ -1,0 +1,209 @@
+/*
+ * mpslcc.h -- C ABI of the MI355X (gfx950) two-site H_eff x and local LCC solve library.
+ *
+ * The library implements the hot path of MPS-LCC (Sharma and Alavi, arXiv:1509.00216):
+ * the derivative of the transition element <Psi|H|Phi> with respect to the two-site
+ * tensor (Implementation section, local-derivative figure), i.e. the effective Hamiltonian
+ * of the two-site block applied to a block-sparse vector, and the local linear solve by
+ * conjugate gradients of the first-order equation (Theory section, equation for Phi^(n)),
+ * equivalently the stationarity of the local Hylleraas functional.
+ *
+ * Conventions used by every entry point
+ *  - Local states of one spatial orbital, in order: |0>, |up>, |dn>, |updn>,
+ *    |updn> = c+_up c+_dn |0>.  Quantum numbers (N, 2Sz) = (0,0), (1,1), (1,-1), (2,0).
+ *  - Fock ordering: spin orbital 2i (up) before 2i+1 (down), orbital i = chain position i.
+ *  - MPS bond j (j = 0..K) lies left of site j and its sectors are labelled by the (N, 2Sz)
+ *    of the sites left of it.  Site j maps sector q to q + qn(s).
+ *  - All matrices are row-major.  Device vectors are contiguous and on the context's device.
+ *  - Status codes: 0 = OK, > 0 warning, < 0 error.  lcc_last_error() gives a message.
+ *    No C++ exception or abort crosses this interface.
+ *  - Asynchronous calls run on the context's stream; synchronous calls say so.
+ *
+ * Ownership: handles are owned by the library and freed by their destroy call
+ * (destroy(NULL) is a no-op).  Host input arrays are copied; the caller may free them after
+ * the call returns.  Device vectors belong to the caller; the library keeps no pointer to
+ * them after a call returns.  A context is not thread safe; distinct contexts are.
+ */
+#ifndef MPSLCC_H
+#define MPSLCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lcc_status;
+#define LCC_OK 0
+#define LCC_NOT_CONVERGED 1   /* solve stopped at max_iter / max_outer; x holds the last iterate */
+#define LCC_ERR_ARG (-1)      /* invalid argument or inconsistent descriptor */
+#define LCC_ERR_QN (-2)       /* a block violates the (N, 2Sz) selection rule */
+#define LCC_ERR_NOT_SPD (-3)  /* p^T A p <= 0 met in conjugate gradients */
+#define LCC_ERR_NAN (-4)      /* non-finite value in an input or an iterate */
+#define LCC_ERR_OOM (-5)      /* device allocation failed */
+#define LCC_ERR_HIP (-6)      /* a HIP runtime call failed */
+#define LCC_ERR_STATE (-7)    /* handle in the wrong state (e.g. host-only context) */
+#define LCC_ERR_NODEV (-8)    /* no usable gfx950 device */
+
+typedef int32_t lcc_precision;
+#define LCC_FP64 0    /* FP64 operands, FP64 MFMA */
+#define LCC_FP32 1    /* FP32 operands, FP32 MFMA, FP32 accumulation */
+#define LCC_BF16X3 2  /* FP32 operands split into bf16 hi + lo; hi*hi + hi*lo + lo*hi on bf16 MFMA,
+                         FP32 accumulation */
+
+typedef struct lcc_context_s* lcc_context;
+typedef struct lcc_hamiltonian_s* lcc_hamiltonian;
+typedef struct lcc_env_s* lcc_env;
+
+/* ---------------------------------------------------------------------------------------
+ * Context.  device >= 0 selects a HIP device (must be gfx950); device = -1 makes a host-only
+ * context on which only lcc_create_hamiltonian and the Hamiltonian queries work.
+ * stream: the hipStream_t all asynchronous work of this context is queued on, borrowed
+ * as given (NULL = the device's null stream, which orders with other null-stream work,
+ * e.g. PyTorch's default stream).  The caller keeps it alive until the context is
+ * destroyed.
+ * ------------------------------------------------------------------------------------- */
+lcc_status lcc_context_create(int32_t device, void* stream, lcc_context* out);
+void lcc_context_destroy(lcc_context ctx);
+/* Message of the last failing call on ctx (or of the last context-less failure if ctx is
+ * NULL).  Valid until the next call on the same context. */
+const char* lcc_last_error(lcc_context ctx);
+/* Wait for all work queued on the context's stream. */
+lcc_status lcc_context_synchronize(lcc_context ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * Hamiltonian (Theory section, partitioned-Hamiltonian equation, read with the usual 1/2):
+ *   H = sum_{ij,s} h[i][j] a+_{is} a_{js}
+ *     + 1/2 sum_{ijkl,s,t} eri[i][j][k][l] a+_{is} a+_{kt} a_{lt} a_{js}   (chemists' (ij|kl))
+ *     + sum_i u[i] n_{i up} n_{i dn} + e_const
+ * restricted to N = n_elec, 2Sz = two_sz.  It is compiled into an MPO (MPO equation) whose
+ * bond dimension stays O(k^2) for two-body terms (Implementation section, bound k^2 with
+ * spin adaptation; here spin orbitals are used and D is about 2 k^2 at the centre).
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_orb;           /* k, number of spatial orbitals = MPS length (1..64) */
+  int32_t n_elec;          /* N */
+  int32_t two_sz;          /* 2 Sz */
+  const double* h;         /* n_orb*n_orb, need not be symmetric (used as given) */
+  const double* eri;       /* n_orb^4 or NULL */
+  const double* u_onsite;  /* n_orb or NULL */
+  double e_const;
+  int32_t switch_bond;     /* bond from which two-operator channels are labelled by their
+                              right partners; < 0 selects n_orb/2 + 1 */
+} lcc_ham_desc;
+
+lcc_status lcc_create_hamiltonian(lcc_context ctx, const lcc_ham_desc* desc, lcc_hamiltonian* out);
+void lcc_hamiltonian_destroy(lcc_hamiltonian ham);
+/* MPO bond dimensions D_0..D_K (bond_dims has n_orb + 1 entries). */
+lcc_status lcc_hamiltonian_bond_dims(lcc_hamiltonian ham, int32_t* bond_dims);
+/* Channel quantum-number shifts of MPO bond `bond`: dn[D], d2sz[D] (the change of (N, 2Sz)
+ * caused by the channel's operator on the sites left of the bond). */
+lcc_status lcc_hamiltonian_channels(lcc_hamiltonian ham, int32_t bond, int32_t* dn, int32_t* d2sz);
+/* Nonzero MPO entries of site `site`.  Call with w_in == NULL to get *count; then arrays of
+ * *count entries: w_in, w_out and 16 doubles per entry (row-major <s'|W|s>). */
+lcc_status lcc_hamiltonian_site_mpo(lcc_hamiltonian ham, int32_t site, int64_t* count,
+                                    int32_t* w_in, int32_t* w_out, double* mats);
+
+/* ---------------------------------------------------------------------------------------
+ * MPS (MPS equation) as block-sparse site tensors.
+ * ------------------------------------------------------------------------------------- */
+typedef struct { int32_t n; int32_t two_sz; int32_t dim; } lcc_sector;
+typedef struct {
+  int32_t left;   /* sector index within bond j */
+  int32_t s;      /* local state 0..3 */
+  int32_t right;  /* sector index within bond j+1; must equal left + qn(s) */
+  const double* data;  /* host, dim(left) x dim(right) row-major */
+} lcc_mps_block;
+typedef struct {
+  int32_t n_sites;               /* K */
+  const int32_t* bond_offsets;   /* K+2 entries: bond j owns sectors[bond_offsets[j] .. bond_offsets[j+1]) */
+  const lcc_sector* sectors;     /* sectors of each bond, (n, two_sz) strictly increasing */
+  const int64_t* block_offsets;  /* K+1 entries: site j owns blocks[block_offsets[j] .. block_offsets[j+1]) */
+  const lcc_mps_block* blocks;
+} lcc_mps_desc;
+
+/* Build the left environment (sites < site) and right environment (sites > site+1) of
+ * the two-site block (site, site+1) and the contraction plan of H_eff (transition-element
+ * figure; the derivative graph of the local-derivative figure).  Sites left of the block
+ * must be left-canonical and sites right of it right-canonical; this is checked on the
+ * device to 1e-10 (LCC_ERR_ARG otherwise).  The block's own tensors are ignored.
+ * Synchronous.  The environment keeps its own copies of everything it needs. */
+lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps,
+                                  int32_t site, lcc_env* out);
+void lcc_env_destroy(lcc_env env);
+
+/* Layout of two-site vectors x, y, b (the unknown tensor of the local problem).
+ * Blocks are (left sector a of bond site, s1, s2, right sector b of bond site+2) with
+ * qn(a) + qn(s1) + qn(s2) = qn(b).  Element (i, j) of a block sits at
+ * offset + i * ld + j. */
+typedef struct {
+  int64_t n_elements;   /* length of a two-site vector */
+  int32_t n_blocks;
+  int32_t n_sectors;    /* middle-bond sectors (the vector is block diagonal over them) */
+  int32_t mpo_bond_dim; /* D of the middle MPO bond: the number of terms L~ (x) R~ */
+  int32_t reserved;
+  double flops_per_apply;  /* exact algorithmic flops of one H_eff x (see lcc_env_flops) */
+} lcc_layout_info;
+typedef struct { int32_t left, s1, s2, right; int64_t offset; int32_t ld, rows, cols; } lcc_block_entry;
+/* blocks may be NULL; otherwise it receives info->n_blocks entries. */
+lcc_status lcc_env_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* blocks);
+
+/* Flop counts of one H_eff x: 2*m*n*k summed over every block product the plan performs
+ * (phase 1: enlarged left operator times x; phase 2: times enlarged right operator).
+ * Only symmetry-allowed blocks and nonzero MPO entries are counted; no padding. */
+lcc_status lcc_env_flops(lcc_env env, double* phase1, double* phase2);
+
+/* y = H_eff x.  precision LCC_FP64: x, y are double*; LCC_FP32 / LCC_BF16X3: float*.
+ * x and y must not overlap.  Asynchronous on the context stream. */
+lcc_status lcc_apply_heff(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev);
+
+/* Time the two grouped-GEMM phases of lcc_apply_heff with HIP events on the context stream:
+ * runs `reps` applications y = H_eff x and returns the mean duration of each phase in
+ * milliseconds (phase 1: enlarged left operator times x; phase 2: times enlarged right
+ * operator, accumulated into y).  Synchronous.  Buffers as for lcc_apply_heff. */
+lcc_status lcc_env_profile_apply(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev,
+                                 int32_t reps, float* ms_phase1, float* ms_phase2);
+
+/* Lowest eigenvalue of H_eff by Lanczos with full re-orthogonalisation in FP64 (the DMRG
+ * energy functional, Implementation section): `steps` Krylov vectors from a start vector
+ * drawn by a counter-based generator from `seed`.  Returns the lowest Ritz value and the
+ * norm of its residual ||H_eff u - theta u|| (a rigorous bound: some eigenvalue lies within
+ * it).  Synchronous; uses steps+2 device vectors of workspace. */
+lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual);
+
+/* ---------------------------------------------------------------------------------------
+ * Local LCC solve:  Q (H_eff - e0) Q x = Q b,  Q = 1 - v v^T (v unit norm) or Q = 1.
+ * Conjugate gradients (Implementation section).  precision selects the inner operator;
+ * LCC_FP64 runs plain FP64 CG; LCC_FP32 / LCC_BF16X3 run an FP64 iterative refinement whose
+ * correction equations are solved by CG with the low-precision operator.  Dot products,
+ * scalars, the residual r = Q b - A x of every refinement step and the energy are FP64.
+ * Synchronous.
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  lcc_precision precision;
+  int32_t max_iter;      /* CG iterations in total (default 1000 when <= 0) */
+  double tol;            /* stop when ||Q b - A x|| <= tol ||Q b|| in FP64 (default 1e-10) */
+  double inner_tol;      /* relative tolerance of each low-precision correction solve
+                            (default 1e-6 FP32, 1e-4 BF16X3) */
+  int32_t max_outer;     /* refinement steps (default 20) */
+  int32_t replace_every; /* FP64 CG: recompute r = Q b - A x every this many iterations (default 50) */
+} lcc_solve_opts;
+typedef struct {
+  int32_t iterations;    /* CG iterations, all precisions */
+  int32_t outer;         /* refinement steps (1 for FP64) */
+  int32_t applies_fp64;  /* H_eff x products in FP64 */
+  int32_t applies_low;   /* H_eff x products in FP32 / BF16X3 */
+  double rel_residual;   /* final ||Q b - A x|| / ||Q b|| in FP64 */
+  double hylleraas;      /* J(x) = x^T A x - 2 b^T Q x, FP64 */
+  double e2;             /* -b^T Q x, equal to J at the exact solution */
+  double ms_total;       /* wall time of the call */
+} lcc_solve_info;
+/* b_dev, v_dev, x_dev: double*.  x_dev holds the initial guess on entry (zeros for none)
+ * and the solution on return.  v_dev may be NULL. */
+lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const double* b_dev,
+                               double e0, const double* v_dev, double* x_dev, lcc_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,268 @@
+// C ABI entry points: argument checks, error capture, and dispatch into the planner,
+// kernels and solver.  No exception crosses this boundary.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "state.h"
+
+using namespace lcc;
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_last_error;
+
+lcc_status fail(lcc_context ctx, lcc_status code, const std::string& msg) {
+  if (ctx) ctx->c.err = msg;
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+lcc_status guarded(lcc_context ctx, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(ctx, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, LCC_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(ctx, LCC_ERR_ARG, e.what());
+  } catch (...) {
+    return fail(ctx, LCC_ERR_ARG, "unknown failure");
+  }
+}
+
+void require_device(lcc_context ctx) {
+  if (!ctx || ctx->c.device < 0) throw Error{LCC_ERR_STATE, "this call needs a context on a device"};
+  check_hip(hipSetDevice(ctx->c.device), "hipSetDevice");
+}
+
+}  // namespace
+
+extern "C" {
+
+lcc_status lcc_context_create(int32_t device, void* stream, lcc_context* out) {
+  if (!out) return fail(nullptr, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(nullptr, [&]() -> lcc_status {
+    std::unique_ptr<lcc_context_s> c(new lcc_context_s());
+    c->c.device = device;
+    c->c.handle = c.get();
+    if (device >= 0) {
+      int n = 0;
+      if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+        (void)hipGetLastError();
+        throw Error{LCC_ERR_NODEV, "no HIP device " + std::to_string(device)};
+      }
+      hipDeviceProp_t prop;
+      check_hip(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+      if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        throw Error{LCC_ERR_NODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950"};
+      check_hip(hipSetDevice(device), "hipSetDevice");
+      c->c.stream = static_cast<hipStream_t>(stream);
+      c->c.dot_partial.alloc(sizeof(double) * kDotBlocks);
+      c->c.dot_out.alloc(sizeof(double) * 8);
+      check_hip(hipHostMalloc(reinterpret_cast<void**>(&c->c.host_scalar), sizeof(double) * 8, hipHostMallocDefault),
+                "hipHostMalloc");
+    }
+    *out = c.release();
+    return LCC_OK;
+  });
+}
+
+void lcc_context_destroy(lcc_context ctx) {
+  if (!ctx) return;
+  if (ctx->c.device >= 0) {
+    (void)hipSetDevice(ctx->c.device);
+    if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+    if (ctx->c.host_scalar) (void)hipHostFree(ctx->c.host_scalar);
+    if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+  }
+  delete ctx;
+}
+
+const char* lcc_last_error(lcc_context ctx) {
+  if (ctx) return ctx->c.err.c_str();
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  return g_last_error.c_str();
+}
+
+lcc_status lcc_context_synchronize(lcc_context ctx) {
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    check_hip(hipStreamSynchronize(ctx->c.stream), "hipStreamSynchronize");
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_create_hamiltonian(lcc_context ctx, const lcc_ham_desc* d, lcc_hamiltonian* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!d || !d->h) throw Error{LCC_ERR_ARG, "descriptor or h is NULL"};
+    if (d->n_orb < 2 || d->n_orb > 64) throw Error{LCC_ERR_ARG, "n_orb must be in [2, 64]"};
+    if (d->n_elec < 0 || d->n_elec > 2 * d->n_orb) throw Error{LCC_ERR_ARG, "n_elec out of range"};
+    if (std::abs(d->two_sz) > d->n_elec || ((d->n_elec + d->two_sz) & 1)) throw Error{LCC_ERR_QN, "two_sz incompatible with n_elec"};
+    std::unique_ptr<lcc_hamiltonian_s> h(new lcc_hamiltonian_s());
+    HamDesc& hd = h->h.desc;
+    const size_t K = (size_t)d->n_orb;
+    hd.K = d->n_orb;
+    hd.N = d->n_elec;
+    hd.two_sz = d->two_sz;
+    hd.h.assign(d->h, d->h + K * K);
+    if (d->eri) hd.eri.assign(d->eri, d->eri + K * K * K * K);
+    if (d->u_onsite) hd.u.assign(d->u_onsite, d->u_onsite + K);
+    hd.e_const = d->e_const;
+    hd.switch_bond = d->switch_bond;
+    for (double v : hd.h)
+      if (!std::isfinite(v)) throw Error{LCC_ERR_NAN, "non-finite h"};
+    for (double v : hd.eri)
+      if (!std::isfinite(v)) throw Error{LCC_ERR_NAN, "non-finite eri"};
+    for (double v : hd.u)
+      if (!std::isfinite(v)) throw Error{LCC_ERR_NAN, "non-finite u"};
+    const std::string err = build_mpo(hd, h->h.mpo);
+    if (!err.empty()) throw Error{LCC_ERR_ARG, err};
+    h->h.ctx = ctx ? &ctx->c : nullptr;
+    *out = h.release();
+    return LCC_OK;
+  });
+}
+
+void lcc_hamiltonian_destroy(lcc_hamiltonian ham) { delete ham; }
+
+lcc_status lcc_hamiltonian_bond_dims(lcc_hamiltonian ham, int32_t* dims) {
+  if (!ham || !dims) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  for (int b = 0; b <= ham->h.mpo.K; ++b) dims[b] = (int32_t)ham->h.mpo.dq[b].size();
+  return LCC_OK;
+}
+
+lcc_status lcc_hamiltonian_channels(lcc_hamiltonian ham, int32_t bond, int32_t* dn, int32_t* d2sz) {
+  if (!ham || !dn || !d2sz) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  if (bond < 0 || bond > ham->h.mpo.K) return fail(nullptr, LCC_ERR_ARG, "bond out of range");
+  const auto& dq = ham->h.mpo.dq[bond];
+  for (size_t i = 0; i < dq.size(); ++i) {
+    dn[i] = dq[i].n;
+    d2sz[i] = dq[i].sz;
+  }
+  return LCC_OK;
+}
+
+lcc_status lcc_hamiltonian_site_mpo(lcc_hamiltonian ham, int32_t site, int64_t* count, int32_t* w_in,
+                                    int32_t* w_out, double* mats) {
+  if (!ham || !count) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  if (site < 0 || site >= ham->h.mpo.K) return fail(nullptr, LCC_ERR_ARG, "site out of range");
+  const auto& W = ham->h.mpo.W[site];
+  if (!w_in) {
+    *count = (int64_t)W.size();
+    return LCC_OK;
+  }
+  if (*count < (int64_t)W.size() || !w_out || !mats) return fail(nullptr, LCC_ERR_ARG, "output arrays too small");
+  for (size_t i = 0; i < W.size(); ++i) {
+    w_in[i] = W[i].win;
+    w_out[i] = W[i].wout;
+    std::memcpy(mats + 16 * i, W[i].m, sizeof(double) * 16);
+  }
+  *count = (int64_t)W.size();
+  return LCC_OK;
+}
+
+lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t site,
+                                  lcc_env* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    if (!ham || !mps) throw Error{LCC_ERR_ARG, "NULL argument"};
+    std::unique_ptr<lcc_env_s> e(new lcc_env_s());
+    e->e.reset(build_env(&ctx->c, ham->h, *mps, site));
+    *out = e.release();
+    return LCC_OK;
+  });
+}
+
+void lcc_env_destroy(lcc_env env) {
+  if (!env) return;
+  if (env->e && env->e->ctx) {
+    (void)hipSetDevice(env->e->ctx->device);
+    (void)hipStreamSynchronize(env->e->ctx->stream);
+  }
+  delete env;
+}
+
+lcc_status lcc_env_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* blocks) {
+  if (!env || !info) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  const Env& e = *env->e;
+  info->n_elements = e.n_elements;
+  info->n_blocks = (int32_t)e.layout.size();
+  info->n_sectors = (int32_t)e.sectors.size();
+  info->mpo_bond_dim = e.D_mid;
+  info->reserved = 0;
+  info->flops_per_apply = e.plan.flops1 + e.plan.flops2;
+  if (blocks) std::memcpy(blocks, e.layout.data(), sizeof(lcc_block_entry) * e.layout.size());
+  return LCC_OK;
+}
+
+lcc_status lcc_env_flops(lcc_env env, double* phase1, double* phase2) {
+  if (!env || !phase1 || !phase2) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  *phase1 = env->e->plan.flops1;
+  *phase2 = env->e->plan.flops2;
+  return LCC_OK;
+}
+
+lcc_status lcc_apply_heff(lcc_env env, lcc_precision precision, const void* x, void* y) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!x || !y) throw Error{LCC_ERR_ARG, "x or y is NULL"};
+    if (x == y) throw Error{LCC_ERR_ARG, "x and y must not overlap"};
+    if (precision != LCC_FP64 && precision != LCC_FP32 && precision != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    apply_heff(*env->e, precision, x, y);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_env_profile_apply(lcc_env env, lcc_precision precision, const void* x, void* y, int32_t reps,
+                                 float* ms1, float* ms2) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!x || !y || !ms1 || !ms2 || x == y) throw Error{LCC_ERR_ARG, "invalid buffers"};
+    if (precision != LCC_FP64 && precision != LCC_FP32 && precision != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    if (precision != LCC_FP64) ensure_fp32(*env->e);
+    profile_apply(*env->e, precision, x, y, reps, ms1, ms2);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!theta || !residual) throw Error{LCC_ERR_ARG, "NULL output"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    lowest_eigenvalue(*env->e, steps, seed, theta, residual);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const double* b, double e0, const double* v,
+                               double* x, lcc_solve_info* info) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!b || !x) throw Error{LCC_ERR_ARG, "b or x is NULL"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    lcc_solve_opts o{};
+    if (opts) o = *opts;
+    return solve_local(*env->e, o, b, e0, v, x, info);
+  });
+}
+
+}  // extern "C"

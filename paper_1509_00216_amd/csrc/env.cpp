@@ -1,0 +1,771 @@
+// Environments, the enlarged two-site operators and the H_eff contraction plan.
+//
+// Transition-element figure (Implementation section): <Psi|H|Psi> is contracted site by
+// site; cutting out the two-site tensor at (l, l+1) leaves
+//     H_eff = sum_{w1} Lt^{w1} (x) Rt^{w1},          w1 = channels of MPO bond l+1,
+//     Lt^{w1}[(a',s1'),(a,s1)] = sum_w W_l^{w,w1}[s1',s1] L^w[a',a]      (left block + site l)
+//     Rt^{w1}[(s2',b'),(s2,b)] = sum_w2 W_{l+1}^{w1,w2}[s2',s2] R^w2[b',b] (site l+1 + right block)
+// so that, with the two-site vector stored as one matrix X_q per middle-bond sector q
+// (rows (a,s1), columns (s2,b)),
+//     phase 1:  T_{w1,q} = Lt^{w1} X_q            (grouped GEMM over L blocks)
+//     phase 2:  Y_{q'}  += T_{w1,q} Rt^{w1 T}     (grouped GEMM over R blocks),  q' = q + dq(w1).
+// The MPO sums over w and w2 (the "W mixing") are folded in once per environment: a
+// single contributing block is referenced with its coefficient as the GEMM alpha, several
+// are pre-summed into a merged block.  Environments themselves are built on the device by
+// the same grouped GEMM:  L_{j+1}^{w'} = sum W_j^{w,w'}[s',s] A^{s' T} L_j^w A^s.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <unordered_map>
+
+#include "state.h"
+
+namespace lcc {
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error{LCC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void DevBuf::alloc(size_t n) {
+  release();
+  if (n == 0) n = 16;
+  n = (n + 255) & ~(size_t)255;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error{e == hipErrorOutOfMemory ? LCC_ERR_OOM : LCC_ERR_HIP,
+                "device allocation of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
+  }
+  bytes = n;
+}
+
+template <class T>
+void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
+  buf.alloc(v.size() * sizeof(T));
+  if (!v.empty()) check_hip(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  check_hip(hipStreamSynchronize(s), "upload sync");
+}
+template void upload<double>(DevBuf&, const std::vector<double>&, hipStream_t);
+template void upload<float>(DevBuf&, const std::vector<float>&, hipStream_t);
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// Grouped GEMM launch construction
+// ---------------------------------------------------------------------------------------
+struct GemmBuilder {
+  std::vector<GemmTerm> terms;
+  std::vector<GemmGroup> groups;
+  double flops = 0;
+  void group(int8_t c_base, int64_t c_off, int ldc, int m, int n, bool accumulate) {
+    GemmGroup g{};
+    g.c_off = c_off;
+    g.ldc = ldc;
+    g.m = m;
+    g.n = n;
+    g.c_base = c_base;
+    g.accumulate = accumulate ? 1 : 0;
+    g.term_begin = g.term_end = (int32_t)terms.size();
+    groups.push_back(g);
+  }
+  void term(int8_t a_base, int64_t a_off, int lda, int8_t b_base, int64_t b_off, int ldb, int k, double alpha) {
+    GemmTerm t{};
+    t.a_base = a_base;
+    t.a_off = a_off;
+    t.lda = lda;
+    t.b_base = b_base;
+    t.b_off = b_off;
+    t.ldb = ldb;
+    t.k = k;
+    t.alpha = alpha;
+    terms.push_back(t);
+    GemmGroup& g = groups.back();
+    g.term_end = (int32_t)terms.size();
+    flops += 2.0 * g.m * (double)g.n * k;
+  }
+};
+
+int shape_for(int m) { return m <= 16 ? TILE_32x32 : TILE_64x64; }
+void shape_dims(int shape, int& bm, int& bn) {
+  if (shape == TILE_64x64) { bm = 64; bn = 64; } else { bm = 16; bn = 64; }
+}
+
+std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s) {
+  std::vector<GemmLaunch> out;
+  for (int shape : {TILE_64x64, TILE_32x32}) {
+    int bm, bn;
+    shape_dims(shape, bm, bn);
+    std::vector<GemmTerm> terms;
+    std::vector<GemmGroup> groups;
+    std::vector<GemmTile> tiles;
+    for (const GemmGroup& g0 : b.groups) {
+      if (g0.m <= 0 || g0.n <= 0) continue;
+      if (shape_for(g0.m) != shape) continue;
+      GemmGroup g = g0;
+      g.term_begin = (int32_t)terms.size();
+      for (int t = g0.term_begin; t < g0.term_end; ++t) terms.push_back(b.terms[t]);
+      g.term_end = (int32_t)terms.size();
+      g.tiles_n = (g.n + bn - 1) / bn;
+      const int tiles_m = (g.m + bm - 1) / bm;
+      const int gi = (int)groups.size();
+      groups.push_back(g);
+      for (int t = 0; t < tiles_m * g.tiles_n; ++t) tiles.push_back(GemmTile{gi, t});
+    }
+    if (tiles.empty()) continue;
+    if (tiles.size() > (size_t)INT32_MAX) throw Error{LCC_ERR_ARG, "plan too large"};
+    GemmLaunch L;
+    L.ta = ta;
+    L.tb = tb;
+    L.shape = shape;
+    L.n_tiles = (int)tiles.size();
+    upload(L.terms, terms, s);
+    upload(L.groups, groups, s);
+    upload(L.tiles, tiles, s);
+    out.push_back(std::move(L));
+  }
+  return out;
+}
+
+void run_gemm64(const std::vector<GemmLaunch>& Ls, const Bases<double>& b, hipStream_t s) {
+  for (const GemmLaunch& L : Ls)
+    check_hip(launch_gemm_f64(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
+                              L.n_tiles, L.ta, L.tb, L.shape, b, s),
+              "gemm f64 launch");
+}
+
+struct MixBuilder {
+  std::vector<MixTerm> terms;
+  std::vector<MixGroup> groups;
+  void group(int8_t dst_base, int64_t dst_off, int count, int8_t src_base) {
+    MixGroup g{};
+    g.dst_off = dst_off;
+    g.count = count;
+    g.dst_base = dst_base;
+    g.src_base = src_base;
+    g.term_begin = g.term_end = (int32_t)terms.size();
+    groups.push_back(g);
+  }
+  void term(int64_t src_off, double alpha) {
+    terms.push_back(MixTerm{src_off, alpha});
+    groups.back().term_end = (int32_t)terms.size();
+  }
+};
+
+void run_mix(const MixBuilder& mb, const Bases<double>& b, hipStream_t s) {
+  std::vector<MixTile> tiles;
+  for (size_t g = 0; g < mb.groups.size(); ++g) {
+    const int chunks = (mb.groups[g].count + 1023) / 1024;
+    for (int c = 0; c < chunks; ++c) tiles.push_back(MixTile{(int32_t)g, c});
+  }
+  if (tiles.empty()) return;
+  DevBuf dt, dg, dtl;
+  upload(dt, mb.terms, s);
+  upload(dg, mb.groups, s);
+  upload(dtl, tiles, s);
+  check_hip(launch_mix_f64(dt.as<MixTerm>(), dg.as<MixGroup>(), dtl.as<MixTile>(), (int)tiles.size(), b, s),
+            "mix launch");
+  check_hip(hipStreamSynchronize(s), "mix sync");
+}
+
+// ---------------------------------------------------------------------------------------
+// MPS on the device
+// ---------------------------------------------------------------------------------------
+struct SiteBlock {
+  int l, s, r;
+  int64_t off;
+  int rows, cols;
+};
+struct DeviceMps {
+  int K = 0;
+  std::vector<Bond> bonds;
+  std::vector<std::vector<SiteBlock>> sites;
+  DevBuf data;
+};
+
+void load_mps(const lcc_mps_desc& d, int N, int two_sz, hipStream_t s, DeviceMps& out) {
+  if (d.n_sites < 2 || !d.bond_offsets || !d.sectors || !d.block_offsets || !d.blocks)
+    throw Error{LCC_ERR_ARG, "incomplete MPS descriptor"};
+  const int K = d.n_sites;
+  out.K = K;
+  out.bonds.resize(K + 1);
+  for (int j = 0; j <= K; ++j) {
+    const int b0 = d.bond_offsets[j], b1 = d.bond_offsets[j + 1];
+    if (b1 < b0) throw Error{LCC_ERR_ARG, "bond offsets must be non-decreasing"};
+    Bond& B = out.bonds[j];
+    for (int i = b0; i < b1; ++i) {
+      const lcc_sector& sc = d.sectors[i];
+      if (sc.dim <= 0) throw Error{LCC_ERR_ARG, "sector dimensions must be positive"};
+      QN q(sc.n, sc.two_sz);
+      if (!B.q.empty() && !(B.q.back() < q)) throw Error{LCC_ERR_ARG, "bond sectors must be strictly increasing"};
+      B.index[q] = (int)B.q.size();
+      B.q.push_back(q);
+      B.dim.push_back(sc.dim);
+    }
+  }
+  if (out.bonds[0].q.size() != 1 || out.bonds[0].q[0] != QN(0, 0) || out.bonds[0].dim[0] != 1)
+    throw Error{LCC_ERR_QN, "bond 0 must hold the single sector (0, 0) of dimension 1"};
+  if (out.bonds[K].q.size() != 1 || out.bonds[K].q[0] != QN(N, two_sz) || out.bonds[K].dim[0] != 1)
+    throw Error{LCC_ERR_QN, "bond K must hold the single sector (N, 2Sz) of dimension 1"};
+  out.sites.resize(K);
+  int64_t total = 0;
+  for (int j = 0; j < K; ++j) {
+    std::set<std::pair<int, int>> seen;
+    for (int64_t i = d.block_offsets[j]; i < d.block_offsets[j + 1]; ++i) {
+      const lcc_mps_block& b = d.blocks[i];
+      const Bond &L = out.bonds[j], &R = out.bonds[j + 1];
+      if (b.left < 0 || b.left >= (int)L.q.size() || b.right < 0 || b.right >= (int)R.q.size() || b.s < 0 ||
+          b.s > 3 || !b.data)
+        throw Error{LCC_ERR_ARG, "MPS block index out of range at site " + std::to_string(j)};
+      if (L.q[b.left] + local_qn(b.s) != R.q[b.right])
+        throw Error{LCC_ERR_QN, "MPS block violates the (N, 2Sz) rule at site " + std::to_string(j)};
+      if (!seen.insert({b.left, b.s}).second) throw Error{LCC_ERR_ARG, "duplicate MPS block"};
+      SiteBlock sb{b.left, b.s, b.right, total, L.dim[b.left], R.dim[b.right]};
+      total += (int64_t)sb.rows * sb.cols;
+      out.sites[j].push_back(sb);
+    }
+  }
+  std::vector<double> host(total);
+  for (int j = 0; j < K; ++j) {
+    int64_t i = d.block_offsets[j];
+    for (const SiteBlock& sb : out.sites[j]) {
+      std::memcpy(host.data() + sb.off, d.blocks[i].data, sizeof(double) * sb.rows * sb.cols);
+      ++i;
+    }
+  }
+  for (double v : host)
+    if (!std::isfinite(v)) throw Error{LCC_ERR_NAN, "non-finite MPS entry"};
+  upload(out.data, host, s);
+}
+
+// ---------------------------------------------------------------------------------------
+// Environment steps
+// ---------------------------------------------------------------------------------------
+inline double wcoef(const MpoEntry& e, int sp, int s) { return e.m[sp * 4 + s]; }
+
+// L_{j+1}^{w'}[a', a] = sum_{w,s',s} W_j^{w,w'}[s',s] (A^{s'T} L_j^w A^s)[a', a]
+Environment left_step(const Environment& L, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st) {
+  const Bond& bj = mps.bonds[j];
+  const Bond& bn = mps.bonds[j + 1];
+  std::map<std::pair<int, int>, int> A;  // (left sector, s) -> block
+  for (size_t i = 0; i < mps.sites[j].size(); ++i) A[{mps.sites[j][i].l, mps.sites[j][i].s}] = (int)i;
+  auto Ablk = [&](int l, int s) -> const SiteBlock* {
+    auto it = A.find({l, s});
+    return it == A.end() ? nullptr : &mps.sites[j][it->second];
+  };
+  // enumerate sandwiches S(w, s', s, c) and their destinations
+  struct SKey { int w, sp, s, c; bool operator<(const SKey& o) const { return std::tie(w, sp, s, c) < std::tie(o.w, o.sp, o.s, o.c); } };
+  std::map<SKey, int64_t> s_off;      // sandwich -> offset in S buffer
+  std::map<std::tuple<int, int, int>, int64_t> u_off;  // (w, s, c) -> offset in U buffer
+  struct Dest { int wp, ap, a; };
+  std::map<std::tuple<int, int, int>, std::vector<std::pair<SKey, double>>> dest;  // (w', a, a') -> terms
+  std::vector<std::vector<int>> L_by_w(mpo.dq[j].size());
+  for (size_t i = 0; i < L.blocks.size(); ++i) L_by_w[L.blocks[i].w].push_back((int)i);
+  int64_t u_total = 0, s_total = 0;
+  for (const MpoEntry& e : mpo.W[j]) {
+    for (int bi : L_by_w[e.win]) {
+      const EnvBlock& lb = L.blocks[bi];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s = 0; s < 4; ++s) {
+          const double c = wcoef(e, sp, s);
+          if (c == 0.0) continue;
+          const SiteBlock* as = Ablk(lb.c, s);
+          const SiteBlock* ap = Ablk(lb.r, sp);
+          if (!as || !ap) continue;
+          auto uk = std::make_tuple(lb.w, s, lb.c);
+          if (!u_off.count(uk)) { u_off[uk] = u_total; u_total += (int64_t)lb.rows * as->cols; }
+          SKey sk{lb.w, sp, s, lb.c};
+          if (!s_off.count(sk)) { s_off[sk] = s_total; s_total += (int64_t)ap->cols * as->cols; }
+          dest[std::make_tuple(e.wout, as->r, ap->r)].push_back({sk, c});
+        }
+    }
+  }
+  Environment out;
+  out.nsec = (int)bn.q.size();
+  // output blocks in (w', a) order
+  for (const auto& kv : dest) {
+    EnvBlock b;
+    b.w = std::get<0>(kv.first);
+    b.c = std::get<1>(kv.first);
+    b.r = std::get<2>(kv.first);
+    if (bn.q[b.r] != bn.q[b.c] + mpo.dq[j + 1][b.w]) throw Error{LCC_ERR_QN, "internal: environment charge mismatch"};
+    b.rows = bn.dim[b.r];
+    b.cols = bn.dim[b.c];
+    b.off = out.size;
+    out.size += (int64_t)b.rows * b.cols;
+    out.lookup[(int64_t)b.w * out.nsec + b.c] = (int)out.blocks.size();
+    out.blocks.push_back(b);
+  }
+  out.data.alloc(sizeof(double) * std::max<int64_t>(out.size, 1));
+  if (out.blocks.empty()) return out;
+  DevBuf U, S;
+  U.alloc(sizeof(double) * std::max<int64_t>(u_total, 1));
+  S.alloc(sizeof(double) * std::max<int64_t>(s_total, 1));
+  // step 1: U(w, s, c) = L^w[r<-c] A^s[c -> a]
+  GemmBuilder g1;
+  for (const auto& kv : u_off) {
+    const int w = std::get<0>(kv.first), s = std::get<1>(kv.first), c = std::get<2>(kv.first);
+    const EnvBlock& lb = L.blocks[L.find(w, c)];
+    const SiteBlock* as = Ablk(c, s);
+    g1.group(BASE_T, kv.second, as->cols, lb.rows, as->cols, false);
+    g1.term(BASE_ENV, lb.off, lb.cols, BASE_MPS, as->off, as->cols, lb.cols, 1.0);
+  }
+  // step 2: S(w, s', s, c) = A^{s'}[r -> a']^T U(w, s, c)
+  GemmBuilder g2;
+  for (const auto& kv : s_off) {
+    const SKey& k = kv.first;
+    const EnvBlock& lb = L.blocks[L.find(k.w, k.c)];
+    const SiteBlock* as = Ablk(k.c, k.s);
+    const SiteBlock* ap = Ablk(lb.r, k.sp);
+    g2.group(BASE_Y, kv.second, as->cols, ap->cols, as->cols, false);
+    g2.term(BASE_MPS, ap->off, ap->cols, BASE_T, u_off[std::make_tuple(k.w, k.s, k.c)], as->cols, ap->rows, 1.0);
+  }
+  Bases<double> b{};
+  b.p[BASE_ENV] = L.data.as<double>();
+  b.p[BASE_MPS] = mps.data.as<double>();
+  b.p[BASE_T] = U.as<double>();
+  b.p[BASE_Y] = S.as<double>();
+  b.p[BASE_X] = out.data.as<double>();
+  {
+    auto l1 = finalize(g1, false, false, st);
+    run_gemm64(l1, b, st);
+    auto l2 = finalize(g2, true, false, st);
+    run_gemm64(l2, b, st);
+    check_hip(hipStreamSynchronize(st), "left step gemm");
+  }
+  // step 3: mix
+  MixBuilder mb;
+  for (const EnvBlock& ob : out.blocks) {
+    mb.group(BASE_X, ob.off, ob.rows * ob.cols, BASE_Y);
+    for (const auto& t : dest[std::make_tuple(ob.w, ob.c, ob.r)]) mb.term(s_off[t.first], t.second);
+  }
+  run_mix(mb, b, st);
+  return out;
+}
+
+// R_j^{w}[b', b] = sum_{w',s',s} W_j^{w,w'}[s',s] (B^{s'} R_{j+1}^{w'} B^{s T})[b', b]
+Environment right_step(const Environment& R, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st) {
+  const Bond& bj = mps.bonds[j];
+  std::map<std::pair<int, int>, int> B;  // (right sector, s) -> block
+  for (size_t i = 0; i < mps.sites[j].size(); ++i) B[{mps.sites[j][i].r, mps.sites[j][i].s}] = (int)i;
+  auto Bblk = [&](int r, int s) -> const SiteBlock* {
+    auto it = B.find({r, s});
+    return it == B.end() ? nullptr : &mps.sites[j][it->second];
+  };
+  struct SKey { int w, sp, s, c; bool operator<(const SKey& o) const { return std::tie(w, sp, s, c) < std::tie(o.w, o.sp, o.s, o.c); } };
+  std::map<SKey, int64_t> s_off;
+  std::map<std::tuple<int, int, int>, int64_t> u_off;  // (w', s, c)
+  std::map<std::tuple<int, int, int>, std::vector<std::pair<SKey, double>>> dest;  // (w, b, b') -> terms
+  std::vector<std::vector<int>> R_by_w(mpo.dq[j + 1].size());
+  for (size_t i = 0; i < R.blocks.size(); ++i) R_by_w[R.blocks[i].w].push_back((int)i);
+  int64_t u_total = 0, s_total = 0;
+  for (const MpoEntry& e : mpo.W[j]) {
+    for (int bi : R_by_w[e.wout]) {
+      const EnvBlock& rb = R.blocks[bi];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s = 0; s < 4; ++s) {
+          const double c = wcoef(e, sp, s);
+          if (c == 0.0) continue;
+          const SiteBlock* bs = Bblk(rb.c, s);
+          const SiteBlock* bp = Bblk(rb.r, sp);
+          if (!bs || !bp) continue;
+          auto uk = std::make_tuple(rb.w, s, rb.c);
+          if (!u_off.count(uk)) { u_off[uk] = u_total; u_total += (int64_t)rb.rows * bs->rows; }
+          SKey sk{rb.w, sp, s, rb.c};
+          if (!s_off.count(sk)) { s_off[sk] = s_total; s_total += (int64_t)bp->rows * bs->rows; }
+          dest[std::make_tuple(e.win, bs->l, bp->l)].push_back({sk, c});
+        }
+    }
+  }
+  Environment out;
+  out.nsec = (int)bj.q.size();
+  for (const auto& kv : dest) {
+    EnvBlock b;
+    b.w = std::get<0>(kv.first);
+    b.c = std::get<1>(kv.first);
+    b.r = std::get<2>(kv.first);
+    if (bj.q[b.r] != bj.q[b.c] + mpo.dq[j][b.w]) throw Error{LCC_ERR_QN, "internal: environment charge mismatch"};
+    b.rows = bj.dim[b.r];
+    b.cols = bj.dim[b.c];
+    b.off = out.size;
+    out.size += (int64_t)b.rows * b.cols;
+    out.lookup[(int64_t)b.w * out.nsec + b.c] = (int)out.blocks.size();
+    out.blocks.push_back(b);
+  }
+  out.data.alloc(sizeof(double) * std::max<int64_t>(out.size, 1));
+  if (out.blocks.empty()) return out;
+  DevBuf U, S;
+  U.alloc(sizeof(double) * std::max<int64_t>(u_total, 1));
+  S.alloc(sizeof(double) * std::max<int64_t>(s_total, 1));
+  // step 1: U(w', s, c) = R^{w'}[r <- c] B^s[b -> c]^T     (rows M_r, cols M_b)
+  GemmBuilder g1;
+  for (const auto& kv : u_off) {
+    const int w = std::get<0>(kv.first), s = std::get<1>(kv.first), c = std::get<2>(kv.first);
+    const EnvBlock& rb = R.blocks[R.find(w, c)];
+    const SiteBlock* bs = Bblk(c, s);
+    g1.group(BASE_T, kv.second, bs->rows, rb.rows, bs->rows, false);
+    g1.term(BASE_ENV, rb.off, rb.cols, BASE_MPS, bs->off, bs->cols, rb.cols, 1.0);
+  }
+  // step 2: S(w', s', s, c) = B^{s'}[b' -> r] U(w', s, c)  (rows M_b', cols M_b)
+  GemmBuilder g2;
+  for (const auto& kv : s_off) {
+    const SKey& k = kv.first;
+    const EnvBlock& rb = R.blocks[R.find(k.w, k.c)];
+    const SiteBlock* bs = Bblk(k.c, k.s);
+    const SiteBlock* bp = Bblk(rb.r, k.sp);
+    g2.group(BASE_Y, kv.second, bs->rows, bp->rows, bs->rows, false);
+    g2.term(BASE_MPS, bp->off, bp->cols, BASE_T, u_off[std::make_tuple(k.w, k.s, k.c)], bs->rows, bp->cols, 1.0);
+  }
+  Bases<double> b{};
+  b.p[BASE_ENV] = R.data.as<double>();
+  b.p[BASE_MPS] = mps.data.as<double>();
+  b.p[BASE_T] = U.as<double>();
+  b.p[BASE_Y] = S.as<double>();
+  b.p[BASE_X] = out.data.as<double>();
+  {
+    auto l1 = finalize(g1, false, true, st);
+    run_gemm64(l1, b, st);
+    auto l2 = finalize(g2, false, false, st);
+    run_gemm64(l2, b, st);
+    check_hip(hipStreamSynchronize(st), "right step gemm");
+  }
+  MixBuilder mb;
+  for (const EnvBlock& ob : out.blocks) {
+    mb.group(BASE_X, ob.off, ob.rows * ob.cols, BASE_Y);
+    for (const auto& t : dest[std::make_tuple(ob.w, ob.c, ob.r)]) mb.term(s_off[t.first], t.second);
+  }
+  run_mix(mb, b, st);
+  return out;
+}
+
+Environment unit_env(hipStream_t st) {
+  Environment e;
+  e.nsec = 1;
+  e.blocks.push_back(EnvBlock{0, 0, 0, 0, 1, 1});
+  e.lookup[0] = 0;
+  e.size = 1;
+  std::vector<double> one{1.0};
+  upload(e.data, one, st);
+  return e;
+}
+
+// The identity channel of a canonical environment must be the identity matrix.
+void check_identity(const Environment& E, int w_id, const Bond& bond, hipStream_t st, const char* which) {
+  for (size_t q = 0; q < bond.q.size(); ++q) {
+    const int bi = E.find(w_id, (int)q);
+    if (bi < 0) throw Error{LCC_ERR_ARG, std::string(which) + " environment lacks its identity channel"};
+    const EnvBlock& b = E.blocks[bi];
+    std::vector<double> h((size_t)b.rows * b.cols);
+    check_hip(hipMemcpyAsync(h.data(), E.data.as<double>() + b.off, h.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+              "identity check copy");
+    check_hip(hipStreamSynchronize(st), "identity check sync");
+    double worst = 0;
+    for (int r = 0; r < b.rows; ++r)
+      for (int c = 0; c < b.cols; ++c) worst = std::max(worst, std::fabs(h[(size_t)r * b.cols + c] - (r == c ? 1.0 : 0.0)));
+    if (!(worst <= 1e-10))
+      throw Error{LCC_ERR_ARG, std::string("MPS is not ") + which + "-canonical (deviation " + std::to_string(worst) + ")"};
+  }
+}
+
+int channel_of_kind(const Mpo& mpo, int bond, int kind) {
+  for (size_t i = 0; i < mpo.kind[bond].size(); ++i)
+    if (mpo.kind[bond][i] == kind) return (int)i;
+  return -1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// build_env: environments, enlarged operators, vector layout, and the apply plan
+// ---------------------------------------------------------------------------------------
+Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int site) {
+  hipStream_t st = ctx->stream;
+  const Mpo& mpo = ham.mpo;
+  const int K = mpo.K;
+  if (md.n_sites != K) throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
+  if (site < 0 || site + 1 >= K) throw Error{LCC_ERR_ARG, "two-site block must satisfy 0 <= site < K-1"};
+  DeviceMps mps;
+  load_mps(md, ham.desc.N, ham.desc.two_sz, st, mps);
+
+  // left environment at MPS bond `site`, right environment at MPS bond `site + 2`
+  Environment L = unit_env(st);
+  for (int j = 0; j < site; ++j) L = left_step(L, mps, j, mpo, st);
+  Environment R = unit_env(st);
+  for (int j = K - 1; j >= site + 2; --j) R = right_step(R, mps, j, mpo, st);
+  // the identity channel of each environment certifies the canonical form of its sites
+  const int w_left_id = channel_of_kind(mpo, site, 0), w_right_id = channel_of_kind(mpo, site + 2, 1);
+  if (site > 0 && w_left_id >= 0) check_identity(L, w_left_id, mps.bonds[site], st, "left");
+  if (site + 2 < K && w_right_id >= 0) check_identity(R, w_right_id, mps.bonds[site + 2], st, "right");
+
+  std::unique_ptr<Env> env(new Env());
+  env->ctx = ctx;
+  env->site = site;
+  env->K = K;
+  env->bl = mps.bonds[site];
+  env->br = mps.bonds[site + 2];
+  const Bond& bl = env->bl;
+  const Bond& br = env->br;
+  const int mid = site + 1;  // MPO bond between the two sites
+  env->D_mid = (int)mpo.dq[mid].size();
+
+  // ---- middle-bond sectors and the vector layout
+  std::map<QN, MiddleSector> secs;
+  for (size_t a = 0; a < bl.q.size(); ++a)
+    for (int s1 = 0; s1 < 4; ++s1) secs[bl.q[a] + local_qn(s1)].rows.push_back({(int)a, s1});
+  for (int s2 = 0; s2 < 4; ++s2)
+    for (size_t b = 0; b < br.q.size(); ++b) {
+      auto it = secs.find(br.q[b] - local_qn(s2));
+      if (it != secs.end()) it->second.cols.push_back({s2, (int)b});
+    }
+  std::map<QN, int> sec_index;
+  for (auto& kv : secs) {
+    MiddleSector& m = kv.second;
+    if (m.rows.empty() || m.cols.empty()) continue;
+    m.q = kv.first;
+    for (auto& r : m.rows) { m.row_off.push_back(m.nrows); m.nrows += bl.dim[r.first]; }
+    for (auto& c : m.cols) { m.col_off.push_back(m.ncols); m.ncols += br.dim[c.second]; }
+    m.off = env->n_elements;
+    env->n_elements += (int64_t)m.nrows * m.ncols;
+    sec_index[m.q] = (int)env->sectors.size();
+    env->sectors.push_back(m);
+  }
+  for (const MiddleSector& m : env->sectors)
+    for (size_t i = 0; i < m.rows.size(); ++i)
+      for (size_t jx = 0; jx < m.cols.size(); ++jx) {
+        lcc_block_entry e;
+        e.left = m.rows[i].first;
+        e.s1 = m.rows[i].second;
+        e.s2 = m.cols[jx].first;
+        e.right = m.cols[jx].second;
+        e.offset = m.off + (int64_t)m.row_off[i] * m.ncols + m.col_off[jx];
+        e.ld = m.ncols;
+        e.rows = bl.dim[e.left];
+        e.cols = br.dim[e.right];
+        env->layout.push_back(e);
+      }
+  // row / column lookup: (a, s1) -> (sector, row index); (s2, b) -> (sector, col index)
+  std::map<std::pair<int, int>, std::pair<int, int>> row_at, col_at;
+  for (size_t m = 0; m < env->sectors.size(); ++m) {
+    for (size_t i = 0; i < env->sectors[m].rows.size(); ++i) row_at[env->sectors[m].rows[i]] = {(int)m, (int)i};
+    for (size_t i = 0; i < env->sectors[m].cols.size(); ++i) col_at[env->sectors[m].cols[i]] = {(int)m, (int)i};
+  }
+
+  // ---- environment data on the device: [L | R]
+  env->env_elems = L.size + R.size;
+  env->env64.alloc(sizeof(double) * std::max<int64_t>(env->env_elems, 1));
+  check_hip(hipMemcpyAsync(env->env64.p, L.data.p, sizeof(double) * L.size, hipMemcpyDeviceToDevice, st), "env copy");
+  check_hip(hipMemcpyAsync(env->env64.as<double>() + L.size, R.data.p, sizeof(double) * R.size, hipMemcpyDeviceToDevice, st),
+            "env copy");
+  const int64_t r_base = L.size;
+
+  // ---- enlarged operators.  A reference is (base, offset, coefficient).
+  struct Ref { int8_t base; int64_t off; double alpha; };
+  // Lt: key (w1, row (a',s1'), src row (a,s1)) -> contributions (L block, coef)
+  std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> lt_terms;
+  std::vector<std::vector<int>> L_by_w(mpo.dq[site].size());
+  for (size_t i = 0; i < L.blocks.size(); ++i) L_by_w[L.blocks[i].w].push_back((int)i);
+  for (const MpoEntry& e : mpo.W[site])
+    for (int bi : L_by_w[e.win]) {
+      const EnvBlock& lb = L.blocks[bi];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s = 0; s < 4; ++s) {
+          const double c = e.m[sp * 4 + s];
+          if (c == 0.0) continue;
+          if (!row_at.count({lb.r, sp}) || !row_at.count({lb.c, s})) continue;
+          lt_terms[std::make_tuple(e.wout, lb.r, sp, lb.c, s)].push_back({bi, c});
+        }
+    }
+  std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> rt_terms;
+  std::vector<std::vector<int>> R_by_w(mpo.dq[site + 2].size());
+  for (size_t i = 0; i < R.blocks.size(); ++i) R_by_w[R.blocks[i].w].push_back((int)i);
+  for (const MpoEntry& e : mpo.W[site + 1])
+    for (int bi : R_by_w[e.wout]) {
+      const EnvBlock& rb = R.blocks[bi];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s = 0; s < 4; ++s) {
+          const double c = e.m[sp * 4 + s];
+          if (c == 0.0) continue;
+          if (!col_at.count({sp, rb.r}) || !col_at.count({s, rb.c})) continue;
+          rt_terms[std::make_tuple(e.win, sp, rb.r, s, rb.c)].push_back({bi, c});
+        }
+    }
+  // references, merging multi-term entries
+  MixBuilder merge;
+  int64_t merged = 0;
+  // Lt index: (w1, a', s1') -> list of (a, s1, ref)
+  std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, Ref>>> lt;
+  for (const auto& kv : lt_terms) {
+    int w1, ap, sp, a, s;
+    std::tie(w1, ap, sp, a, s) = kv.first;
+    Ref ref;
+    if (kv.second.size() == 1) {
+      ref = Ref{BASE_ENV, L.blocks[kv.second[0].first].off, kv.second[0].second};
+    } else {
+      const EnvBlock& b0 = L.blocks[kv.second[0].first];
+      merge.group(BASE_MERGED, merged, b0.rows * b0.cols, BASE_ENV);
+      for (const auto& c : kv.second) merge.term(L.blocks[c.first].off, c.second);
+      ref = Ref{BASE_MERGED, merged, 1.0};
+      merged += (int64_t)b0.rows * b0.cols;
+    }
+    lt[std::make_tuple(w1, ap, sp)].push_back(std::make_tuple(a, s, ref));
+  }
+  std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, Ref>>> rt;  // (w1, s2', b') -> (s2, b, ref)
+  for (const auto& kv : rt_terms) {
+    int w1, sp, bp, s, b;
+    std::tie(w1, sp, bp, s, b) = kv.first;
+    Ref ref;
+    if (kv.second.size() == 1) {
+      ref = Ref{BASE_ENV, r_base + R.blocks[kv.second[0].first].off, kv.second[0].second};
+    } else {
+      const EnvBlock& b0 = R.blocks[kv.second[0].first];
+      merge.group(BASE_MERGED, merged, b0.rows * b0.cols, BASE_ENV);
+      for (const auto& c : kv.second) merge.term(r_base + R.blocks[c.first].off, c.second);
+      ref = Ref{BASE_MERGED, merged, 1.0};
+      merged += (int64_t)b0.rows * b0.cols;
+    }
+    rt[std::make_tuple(w1, sp, bp)].push_back(std::make_tuple(s, b, ref));
+  }
+  env->merged_elems = merged;
+  env->merged64.alloc(sizeof(double) * std::max<int64_t>(merged, 1));
+  {
+    Bases<double> b{};
+    b.p[BASE_ENV] = env->env64.as<double>();
+    b.p[BASE_MERGED] = env->merged64.as<double>();
+    run_mix(merge, b, st);
+  }
+
+  // ---- active (w1, source sector) pairs and the intermediate layout
+  const int D = env->D_mid;
+  const int nsec = (int)env->sectors.size();
+  std::vector<char> lact((size_t)D * nsec, 0), ract((size_t)D * nsec, 0);
+  for (const auto& kv : lt) {
+    const int w1 = std::get<0>(kv.first);
+    for (const auto& src : kv.second) lact[(size_t)w1 * nsec + row_at[{std::get<0>(src), std::get<1>(src)}].first] = 1;
+  }
+  for (const auto& kv : rt) {
+    const int w1 = std::get<0>(kv.first);
+    for (const auto& src : kv.second) ract[(size_t)w1 * nsec + col_at[{std::get<0>(src), std::get<1>(src)}].first] = 1;
+  }
+  std::vector<int64_t> t_off((size_t)D * nsec, -1);
+  int64_t t_total = 0;
+  for (int w1 = 0; w1 < D; ++w1)
+    for (int m = 0; m < nsec; ++m) {
+      if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
+      auto it = sec_index.find(env->sectors[m].q + mpo.dq[mid][w1]);
+      if (it == sec_index.end()) continue;
+      t_off[(size_t)w1 * nsec + m] = t_total;
+      t_total += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
+    }
+  env->t_elems = t_total;
+  env->tbuf.alloc(sizeof(double) * std::max<int64_t>(t_total, 1));
+
+  // ---- phase 1: T_{w1,m}[(a',s1') rows] = sum Lt^{w1}[(a',s1'),(a,s1)] X_m[(a,s1) rows]
+  GemmBuilder p1;
+  for (int w1 = 0; w1 < D; ++w1)
+    for (int m = 0; m < nsec; ++m) {
+      const int64_t to = t_off[(size_t)w1 * nsec + m];
+      if (to < 0) continue;
+      const MiddleSector& S = env->sectors[m];
+      const MiddleSector& Sp = env->sectors[sec_index[S.q + mpo.dq[mid][w1]]];
+      for (size_t i = 0; i < Sp.rows.size(); ++i) {
+        const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
+        p1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
+        auto it = lt.find(std::make_tuple(w1, ap, sp));
+        if (it == lt.end()) continue;
+        for (const auto& src : it->second) {
+          const auto ra = row_at[{std::get<0>(src), std::get<1>(src)}];
+          if (ra.first != m) continue;
+          const Ref& ref = std::get<2>(src);
+          const int ka = bl.dim[std::get<0>(src)];
+          p1.term(ref.base, ref.off, ka, BASE_X, S.off + (int64_t)S.row_off[ra.second] * S.ncols, S.ncols, ka, ref.alpha);
+        }
+      }
+    }
+  // ---- phase 2: Y_{m'}[:, (s2',b')] = sum_{w1,(s2,b)} T_{w1,m}[:, (s2,b)] Rt^{w1}[(s2',b'),(s2,b)]^T
+  GemmBuilder p2;
+  for (int mp = 0; mp < nsec; ++mp) {
+    const MiddleSector& Sp = env->sectors[mp];
+    for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
+      const int s2p = Sp.cols[jx].first, bp = Sp.cols[jx].second;
+      p2.group(BASE_Y, Sp.off + Sp.col_off[jx], Sp.ncols, Sp.nrows, br.dim[bp], false);
+      for (int w1 = 0; w1 < D; ++w1) {
+        auto si = sec_index.find(Sp.q - mpo.dq[mid][w1]);
+        if (si == sec_index.end()) continue;
+        const int m = si->second;
+        const int64_t to = t_off[(size_t)w1 * nsec + m];
+        if (to < 0) continue;
+        auto it = rt.find(std::make_tuple(w1, s2p, bp));
+        if (it == rt.end()) continue;
+        const MiddleSector& S = env->sectors[m];
+        for (const auto& src : it->second) {
+          const auto ca = col_at[{std::get<0>(src), std::get<1>(src)}];
+          if (ca.first != m) continue;
+          const Ref& ref = std::get<2>(src);
+          const int kb = br.dim[std::get<1>(src)];
+          p2.term(BASE_T, to + S.col_off[ca.second], S.ncols, ref.base, ref.off, kb, kb, ref.alpha);
+        }
+      }
+    }
+  }
+  env->plan.flops1 = p1.flops;
+  env->plan.flops2 = p2.flops;
+  env->plan.phase1 = finalize(p1, false, false, st);
+  env->plan.phase2 = finalize(p2, false, true, st);
+  // CG workspace (FP64)
+  for (auto& w : env->w64) w.alloc(sizeof(double) * std::max<int64_t>(env->n_elements, 1));
+  env->flag.alloc(sizeof(int) * 4);
+  check_hip(hipStreamSynchronize(st), "build_env");
+  return env.release();
+}
+
+void ensure_fp32(Env& env) {
+  if (env.have32) return;
+  hipStream_t st = env.ctx->stream;
+  env.env32.alloc(sizeof(float) * std::max<int64_t>(env.env_elems, 1));
+  env.merged32.alloc(sizeof(float) * std::max<int64_t>(env.merged_elems, 1));
+  check_hip(launch_convert_f64_f32(env.env_elems, env.env64.as<double>(), env.env32.as<float>(), st), "convert env");
+  if (env.merged_elems)
+    check_hip(launch_convert_f64_f32(env.merged_elems, env.merged64.as<double>(), env.merged32.as<float>(), st), "convert merged");
+  for (auto& w : env.w32) w.alloc(sizeof(float) * std::max<int64_t>(env.n_elements, 1));
+  check_hip(hipStreamSynchronize(st), "ensure_fp32");
+  env.have32 = true;
+}
+
+void apply_heff(Env& env, int precision, const void* x, void* y) { apply_heff_phase(env, precision, x, y, 0); }
+
+void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase) {
+  hipStream_t st = env.ctx->stream;
+  if (precision == LCC_FP64) {
+    Bases<double> b{};
+    b.p[BASE_ENV] = env.env64.as<double>();
+    b.p[BASE_MERGED] = env.merged64.as<double>();
+    b.p[BASE_X] = const_cast<double*>(static_cast<const double*>(x));
+    b.p[BASE_T] = env.tbuf.as<double>();
+    b.p[BASE_Y] = static_cast<double*>(y);
+    if (phase != 2) run_gemm64(env.plan.phase1, b, st);
+    if (phase != 1) run_gemm64(env.plan.phase2, b, st);
+    return;
+  }
+  ensure_fp32(env);
+  Bases<float> b{};
+  b.p[BASE_ENV] = env.env32.as<float>();
+  b.p[BASE_MERGED] = env.merged32.as<float>();
+  b.p[BASE_X] = const_cast<float*>(static_cast<const float*>(x));
+  b.p[BASE_T] = env.tbuf.as<float>();
+  b.p[BASE_Y] = static_cast<float*>(y);
+  for (int ph = 1; ph <= 2; ++ph) {
+    if (phase != 0 && phase != ph) continue;
+    for (const GemmLaunch& L : ph == 1 ? env.plan.phase1 : env.plan.phase2) {
+      hipError_t e = precision == LCC_FP32
+                         ? launch_gemm_f32(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
+                                           L.n_tiles, L.ta, L.tb, L.shape, b, st)
+                         : launch_gemm_bf16x3(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
+                                              L.n_tiles, L.ta, L.tb, L.shape, b, st);
+      check_hip(e, "gemm low-precision launch");
+    }
+  }
+}
+
+}  // namespace lcc

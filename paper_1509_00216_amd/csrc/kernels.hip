@@ -1,0 +1,508 @@
+// gfx950 kernels: grouped block GEMM on MFMA (FP64, FP32, BF16x3), block mixing, and the
+// FP64-accumulating vector operations of conjugate gradients.
+//
+// The grouped GEMM computes, for every output block ("group") g,
+//     C_g  (=|+=)  sum_{t in terms(g)} alpha_t * op(A_t) * op(B_t)
+// with uneven m, n, k.  A workgroup owns one BM x BN output tile of one group and walks the
+// group's whole term list, so every output element is produced by exactly one workgroup in
+// a fixed order: results are deterministic and no atomics are used.  The per-term alpha is
+// applied while A is staged into LDS: this is where the MPO coefficients of the two sites
+// (the W-mixing of the effective Hamiltonian) enter without an extra pass over memory.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace lcc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kThreads = 256;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber so that consecutive
+// logical tiles (which share operands) run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int xcd = bid & 7, local = bid >> 3;
+  const int start = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+  return start + local;
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 / FP32 MFMA 16x16x4 grouped GEMM.
+//   MODE 0: double operands, v_mfma_f64_16x16x4_f64: lane l holds A[l%16][l/16], B[l/16][l%16],
+//           accumulator element r at row l/16 + 4r, column l%16.
+//   MODE 1: float operands, v_mfma_f32_16x16x4_f32: same inputs, accumulator element r at
+//           row 4(l/16) + r, column l%16.
+// Waves are arranged WM x WN; each wave owns (BM/WM) x (BN/WN) = (16 TM) x (16 TN).
+// ------------------------------------------------------------------------------------------
+template <int MODE>
+struct Mfma;
+template <>
+struct Mfma<0> {
+  typedef double T;
+  typedef d4 Acc;
+  static __device__ __forceinline__ Acc step(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<1> {
+  typedef float T;
+  typedef f4 Acc;
+  static __device__ __forceinline__ Acc step(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(kThreads)
+gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
+                 const GemmTile* __restrict__ tiles, int n_tiles,
+                 Bases<typename Mfma<MODE>::T> bases) {
+  typedef typename Mfma<MODE>::T T;
+  typedef typename Mfma<MODE>::Acc Acc;
+  constexpr int BK = 16;
+  constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  static_assert(WM * WN == kThreads / 64, "four waves");
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+
+  const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
+  const GemmGroup g = groups[tile.group];
+  const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  for (int t = g.term_begin; t < g.term_end; ++t) {
+    const GemmTerm term = terms[t];
+    const T* __restrict__ A = bases.p[term.a_base] + term.a_off;
+    const T* __restrict__ B = bases.p[term.b_base] + term.b_off;
+    const T alpha = (T)term.alpha;
+    const int K = term.k;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      __syncthreads();
+      // stage alpha * op(A)[row0 .. row0+BM, k0 .. k0+BK) as As[k][m]
+      if (!TA) {
+#pragma unroll
+        for (int e = tid; e < BM * BK; e += kThreads) {
+          const int kk = e % BK, mm = e / BK;
+          const int gr = row0 + mm, gk = k0 + kk;
+          As[kk][mm] = (gr < g.m && gk < K) ? alpha * A[(int64_t)gr * term.lda + gk] : (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int e = tid; e < BM * BK; e += kThreads) {
+          const int mm = e % BM, kk = e / BM;
+          const int gr = row0 + mm, gk = k0 + kk;
+          As[kk][mm] = (gr < g.m && gk < K) ? alpha * A[(int64_t)gk * term.lda + gr] : (T)0;
+        }
+      }
+      // stage op(B)[k0 .. k0+BK, col0 .. col0+BN) as Bs[k][n]
+      if (!TB) {
+#pragma unroll
+        for (int e = tid; e < BN * BK; e += kThreads) {
+          const int nn = e % BN, kk = e / BN;
+          const int gc = col0 + nn, gk = k0 + kk;
+          Bs[kk][nn] = (gc < g.n && gk < K) ? B[(int64_t)gk * term.ldb + gc] : (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int e = tid; e < BN * BK; e += kThreads) {
+          const int kk = e % BK, nn = e / BK;
+          const int gc = col0 + nn, gk = k0 + kk;
+          Bs[kk][nn] = (gc < g.n && gk < K) ? B[(int64_t)gc * term.ldb + gk] : (T)0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        T a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[kk + (lane >> 4)][wm * (BM / WM) + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * (BN / WN) + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<MODE>::step(a[i], b[j], acc[i][j]);
+      }
+    }
+  }
+
+  T* __restrict__ C = bases.p[g.c_base] + g.c_off;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * (BM / WM) + i * 16 + Mfma<MODE>::row(lane, r);
+        const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
+        if (gr < g.m && gc < g.n) {
+          T* p = C + (int64_t)gr * g.ldc + gc;
+          *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16x3 split-product GEMM on v_mfma_f32_16x16x32_bf16.  FP32 operands are split while
+// staged: hi = bf16(x), lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi with FP32
+// accumulation (the lo*lo term is below the representation error of the split).
+// Lane l holds A[l%16][8(l/16) + i], B[8(l/16) + i][l%16] (i = 0..7); accumulator element r
+// at row 4(l/16) + r, column l%16.  LDS holds A as [m][k] and B as [n][k] so that each
+// lane's eight k values are contiguous.
+// ------------------------------------------------------------------------------------------
+template <bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(kThreads)
+gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
+                   const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases) {
+  constexpr int BK = 32;
+  constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][KP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+
+  const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
+  const GemmGroup g = groups[tile.group];
+  const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = g.term_begin; t < g.term_end; ++t) {
+    const GemmTerm term = terms[t];
+    const float* __restrict__ A = bases.p[term.a_base] + term.a_off;
+    const float* __restrict__ B = bases.p[term.b_base] + term.b_off;
+    const float alpha = (float)term.alpha;
+    const int K = term.k;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+      __syncthreads();
+#pragma unroll
+      for (int e = tid; e < BM * BK; e += kThreads) {
+        int kk, mm;
+        if (!TA) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+        const int gr = row0 + mm, gk = k0 + kk;
+        float v = 0.f;
+        if (gr < g.m && gk < K) v = alpha * (TA ? A[(int64_t)gk * term.lda + gr] : A[(int64_t)gr * term.lda + gk]);
+        const __bf16 h = (__bf16)v;
+        Ah[mm][kk] = h;
+        Al[mm][kk] = (__bf16)(v - (float)h);
+      }
+#pragma unroll
+      for (int e = tid; e < BN * BK; e += kThreads) {
+        int kk, nn;
+        if (!TB) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+        const int gc = col0 + nn, gk = k0 + kk;
+        float v = 0.f;
+        if (gc < g.n && gk < K) v = TB ? B[(int64_t)gc * term.ldb + gk] : B[(int64_t)gk * term.ldb + gc];
+        const __bf16 h = (__bf16)v;
+        Bh[nn][kk] = h;
+        Bl[nn][kk] = (__bf16)(v - (float)h);
+      }
+      __syncthreads();
+      bf8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = wm * (BM / WM) + i * 16 + (lane & 15);
+        ah[i] = *reinterpret_cast<const bf8*>(&Ah[r][8 * (lane >> 4)]);
+        al[i] = *reinterpret_cast<const bf8*>(&Al[r][8 * (lane >> 4)]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int c = wn * (BN / WN) + j * 16 + (lane & 15);
+        bh[j] = *reinterpret_cast<const bf8*>(&Bh[c][8 * (lane >> 4)]);
+        bl[j] = *reinterpret_cast<const bf8*>(&Bl[c][8 * (lane >> 4)]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+
+  float* __restrict__ C = bases.p[g.c_base] + g.c_off;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
+        if (gr < g.m && gc < g.n) {
+          float* p = C + (int64_t)gr * g.ldc + gc;
+          *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers.  Tile shape 0: 64x64 (2x2 waves of 32x32); shape 1: 32x32... realised as 16x64
+// (1x4 waves of 16x16), which suits the short-row blocks of small sectors.
+// ------------------------------------------------------------------------------------------
+template <int MODE, int BM, int BN, int WM, int WN>
+static hipError_t launch_mfma_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
+                                    int n_tiles, bool ta, bool tb,
+                                    const Bases<typename Mfma<MODE>::T>& b, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  dim3 grid(n_tiles), block(kThreads);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  else
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN>
+static hipError_t launch_bf_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
+                                  int n_tiles, bool ta, bool tb, const Bases<float>& b, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  dim3 grid(n_tiles), block(kThreads);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  else
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
+                           int n_tiles, bool ta, bool tb, int shape, const Bases<double>& b,
+                           hipStream_t stream) {
+  if (shape == TILE_64x64) return launch_mfma_shape<0, 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+  return launch_mfma_shape<0, 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+}
+hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
+                           int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
+                           hipStream_t stream) {
+  if (shape == TILE_64x64) return launch_mfma_shape<1, 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+  return launch_mfma_shape<1, 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+}
+hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
+                              int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
+                              hipStream_t stream) {
+  if (shape == TILE_64x64) return launch_bf_shape<64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+  return launch_bf_shape<16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+}
+
+// ------------------------------------------------------------------------------------------
+// Block mixing: dst_g = sum_t alpha_t src_t over contiguous blocks of equal size.
+// ------------------------------------------------------------------------------------------
+constexpr int kMixChunk = 1024;
+
+__global__ void __launch_bounds__(kThreads)
+mix_kernel(const MixTerm* __restrict__ terms, const MixGroup* __restrict__ groups,
+           const MixTile* __restrict__ tiles, Bases<double> bases) {
+  const MixTile tile = tiles[blockIdx.x];
+  const MixGroup g = groups[tile.group];
+  const int base = tile.chunk * kMixChunk;
+  double acc[kMixChunk / kThreads];
+#pragma unroll
+  for (int i = 0; i < kMixChunk / kThreads; ++i) acc[i] = 0.0;
+  for (int t = g.term_begin; t < g.term_end; ++t) {
+    const MixTerm term = terms[t];
+    const double* __restrict__ src = bases.p[g.src_base] + term.src_off;
+#pragma unroll
+    for (int i = 0; i < kMixChunk / kThreads; ++i) {
+      const int e = base + i * kThreads + threadIdx.x;
+      if (e < g.count) acc[i] += term.alpha * src[e];
+    }
+  }
+  double* __restrict__ dst = bases.p[g.dst_base] + g.dst_off;
+#pragma unroll
+  for (int i = 0; i < kMixChunk / kThreads; ++i) {
+    const int e = base + i * kThreads + threadIdx.x;
+    if (e < g.count) dst[e] = acc[i];
+  }
+}
+
+hipError_t launch_mix_f64(const MixTerm* terms, const MixGroup* groups, const MixTile* tiles,
+                          int n_tiles, const Bases<double>& b, hipStream_t stream) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mix_kernel, dim3(n_tiles), dim3(kThreads), 0, stream, terms, groups, tiles, b);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Vector operations.  Dot products accumulate in FP64 with a fixed two-level tree
+// (kDotBlocks partial sums, then one block), so they are reproducible run to run.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kThreads / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kThreads / 64; ++i) r += red[i];
+  }
+  return r;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kThreads) dot_partial_kernel(const T* __restrict__ x, const T* __restrict__ y,
+                                                               int64_t n, double* __restrict__ partial) {
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    s += (double)x[i] * (double)y[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kThreads) dot_final_kernel(const double* __restrict__ partial, int n,
+                                                             double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_dot_f64(const double* x, const double* y, int64_t n, double* partial, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel<double>, dim3(kDotBlocks), dim3(kThreads), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kThreads), 0, s, partial, kDotBlocks, out);
+  return hipGetLastError();
+}
+hipError_t launch_dot_f32(const float* x, const float* y, int64_t n, double* partial, double* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel<float>, dim3(kDotBlocks), dim3(kThreads), 0, s, x, y, n, partial);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kThreads), 0, s, partial, kDotBlocks, out);
+  return hipGetLastError();
+}
+
+static inline dim3 grid_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+template <class T>
+__global__ void axpby_kernel(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+hipError_t launch_axpby_f64(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(axpby_kernel<double>, grid_for(n), dim3(kThreads), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+hipError_t launch_axpby_f32(int64_t n, double a, const float* x, double b, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(axpby_kernel<float>, grid_for(n), dim3(kThreads), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+
+template <class S, class D>
+__global__ void convert_kernel(int64_t n, const S* __restrict__ x, D* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (D)x[i];
+}
+hipError_t launch_convert_f64_f32(int64_t n, const double* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL((convert_kernel<double, float>), grid_for(n), dim3(kThreads), 0, s, n, x, y);
+  return hipGetLastError();
+}
+hipError_t launch_convert_f32_f64(int64_t n, const float* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL((convert_kernel<float, double>), grid_for(n), dim3(kThreads), 0, s, n, x, y);
+  return hipGetLastError();
+}
+
+__global__ void axpy_f32_into_f64_kernel(int64_t n, double a, const float* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * (double)x[i];
+}
+hipError_t launch_axpy_f32_into_f64(int64_t n, double a, const float* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_f32_into_f64_kernel, grid_for(n), dim3(kThreads), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[i]);
+  if (bad) flag[0] = 1;  // benign race: every writer stores the same value
+}
+hipError_t launch_nonfinite_f64(const double* x, int64_t n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel, grid_for(n), dim3(kThreads), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void fill_kernel(T* __restrict__ x, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+hipError_t launch_fill_f64(double* x, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel<double>, grid_for(n), dim3(kThreads), 0, s, x, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel<float>, grid_for(n), dim3(kThreads), 0, s, x, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace lcc
+
+namespace lcc {
+// Counter-based start vectors: splitmix64 of (seed, index) mapped to [-0.5, 0.5).
+__global__ void random_fill_kernel(double* __restrict__ x, int64_t n, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    x[i] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  }
+}
+hipError_t launch_random_fill_f64(double* x, int64_t n, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(random_fill_kernel, grid_for(n), dim3(kThreads), 0, s, x, n, seed);
+  return hipGetLastError();
+}
+}  // namespace lcc

@@ -1,0 +1,147 @@
+// Lowest eigenvalue of H_eff by Lanczos (the DMRG energy functional of the Implementation
+// section) and event timing of the two apply phases.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "state.h"
+
+namespace lcc {
+namespace {
+
+double dot(Env& env, const double* a, const double* b) {
+  Context* c = env.ctx;
+  hipStream_t st = c->stream;
+  check_hip(launch_dot_f64(a, b, env.n_elements, c->dot_partial.as<double>(), c->dot_out.as<double>(), st), "dot");
+  check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+  check_hip(hipStreamSynchronize(st), "dot sync");
+  return c->host_scalar[0];
+}
+
+// Eigen-decomposition of a small symmetric matrix by cyclic Jacobi rotations (host, k <= a
+// few hundred): returns eigenvalues and eigenvectors (columns of v, row-major k x k).
+void jacobi_eigen(std::vector<double> a, int k, std::vector<double>& w, std::vector<double>& v) {
+  v.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) v[(size_t)i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += a[(size_t)p * k + q] * a[(size_t)p * k + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[(size_t)p * k + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = a[(size_t)p * k + p], aqq = a[(size_t)q * k + q];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int r = 0; r < k; ++r) {
+          const double arp = a[(size_t)r * k + p], arq = a[(size_t)r * k + q];
+          a[(size_t)r * k + p] = c * arp - s * arq;
+          a[(size_t)r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = a[(size_t)p * k + r], aqr = a[(size_t)q * k + r];
+          a[(size_t)p * k + r] = c * apr - s * aqr;
+          a[(size_t)q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = v[(size_t)r * k + p], vrq = v[(size_t)r * k + q];
+          v[(size_t)r * k + p] = c * vrp - s * vrq;
+          v[(size_t)r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  w.resize(k);
+  for (int i = 0; i < k; ++i) w[i] = a[(size_t)i * k + i];
+}
+
+}  // namespace
+
+void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual) {
+  hipStream_t st = env.ctx->stream;
+  const int64_t n = env.n_elements;
+  if (steps < 1) throw Error{LCC_ERR_ARG, "steps must be >= 1"};
+  steps = (int)std::min<int64_t>(steps, n);
+  DevBuf Qbuf, wbuf;
+  Qbuf.alloc(sizeof(double) * (size_t)n * (steps + 1));
+  wbuf.alloc(sizeof(double) * (size_t)n);
+  double* Q = Qbuf.as<double>();
+  double* w = wbuf.as<double>();
+  check_hip(launch_random_fill_f64(Q, n, seed, st), "start vector");
+  double nrm = std::sqrt(dot(env, Q, Q));
+  check_hip(launch_axpby_f64(n, 0.0, Q, 1.0 / nrm, Q, st), "normalise");
+  std::vector<double> alpha, beta;
+  int k = 0;
+  for (; k < steps; ++k) {
+    double* qk = Q + (size_t)k * n;
+    apply_heff(env, LCC_FP64, qk, w);
+    const double a = dot(env, qk, w);
+    alpha.push_back(a);
+    // full re-orthogonalisation (twice) against every Krylov vector so far
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i <= k; ++i) {
+        const double* qi = Q + (size_t)i * n;
+        const double c = dot(env, qi, w);
+        check_hip(launch_axpby_f64(n, -c, qi, 1.0, w, st), "reorth");
+      }
+    const double b = std::sqrt(dot(env, w, w));
+    if (k + 1 == steps || b < 1e-12 * std::max(1.0, std::fabs(a))) {
+      ++k;
+      break;
+    }
+    beta.push_back(b);
+    check_hip(launch_axpby_f64(n, 1.0 / b, w, 0.0, Q + (size_t)(k + 1) * n, st), "next vector");
+  }
+  const int m = k;
+  std::vector<double> T((size_t)m * m, 0.0), ev, vec;
+  for (int i = 0; i < m; ++i) {
+    T[(size_t)i * m + i] = alpha[i];
+    if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
+  }
+  jacobi_eigen(T, m, ev, vec);
+  int lo = 0;
+  for (int i = 1; i < m; ++i)
+    if (ev[i] < ev[lo]) lo = i;
+  // Ritz vector u = Q s and its residual
+  check_hip(launch_fill_f64(w, n, 0.0, st), "zero");
+  for (int i = 0; i < m; ++i) check_hip(launch_axpby_f64(n, vec[(size_t)i * m + lo], Q + (size_t)i * n, 1.0, w, st), "ritz");
+  double* u = w;
+  double* hu = Q;  // the Krylov basis is no longer needed
+  apply_heff(env, LCC_FP64, u, hu);
+  check_hip(launch_axpby_f64(n, -ev[lo], u, 1.0, hu, st), "residual");
+  const double un = std::sqrt(dot(env, u, u));
+  *theta = ev[lo];
+  *residual = std::sqrt(dot(env, hu, hu)) / un;
+}
+
+void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2) {
+  hipStream_t st = env.ctx->stream;
+  if (reps < 1) throw Error{LCC_ERR_ARG, "reps must be >= 1"};
+  hipEvent_t e0, e1, e2;
+  check_hip(hipEventCreate(&e0), "event");
+  check_hip(hipEventCreate(&e1), "event");
+  check_hip(hipEventCreate(&e2), "event");
+  double t1 = 0, t2 = 0;
+  for (int r = 0; r < reps; ++r) {
+    check_hip(hipEventRecord(e0, st), "record");
+    apply_heff_phase(env, precision, x, y, 1);
+    check_hip(hipEventRecord(e1, st), "record");
+    apply_heff_phase(env, precision, x, y, 2);
+    check_hip(hipEventRecord(e2, st), "record");
+    check_hip(hipEventSynchronize(e2), "event sync");
+    float a = 0, b = 0;
+    check_hip(hipEventElapsedTime(&a, e0, e1), "elapsed");
+    check_hip(hipEventElapsedTime(&b, e1, e2), "elapsed");
+    t1 += a;
+    t2 += b;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  *ms1 = (float)(t1 / reps);
+  *ms2 = (float)(t2 / reps);
+}
+
+}  // namespace lcc

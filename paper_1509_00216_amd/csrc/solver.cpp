@@ -1,0 +1,204 @@
+// Local LCC solve on the device: Q (H_eff - e0) Q x = Q b by conjugate gradients
+// (Implementation section), optionally as FP64 iterative refinement around a
+// low-precision CG.  All dot products accumulate in FP64 and every scalar of the
+// recurrences is FP64; only the operator products and the vector updates of the inner
+// solve run in FP32.
+#include <chrono>
+#include <cmath>
+
+#include "state.h"
+
+namespace lcc {
+namespace {
+
+struct Ops {
+  Env& env;
+  hipStream_t st;
+  int64_t n;
+  double e0;
+  const double* v64;   // may be null
+  float* v32;          // FP32 copy of v (inner solve) or null
+  int applies64 = 0, applies_low = 0;
+
+  double dot64(const double* a, const double* b) {
+    Context* c = env.ctx;
+    check_hip(launch_dot_f64(a, b, n, c->dot_partial.as<double>(), c->dot_out.as<double>(), st), "dot");
+    check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+    check_hip(hipStreamSynchronize(st), "dot sync");
+    return c->host_scalar[0];
+  }
+  double dot32(const float* a, const float* b) {
+    Context* c = env.ctx;
+    check_hip(launch_dot_f32(a, b, n, c->dot_partial.as<double>(), c->dot_out.as<double>(), st), "dot");
+    check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+    check_hip(hipStreamSynchronize(st), "dot sync");
+    return c->host_scalar[0];
+  }
+  // z <- z - (v.z) v
+  void project64(double* z) {
+    if (!v64) return;
+    const double c = dot64(v64, z);
+    check_hip(launch_axpby_f64(n, -c, v64, 1.0, z, st), "project");
+  }
+  void project32(float* z) {
+    if (!v32) return;
+    const double c = dot32(v32, z);
+    check_hip(launch_axpby_f32(n, -c, v32, 1.0, z, st), "project");
+  }
+  // out = Q (H - e0) Q in ; `in` is assumed to lie in range(Q) already (all iterates do)
+  void A64(const double* in, double* out) {
+    apply_heff(env, LCC_FP64, in, out);
+    ++applies64;
+    check_hip(launch_axpby_f64(n, -e0, in, 1.0, out, st), "shift");
+    project64(out);
+  }
+  void A32(int prec, const float* in, float* out) {
+    apply_heff(env, prec, in, out);
+    ++applies_low;
+    check_hip(launch_axpby_f32(n, -e0, in, 1.0, out, st), "shift");
+    project32(out);
+  }
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, double e0, const double* v,
+                       double* x, lcc_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = env.ctx->stream;
+  const int64_t n = env.n_elements;
+  const int prec = o.precision;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
+  const double tol = o.tol > 0 ? o.tol : 1e-10;
+  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (prec == LCC_BF16X3 ? 1e-4 : 1e-6);
+  const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+  const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
+  if (prec != LCC_FP64 && prec != LCC_FP32 && prec != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
+  if (!finite(e0)) throw Error{LCC_ERR_NAN, "e0 is not finite"};
+
+  Ops ops{env, st, n, e0, v, nullptr};
+  double* bq = env.w64[0].as<double>();
+  double* r = env.w64[1].as<double>();
+  double* p = env.w64[2].as<double>();
+  double* Ap = env.w64[3].as<double>();
+
+  // non-finite inputs
+  {
+    int* flag = env.flag.as<int>();
+    check_hip(launch_fill_f32(reinterpret_cast<float*>(flag), 1, 0.0f, st), "flag clear");
+    check_hip(launch_nonfinite_f64(b, n, flag, st), "nan check");
+    check_hip(launch_nonfinite_f64(x, n, flag, st), "nan check");
+    if (v) check_hip(launch_nonfinite_f64(v, n, flag, st), "nan check");
+    int h = 0;
+    check_hip(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+    check_hip(hipStreamSynchronize(st), "flag sync");
+    if (h) throw Error{LCC_ERR_NAN, "non-finite value in b, x or v"};
+  }
+  // bq = Q b ; x <- Q x
+  check_hip(hipMemcpyAsync(bq, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "copy b");
+  ops.project64(bq);
+  ops.project64(x);
+  const double bn = std::sqrt(ops.dot64(bq, bq));
+  lcc_solve_info inf{};
+  lcc_status status = LCC_OK;
+  auto residual64 = [&]() {  // r = bq - A x, returns ||r||
+    ops.A64(x, r);
+    check_hip(launch_axpby_f64(n, 1.0, bq, -1.0, r, st), "residual");
+    return std::sqrt(ops.dot64(r, r));
+  };
+  if (bn == 0.0) {
+    check_hip(launch_fill_f64(x, n, 0.0, st), "zero x");
+    check_hip(launch_fill_f64(r, n, 0.0, st), "zero r");
+  } else if (prec == LCC_FP64) {
+    double rnorm = residual64();
+    check_hip(hipMemcpyAsync(p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "p = r");
+    double rr = rnorm * rnorm;
+    int it = 0;
+    while (std::sqrt(rr) > tol * bn) {
+      if (it >= max_iter) { status = LCC_NOT_CONVERGED; break; }
+      ops.A64(p, Ap);
+      const double pAp = ops.dot64(p, Ap);
+      if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
+      if (pAp <= 0.0) throw Error{LCC_ERR_NOT_SPD, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
+      const double alpha = rr / pAp;
+      check_hip(launch_axpby_f64(n, alpha, p, 1.0, x, st), "x update");
+      ++it;
+      double rr_new;
+      if (it % replace_every == 0) {
+        const double rn = residual64();
+        rr_new = rn * rn;
+      } else {
+        check_hip(launch_axpby_f64(n, -alpha, Ap, 1.0, r, st), "r update");
+        rr_new = ops.dot64(r, r);
+      }
+      if (!finite(rr_new)) throw Error{LCC_ERR_NAN, "non-finite residual"};
+      const double beta = rr_new / rr;
+      check_hip(launch_axpby_f64(n, 1.0, r, beta, p, st), "p update");
+      rr = rr_new;
+    }
+    inf.iterations = it;
+    inf.outer = 1;
+    residual64();
+  } else {
+    // FP64 iterative refinement with a low-precision CG for each correction
+    ensure_fp32(env);
+    float* r32 = env.w32[0].as<float>();
+    float* d32 = env.w32[1].as<float>();
+    float* p32 = env.w32[2].as<float>();
+    float* Ap32 = env.w32[3].as<float>();
+    float* v32 = nullptr;
+    if (v) {
+      v32 = env.w32[4].as<float>();
+      check_hip(launch_convert_f64_f32(n, v, v32, st), "v32");
+    }
+    ops.v32 = v32;
+    int total_it = 0, outer = 0;
+    double rnorm = residual64();
+    while (rnorm > tol * bn) {
+      if (outer >= max_outer || total_it >= max_iter) { status = LCC_NOT_CONVERGED; break; }
+      ++outer;
+      // inner: A d = r / ||r||, d0 = 0
+      check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
+      check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / rnorm, r32, st), "scale r32");
+      check_hip(launch_fill_f32(d32, n, 0.0f, st), "d = 0");
+      check_hip(hipMemcpyAsync(p32, r32, sizeof(float) * n, hipMemcpyDeviceToDevice, st), "p = r");
+      double rr = ops.dot32(r32, r32);
+      const double r0 = std::sqrt(rr);
+      while (std::sqrt(rr) > inner_tol * r0 && total_it < max_iter) {
+        ops.A32(prec, p32, Ap32);
+        const double pAp = ops.dot32(p32, Ap32);
+        if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
+        if (pAp <= 0.0) throw Error{LCC_ERR_NOT_SPD, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
+        const double alpha = rr / pAp;
+        check_hip(launch_axpby_f32(n, alpha, p32, 1.0, d32, st), "d update");
+        check_hip(launch_axpby_f32(n, -alpha, Ap32, 1.0, r32, st), "r update");
+        const double rr_new = ops.dot32(r32, r32);
+        if (!finite(rr_new)) throw Error{LCC_ERR_NAN, "non-finite residual"};
+        check_hip(launch_axpby_f32(n, 1.0, r32, rr_new / rr, p32, st), "p update");
+        rr = rr_new;
+        ++total_it;
+      }
+      check_hip(launch_axpy_f32_into_f64(n, rnorm, d32, x, st), "x += d");
+      ops.project64(x);
+      rnorm = residual64();
+    }
+    inf.iterations = total_it;
+    inf.outer = outer;
+  }
+  // energy from the last FP64 residual r = bq - A x:  J = x^T A x - 2 bq^T x = -x^T r - bq^T x
+  const double xr = ops.dot64(x, r);
+  const double bx = ops.dot64(bq, x);
+  const double rn = std::sqrt(ops.dot64(r, r));
+  inf.rel_residual = bn > 0 ? rn / bn : 0.0;
+  inf.hylleraas = -xr - bx;
+  inf.e2 = -bx;
+  inf.applies_fp64 = ops.applies64;
+  inf.applies_low = ops.applies_low;
+  inf.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace lcc

@@ -1,0 +1,157 @@
+// Library state behind the opaque C handles.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mpslcc.h"
+#include "internal.h"
+
+namespace lcc {
+
+struct Error {
+  lcc_status code;
+  std::string msg;
+};
+
+// Owning device buffer (hipMalloc / hipFree).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // throws Error on failure
+  void alloc(size_t n);
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Upload a host vector into a fresh device buffer (synchronous on `stream`).
+template <class T>
+void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t stream);
+void check_hip(hipError_t e, const char* what);
+
+struct Context {
+  void* handle = nullptr;  // the owning lcc_context_s
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // scratch for reductions
+  DevBuf dot_partial, dot_out;
+  double* host_scalar = nullptr;  // pinned
+};
+
+struct Bond {
+  std::vector<QN> q;
+  std::vector<int> dim;
+  std::map<QN, int> index;
+  int find(const QN& x) const {
+    auto it = index.find(x);
+    return it == index.end() ? -1 : it->second;
+  }
+};
+
+// Block-sparse operator environment: one block per (channel w, column sector c);
+// the row sector is c shifted by the channel's (N, 2Sz) change.
+struct EnvBlock {
+  int w, r, c;
+  int64_t off;
+  int rows, cols;
+};
+struct Environment {
+  std::vector<EnvBlock> blocks;
+  std::unordered_map<int64_t, int> lookup;  // w * nsec + c -> block
+  int nsec = 0;
+  int64_t size = 0;
+  DevBuf data;
+  int find(int w, int c) const {
+    auto it = lookup.find((int64_t)w * nsec + c);
+    return it == lookup.end() ? -1 : it->second;
+  }
+};
+
+// One grouped-GEMM launch resident on the device.
+struct GemmLaunch {
+  bool ta = false, tb = false;
+  int shape = TILE_64x64;
+  int n_tiles = 0;
+  DevBuf terms, groups, tiles;
+};
+
+struct Plan {
+  std::vector<GemmLaunch> phase1, phase2;  // one launch per tile shape
+  double flops1 = 0, flops2 = 0;
+};
+
+struct MiddleSector {
+  QN q;
+  int nrows = 0, ncols = 0;
+  int64_t off = 0;
+  std::vector<std::pair<int, int>> rows;  // (left sector a, s1)
+  std::vector<int> row_off;
+  std::vector<std::pair<int, int>> cols;  // (s2, right sector b)
+  std::vector<int> col_off;
+};
+
+struct Env {
+  Context* ctx = nullptr;
+  int site = 0, K = 0;
+  int D_mid = 0;
+  Bond bl, br;  // MPS bonds site and site+2
+  std::vector<MiddleSector> sectors;
+  std::vector<lcc_block_entry> layout;
+  int64_t n_elements = 0;
+  // device data: [L blocks | R blocks] in FP64 (+ FP32 copy), merged blocks (+ FP32 copy)
+  DevBuf env64, env32, merged64, merged32, tbuf;
+  int64_t env_elems = 0, merged_elems = 0, t_elems = 0;
+  Plan plan;
+  // CG workspace
+  DevBuf w64[6], w32[6];
+  DevBuf flag;
+  bool have32 = false;
+};
+
+struct Hamiltonian {
+  Context* ctx = nullptr;
+  HamDesc desc;
+  Mpo mpo;
+};
+
+// env.cpp
+Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);
+void ensure_fp32(Env& env);
+void apply_heff(Env& env, int precision, const void* x, void* y);
+// phase 0 = both, 1 = enlarged left operator into the intermediate, 2 = into y
+void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase);
+// lanczos.cpp
+void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual);
+void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2);
+// solver.cpp
+lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, double e0, const double* v,
+                       double* x, lcc_solve_info* info);
+
+}  // namespace lcc
+
+struct lcc_context_s {
+  lcc::Context c;
+};
+struct lcc_hamiltonian_s {
+  lcc::Hamiltonian h;
+};
+struct lcc_env_s {
+  std::unique_ptr<lcc::Env> e;
+};

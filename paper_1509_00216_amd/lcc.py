@@ -1,0 +1,354 @@
+"""Python binding of libmpslcc (ctypes).  Argument marshalling only.
+
+The names follow the C ABI in include/mpslcc.h: create_hamiltonian, build_environments,
+apply_heff, solve_local_lcc, ...  Device vectors are torch tensors on the context's device
+(PyTorch is used for device memory and streams); every arithmetic step runs in the library.
+If the shared library is missing this module raises on import of the library, it never
+falls back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpslcc.so")
+
+LCC_FP64, LCC_FP32, LCC_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": LCC_FP64, "fp32": LCC_FP32, "bf16x3": LCC_BF16X3}
+STATUS = {0: "LCC_OK", 1: "LCC_NOT_CONVERGED", -1: "LCC_ERR_ARG", -2: "LCC_ERR_QN", -3: "LCC_ERR_NOT_SPD",
+          -4: "LCC_ERR_NAN", -5: "LCC_ERR_OOM", -6: "LCC_ERR_HIP", -7: "LCC_ERR_STATE", -8: "LCC_ERR_NODEV"}
+EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_context_synchronize",
+           "lcc_create_hamiltonian", "lcc_hamiltonian_destroy", "lcc_hamiltonian_bond_dims",
+           "lcc_hamiltonian_channels", "lcc_hamiltonian_site_mpo", "lcc_build_environments",
+           "lcc_env_destroy", "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
+           "lcc_env_profile_apply", "lcc_lowest_eigenvalue"]
+
+
+class LccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class HamDesc(C.Structure):
+    _fields_ = [("n_orb", C.c_int32), ("n_elec", C.c_int32), ("two_sz", C.c_int32),
+                ("h", C.POINTER(C.c_double)), ("eri", C.POINTER(C.c_double)),
+                ("u_onsite", C.POINTER(C.c_double)), ("e_const", C.c_double), ("switch_bond", C.c_int32)]
+
+
+class Sector(C.Structure):
+    _fields_ = [("n", C.c_int32), ("two_sz", C.c_int32), ("dim", C.c_int32)]
+
+
+class MpsBlock(C.Structure):
+    _fields_ = [("left", C.c_int32), ("s", C.c_int32), ("right", C.c_int32), ("data", C.POINTER(C.c_double))]
+
+
+class MpsDesc(C.Structure):
+    _fields_ = [("n_sites", C.c_int32), ("bond_offsets", C.POINTER(C.c_int32)), ("sectors", C.POINTER(Sector)),
+                ("block_offsets", C.POINTER(C.c_int64)), ("blocks", C.POINTER(MpsBlock))]
+
+
+class LayoutInfo(C.Structure):
+    _fields_ = [("n_elements", C.c_int64), ("n_blocks", C.c_int32), ("n_sectors", C.c_int32),
+                ("mpo_bond_dim", C.c_int32), ("reserved", C.c_int32), ("flops_per_apply", C.c_double)]
+
+
+class BlockEntry(C.Structure):
+    _fields_ = [("left", C.c_int32), ("s1", C.c_int32), ("s2", C.c_int32), ("right", C.c_int32),
+                ("offset", C.c_int64), ("ld", C.c_int32), ("rows", C.c_int32), ("cols", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("replace_every", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("outer", C.c_int32), ("applies_fp64", C.c_int32),
+                ("applies_low", C.c_int32), ("rel_residual", C.c_double), ("hylleraas", C.c_double),
+                ("e2", C.c_double), ("ms_total", C.c_double)]
+
+
+_lib = None
+
+
+def library() -> C.CDLL:
+    """Load libmpslcc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_00216_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "lcc_context_create": (C.c_int32, [C.c_int32, P, C.POINTER(P)]),
+        "lcc_context_destroy": (None, [P]),
+        "lcc_last_error": (C.c_char_p, [P]),
+        "lcc_context_synchronize": (C.c_int32, [P]),
+        "lcc_create_hamiltonian": (C.c_int32, [P, C.POINTER(HamDesc), C.POINTER(P)]),
+        "lcc_hamiltonian_destroy": (None, [P]),
+        "lcc_hamiltonian_bond_dims": (C.c_int32, [P, C.POINTER(C.c_int32)]),
+        "lcc_hamiltonian_channels": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "lcc_hamiltonian_site_mpo": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                                 C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "lcc_build_environments": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
+        "lcc_env_destroy": (None, [P]),
+        "lcc_env_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
+        "lcc_env_flops": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "lcc_apply_heff": (C.c_int32, [P, C.c_int32, P, P]),
+        "lcc_solve_local_lcc": (C.c_int32, [P, C.POINTER(SolveOpts), P, C.c_double, P, P, C.POINTER(SolveInfo)]),
+        "lcc_env_profile_apply": (C.c_int32, [P, C.c_int32, P, P, C.c_int32, C.POINTER(C.c_float),
+                                              C.POINTER(C.c_float)]),
+        "lcc_lowest_eigenvalue": (C.c_int32, [P, C.c_int32, C.c_uint64, C.POINTER(C.c_double),
+                                              C.POINTER(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code, ctx=None, allow=(0,)):
+    if code in allow:
+        return code
+    msg = library().lcc_last_error(ctx)
+    raise LccError(code, msg.decode() if msg else "")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _tensor_ptr(t, dtype_name: str, n: int):
+    import torch
+    want = {"fp64": torch.float64, "fp32": torch.float32}[dtype_name]
+    if t.dtype != want or not t.is_contiguous() or t.numel() != n or t.device.type != "cuda":
+        raise ValueError(f"expected a contiguous {want} CUDA tensor of {n} elements, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """lcc_context on a device (or host-only with device=-1)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = library()
+        h = C.c_void_p()
+        s = None
+        if device >= 0:
+            import torch
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            s = C.c_void_p(stream.cuda_stream) if stream.cuda_stream else None
+        _check(lib.lcc_context_create(device, s, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            library().lcc_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synchronize(self):
+        _check(library().lcc_context_synchronize(self.handle), self.handle)
+
+    def create_hamiltonian(self, spec: dict, switch_bond: int = -1) -> "Hamiltonian":
+        return create_hamiltonian(self, spec, switch_bond)
+
+    def build_environments(self, ham: "Hamiltonian", mps: dict, site: int | None = None) -> "Env":
+        return build_environments(self, ham, mps, site)
+
+
+def context_create(device: int = 0, stream=None) -> Context:
+    return Context(device, stream)
+
+
+class Hamiltonian:
+    def __init__(self, handle, ctx, n_orb):
+        self.handle = handle
+        self.ctx = ctx
+        self.n_orb = n_orb
+
+    def close(self):
+        if self.handle:
+            library().lcc_hamiltonian_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bond_dims(self) -> np.ndarray:
+        out = np.zeros(self.n_orb + 1, dtype=np.int32)
+        _check(library().lcc_hamiltonian_bond_dims(self.handle, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def channels(self, bond: int):
+        D = int(self.bond_dims()[bond])
+        dn = np.zeros(D, dtype=np.int32)
+        dz = np.zeros(D, dtype=np.int32)
+        _check(library().lcc_hamiltonian_channels(self.handle, bond, dn.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  dz.ctypes.data_as(C.POINTER(C.c_int32))))
+        return dn, dz
+
+    def site_mpo(self, site: int):
+        lib = library()
+        cnt = C.c_int64(0)
+        _check(lib.lcc_hamiltonian_site_mpo(self.handle, site, C.byref(cnt), None, None, None))
+        n = cnt.value
+        wi = np.zeros(n, dtype=np.int32)
+        wo = np.zeros(n, dtype=np.int32)
+        m = np.zeros((n, 4, 4))
+        _check(lib.lcc_hamiltonian_site_mpo(self.handle, site, C.byref(cnt), wi.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            wo.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(m)))
+        return wi, wo, m
+
+
+def create_hamiltonian(ctx: Context | None, spec: dict, switch_bond: int = -1) -> Hamiltonian:
+    n = spec["n_orb"]
+    h = np.ascontiguousarray(spec["h"], dtype=np.float64)
+    eri = None if spec.get("eri") is None else np.ascontiguousarray(spec["eri"], dtype=np.float64)
+    u = None if spec.get("u") is None else np.ascontiguousarray(spec["u"], dtype=np.float64)
+    d = HamDesc(n, spec["n_elec"], spec["two_sz"], _dptr(h), _dptr(eri) if eri is not None else None,
+                _dptr(u) if u is not None else None, float(spec.get("e_const", 0.0)), switch_bond)
+    out = C.c_void_p()
+    ch = ctx.handle if ctx is not None else None
+    _check(library().lcc_create_hamiltonian(ch, C.byref(d), C.byref(out)), ch)
+    return Hamiltonian(out, ctx, n)
+
+
+def _mps_desc(mps: dict):
+    """Marshal a workloads-style MPS dict into lcc_mps_desc (keeps the arrays alive)."""
+    K = mps["n_sites"]
+    bond_off = np.zeros(K + 2, dtype=np.int32)
+    secs = []
+    for j, bond in enumerate(mps["bonds"]):
+        secs.extend(bond)
+        bond_off[j + 1] = len(secs)
+    bond_off[K + 1] = len(secs)
+    sectors = (Sector * max(1, len(secs)))(*[Sector(int(n), int(z), int(d)) for n, z, d in secs])
+    keep = []
+    blocks = []
+    blk_off = np.zeros(K + 1, dtype=np.int64)
+    for j, site in enumerate(mps["sites"]):
+        for il, s, ir, a in site:
+            arr = np.ascontiguousarray(a, dtype=np.float64)
+            keep.append(arr)
+            blocks.append(MpsBlock(int(il), int(s), int(ir), _dptr(arr)))
+        blk_off[j + 1] = len(blocks)
+    barr = (MpsBlock * max(1, len(blocks)))(*blocks)
+    desc = MpsDesc(K, bond_off.ctypes.data_as(C.POINTER(C.c_int32)), sectors,
+                   blk_off.ctypes.data_as(C.POINTER(C.c_int64)), barr)
+    return desc, (bond_off, sectors, blk_off, barr, keep)
+
+
+class Env:
+    """Environments + plan of one two-site block; vectors use `layout()`."""
+
+    def __init__(self, handle, ctx: Context):
+        self.handle = handle
+        self.ctx = ctx
+        info = LayoutInfo()
+        _check(library().lcc_env_layout(self.handle, C.byref(info), None))
+        self.n = int(info.n_elements)
+        self.n_blocks = int(info.n_blocks)
+        self.n_sectors = int(info.n_sectors)
+        self.mpo_bond_dim = int(info.mpo_bond_dim)
+        self.flops_per_apply = float(info.flops_per_apply)
+        arr = (BlockEntry * max(1, self.n_blocks))()
+        _check(library().lcc_env_layout(self.handle, C.byref(info), arr))
+        self.blocks = {(b.left, b.s1, b.s2, b.right): (b.offset, b.ld, b.rows, b.cols)
+                       for b in arr[: self.n_blocks]}
+
+    def close(self):
+        if self.handle:
+            library().lcc_env_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def flops(self):
+        a, b = C.c_double(), C.c_double()
+        _check(library().lcc_env_flops(self.handle, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    # -- marshalling between {(a, s1, s2, b): block} dicts and flat vectors
+    def pack(self, vec: dict) -> np.ndarray:
+        out = np.zeros(self.n)
+        for key, (off, ld, rows, cols) in self.blocks.items():
+            blk = vec.get(key)
+            if blk is None:
+                continue
+            idx = off + np.arange(rows)[:, None] * ld + np.arange(cols)[None, :]
+            out[idx] = blk
+        return out
+
+    def unpack(self, flat: np.ndarray) -> dict:
+        out = {}
+        for key, (off, ld, rows, cols) in self.blocks.items():
+            idx = off + np.arange(rows)[:, None] * ld + np.arange(cols)[None, :]
+            out[key] = np.asarray(flat)[idx]
+        return out
+
+    def apply_heff(self, x, y, precision: str = "fp64"):
+        dt = "fp64" if precision == "fp64" else "fp32"
+        _check(library().lcc_apply_heff(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n),
+                                        _tensor_ptr(y, dt, self.n)), self.ctx.handle)
+
+    def profile_apply(self, x, y, precision: str = "fp64", reps: int = 10):
+        """Mean milliseconds of (phase 1, phase 2) of H_eff x, timed with HIP events."""
+        dt = "fp64" if precision == "fp64" else "fp32"
+        a, b = C.c_float(), C.c_float()
+        _check(library().lcc_env_profile_apply(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n),
+                                               _tensor_ptr(y, dt, self.n), reps, C.byref(a), C.byref(b)),
+               self.ctx.handle)
+        return a.value, b.value
+
+    def lowest_eigenvalue(self, steps: int = 60, seed: int = 1):
+        th, res = C.c_double(), C.c_double()
+        _check(library().lcc_lowest_eigenvalue(self.handle, steps, seed, C.byref(th), C.byref(res)),
+               self.ctx.handle)
+        return th.value, res.value
+
+    def solve_local_lcc(self, b, e0: float, x, v=None, precision: str = "fp64", tol: float = 1e-10,
+                        max_iter: int = 1000, inner_tol: float = 0.0, max_outer: int = 20,
+                        replace_every: int = 50) -> dict:
+        opts = SolveOpts(PRECISIONS[precision], max_iter, tol, inner_tol, max_outer, replace_every)
+        info = SolveInfo()
+        code = library().lcc_solve_local_lcc(self.handle, C.byref(opts), _tensor_ptr(b, "fp64", self.n),
+                                             float(e0), _tensor_ptr(v, "fp64", self.n) if v is not None else None,
+                                             _tensor_ptr(x, "fp64", self.n), C.byref(info))
+        _check(code, self.ctx.handle, allow=(0, 1))
+        return {"status": STATUS[code], "iterations": info.iterations, "outer": info.outer,
+                "applies_fp64": info.applies_fp64, "applies_low": info.applies_low,
+                "rel_residual": info.rel_residual, "hylleraas": info.hylleraas, "e2": info.e2,
+                "ms_total": info.ms_total}
+
+
+def build_environments(ctx: Context, ham: Hamiltonian, mps: dict, site: int | None = None) -> Env:
+    if site is None:
+        site = mps["center"]
+    desc, keep = _mps_desc(mps)
+    out = C.c_void_p()
+    _check(library().lcc_build_environments(ctx.handle, ham.handle, C.byref(desc), site, C.byref(out)), ctx.handle)
+    del keep
+    return Env(out, ctx)

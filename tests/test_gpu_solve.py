@@ -1,0 +1,147 @@
+"""GPU local LCC solve (conjugate gradients, FP64 and mixed precision with FP64 refinement)
+against the oracle's exact solution, plus the error paths forced from the host.
+
+Bars: energy |J(x_gpu) - J(x*)| <= 1e-8 for every precision after refinement;
+FP64 solution relative error <= kappa * tol.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import need_gpu, rel, say, to_dev
+from oracle import blocksparse as BS
+from oracle import fock
+from oracle import mpo as OM
+from oracle import solve as OS
+from workloads import configs as C
+from workloads import mps as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch, lcc = need_gpu()
+    return lcc.Context(0)
+
+
+@pytest.fixture(scope="module")
+def chain(ctx):
+    """Complete-basis chain: E0 = E_ED, Q removes the ED ground state (singular but consistent)."""
+    spec, mps = C.make("hubbard1d_k8_m64")
+    blocks = M.two_site_blocks(mps)
+    heff = fock.effective_hamiltonian(spec, mps, blocks)
+    w, U = np.linalg.eigh(heff)
+    rng = np.random.Generator(np.random.PCG64(1001 + 3))
+    b = rng.standard_normal(heff.shape[0])
+    b /= np.linalg.norm(b)
+    v = U[:, 0]
+    xs = OS.dense_solution(heff, b, w[0], v)
+    A = OS.make_operator(lambda z: heff @ z, w[0], v)
+    jstar = OS.hylleraas(A, xs, OS.project(v, b))
+    kappa = w[-1] / w[1] if w[1] > 0 else np.inf
+    env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
+    tmpl = BS.two_site_template(mps, blocks)
+    to_layout = lambda flat: env.pack(BS.unflatten(flat, tmpl, blocks))
+    return dict(spec=spec, mps=mps, env=env, b=to_layout(b), v=to_layout(v), e0=w[0], xs=to_layout(xs),
+                jstar=jstar, kappa=(w[-1] - w[0]) / (w[1] - w[0]))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_chain_solve_with_projector(chain, precision):
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    say(f"[solve] chain8 {precision}")
+    b = to_dev(torch, chain["b"], torch.float64)
+    v = to_dev(torch, chain["v"], torch.float64)
+    x = torch.zeros_like(b)
+    info = env.solve_local_lcc(b, chain["e0"], x, v=v, precision=precision, tol=1e-10)
+    say(f"  {info}")
+    assert info["status"] == "LCC_OK"
+    assert info["rel_residual"] <= 1e-10
+    xg = x.cpu().numpy()
+    assert abs(info["hylleraas"] - chain["jstar"]) <= 1e-8
+    assert abs(info["e2"] - chain["jstar"]) <= 1e-8
+    assert rel(xg, chain["xs"]) <= max(1e-12, chain["kappa"] * 1e-10)
+    if precision != "fp64":
+        assert info["applies_low"] > 0 and info["outer"] >= 1
+
+
+@pytest.mark.parametrize("name,m", [("hubbard2d_4x4_m500", 80), ("threeband_4x2_m2000", 200)])
+def test_lattice_solve_vs_oracle_cg(ctx, name, m):
+    torch, lcc = need_gpu()
+    spec, mps = C.make(name, m_max=m)
+    e0 = C.lower_bound_shift(spec, 0.5)
+    say(f"[solve] {name}@M={m} e0={e0}")
+    oenv = BS.Environments(spec, mps, OM.build_mpo(spec))
+    blocks = M.two_site_blocks(mps)
+    tmpl = BS.two_site_template(mps, blocks)
+    apply_o = lambda z: BS.flatten(oenv.apply(BS.unflatten(z, tmpl, blocks)), blocks)
+    bvec = M.random_two_site_vector(mps, 1002 + 7)
+    bflat = BS.flatten(bvec, blocks)
+    A = OS.make_operator(apply_o, e0)
+    xo, it, relres, _ = OS.cg(A, bflat, tol=1e-13, max_iter=3000)
+    jstar = OS.hylleraas(A, xo, bflat)
+    env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
+    bd = to_dev(torch, env.pack(bvec), torch.float64)
+    xref = env.pack(BS.unflatten(xo, tmpl, blocks))
+    for prec in ("fp64", "fp32", "bf16x3"):
+        x = torch.zeros_like(bd)
+        info = env.solve_local_lcc(bd, e0, x, precision=prec, tol=1e-10, max_iter=4000)
+        say(f"  {prec}: {info}")
+        assert info["status"] == "LCC_OK"
+        assert abs(info["hylleraas"] - jstar) <= 1e-8
+        assert rel(x.cpu().numpy(), xref) <= 1e-6
+
+
+def test_indefinite_shift_is_reported(chain):
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    b = to_dev(torch, chain["b"], torch.float64)
+    x = torch.zeros_like(b)
+    with pytest.raises(lcc.LccError) as e:
+        env.solve_local_lcc(b, 1e3, x, precision="fp64")  # e0 far above the spectrum
+    assert e.value.code == -3
+
+
+def test_nan_input_is_reported(chain):
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    bh = chain["b"].copy()
+    bh[17] = np.nan
+    b = to_dev(torch, bh, torch.float64)
+    x = torch.zeros_like(b)
+    with pytest.raises(lcc.LccError) as e:
+        env.solve_local_lcc(b, chain["e0"], x)
+    assert e.value.code == -4
+
+
+def test_max_iter_returns_not_converged(chain):
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    b = to_dev(torch, chain["b"], torch.float64)
+    v = to_dev(torch, chain["v"], torch.float64)
+    x = torch.zeros_like(b)
+    info = env.solve_local_lcc(b, chain["e0"], x, v=v, max_iter=1)
+    assert info["status"] == "LCC_NOT_CONVERGED"
+    assert info["iterations"] == 1
+    assert np.isfinite(x.cpu().numpy()).all() and float(x.abs().sum()) > 0
+
+
+def test_bad_descriptors(ctx):
+    torch, lcc = need_gpu()
+    spec, mps = C.make("hubbard1d_k8_m64")
+    ham = ctx.create_hamiltonian(spec)
+    # a block whose right sector violates N/Sz conservation
+    bad = dict(mps, sites=[list(s) for s in mps["sites"]])
+    il, s, ir, a = bad["sites"][1][0]
+    wrong = (ir + 1) % len(mps["bonds"][2])
+    bad["sites"][1][0] = (il, s, wrong, np.zeros((mps["bonds"][1][il][2], mps["bonds"][2][wrong][2])))
+    with pytest.raises(lcc.LccError) as e:
+        ctx.build_environments(ham, bad)
+    assert e.value.code in (-2, -1)
+    # a left site that is not left-canonical
+    scaled = dict(mps, sites=[list(s) for s in mps["sites"]])
+    scaled["sites"][1] = [(a, b, c, 1.1 * d) for a, b, c, d in scaled["sites"][1]]
+    with pytest.raises(lcc.LccError) as e:
+        ctx.build_environments(ham, scaled)
+    assert e.value.code == -1
