@@ -88,22 +88,34 @@ struct GemmBuilder {
   }
 };
 
-int shape_for(int m) { return m <= 16 ? TILE_32x32 : TILE_64x64; }
-void shape_dims(int shape, int& bm, int& bn) {
-  if (shape == TILE_64x64) { bm = 64; bn = 64; } else { bm = 16; bn = 64; }
+// Tile shape of a group: the one with the least padded output area plus a fixed per-tile
+// cost (staging, descriptor loads, epilogue), so tiny blocks get small tiles and large
+// blocks get large ones.
+constexpr double kTileOverhead = 2048.0;  // in output elements
+// accumulation length (sum of k over terms) above which a group is split across workgroups
+constexpr int64_t kSplitK = 2048;
+int shape_for(int m, int n) {
+  int best = TILE_64x64;
+  double best_cost = 1e300;
+  for (int s = 0; s < kNumTileShapes; ++s) {
+    const int bm = kTileShapes[s][0], bn = kTileShapes[s][1];
+    const double tiles = (double)((m + bm - 1) / bm) * ((n + bn - 1) / bn);
+    const double cost = tiles * (bm * (double)bn + kTileOverhead);
+    if (cost < best_cost) { best_cost = cost; best = s; }
+  }
+  return best;
 }
 
 std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s) {
   std::vector<GemmLaunch> out;
-  for (int shape : {TILE_64x64, TILE_32x32}) {
-    int bm, bn;
-    shape_dims(shape, bm, bn);
+  for (int shape = 0; shape < kNumTileShapes; ++shape) {
+    const int bm = kTileShapes[shape][0], bn = kTileShapes[shape][1];
     std::vector<GemmTerm> terms;
     std::vector<GemmGroup> groups;
     std::vector<GemmTile> tiles;
     for (const GemmGroup& g0 : b.groups) {
       if (g0.m <= 0 || g0.n <= 0) continue;
-      if (shape_for(g0.m) != shape) continue;
+      if (shape_for(g0.m, g0.n) != shape) continue;
       GemmGroup g = g0;
       g.term_begin = (int32_t)terms.size();
       for (int t = g0.term_begin; t < g0.term_end; ++t) terms.push_back(b.terms[t]);
@@ -125,6 +137,60 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
     upload(L.groups, groups, s);
     upload(L.tiles, tiles, s);
     out.push_back(std::move(L));
+  }
+  return out;
+}
+
+// Split-K: a group whose accumulation chain is longer than `k_per_part` is cut into parts of
+// about equal total k; each part writes its own partial tile into the workspace and a
+// reduction adds the parts in order.  This keeps every CU busy when there are few output
+// blocks with long chains (phase 2 sums over every middle-bond channel).
+GemmBuilder split_k(const GemmBuilder& in, int64_t k_per_part, int max_parts, std::vector<ReduceGroup>& red,
+                    int64_t& work_elems) {
+  GemmBuilder out;
+  out.flops = in.flops;
+  for (const GemmGroup& g : in.groups) {
+    int64_t ksum = 0;
+    for (int t = g.term_begin; t < g.term_end; ++t) ksum += in.terms[t].k;
+    const int nterms = g.term_end - g.term_begin;
+    int parts = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + k_per_part - 1) / k_per_part), max_parts);
+    parts = std::min(parts, std::max(1, nterms));
+    if (parts <= 1 || g.accumulate) {
+      GemmGroup c = g;
+      c.term_begin = (int32_t)out.terms.size();
+      for (int t = g.term_begin; t < g.term_end; ++t) out.terms.push_back(in.terms[t]);
+      c.term_end = (int32_t)out.terms.size();
+      out.groups.push_back(c);
+      continue;
+    }
+    const int64_t mn = (int64_t)g.m * g.n;
+    const int64_t woff = work_elems;
+    int made = 0;
+    int t = g.term_begin;
+    int64_t acc = 0;
+    for (int p = 0; p < parts; ++p) {
+      GemmGroup c = g;
+      c.c_base = BASE_WORK;
+      c.c_off = woff + (int64_t)p * mn;
+      c.ldc = g.n;
+      c.accumulate = 0;
+      c.term_begin = (int32_t)out.terms.size();
+      const int64_t goal = (ksum * (p + 1)) / parts;
+      const int left_parts = parts - p - 1;
+      // take terms until the goal, always at least one, leaving one per remaining part
+      do {
+        acc += in.terms[t].k;
+        out.terms.push_back(in.terms[t]);
+        ++t;
+      } while (t < g.term_end && acc < goal && (g.term_end - t) > left_parts);
+      if (p == parts - 1)
+        while (t < g.term_end) { out.terms.push_back(in.terms[t]); ++t; }
+      c.term_end = (int32_t)out.terms.size();
+      out.groups.push_back(c);
+      ++made;
+    }
+    work_elems += (int64_t)made * mn;
+    red.push_back(ReduceGroup{g.c_off, woff, g.ldc, g.m, g.n, made});
   }
   return out;
 }
@@ -712,7 +778,22 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
   env->plan.flops1 = p1.flops;
   env->plan.flops2 = p2.flops;
   env->plan.phase1 = finalize(p1, false, false, st);
-  env->plan.phase2 = finalize(p2, false, true, st);
+  {
+    std::vector<ReduceGroup> red;
+    int64_t work = 0;
+    GemmBuilder p2s = split_k(p2, kSplitK, 64, red, work);
+    env->plan.phase2 = finalize(p2s, false, true, st);
+    std::vector<ReduceTile> rt;
+    for (size_t g = 0; g < red.size(); ++g) {
+      const int64_t mn = (int64_t)red[g].m * red[g].n;
+      for (int64_t c = 0; c * kReduceChunk < mn; ++c) rt.push_back(ReduceTile{(int32_t)g, (int32_t)c});
+    }
+    upload(env->plan.reduce_groups, red, st);
+    upload(env->plan.reduce_tiles, rt, st);
+    env->plan.n_reduce_tiles = (int)rt.size();
+    env->work_elems = work;
+    env->work.alloc(sizeof(double) * std::max<int64_t>(work, 1));
+  }
   // CG workspace (FP64)
   for (auto& w : env->w64) w.alloc(sizeof(double) * std::max<int64_t>(env->n_elements, 1));
   env->flag.alloc(sizeof(int) * 4);
@@ -737,6 +818,7 @@ void apply_heff(Env& env, int precision, const void* x, void* y) { apply_heff_ph
 
 void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase) {
   hipStream_t st = env.ctx->stream;
+  const Plan& P = env.plan;
   if (precision == LCC_FP64) {
     Bases<double> b{};
     b.p[BASE_ENV] = env.env64.as<double>();
@@ -744,8 +826,14 @@ void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase
     b.p[BASE_X] = const_cast<double*>(static_cast<const double*>(x));
     b.p[BASE_T] = env.tbuf.as<double>();
     b.p[BASE_Y] = static_cast<double*>(y);
-    if (phase != 2) run_gemm64(env.plan.phase1, b, st);
-    if (phase != 1) run_gemm64(env.plan.phase2, b, st);
+    b.p[BASE_WORK] = env.work.as<double>();
+    if (phase != 2) run_gemm64(P.phase1, b, st);
+    if (phase != 1) {
+      run_gemm64(P.phase2, b, st);
+      check_hip(launch_reduce_f64(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
+                                  P.n_reduce_tiles, b, st),
+                "reduce launch");
+    }
     return;
   }
   ensure_fp32(env);
@@ -755,9 +843,10 @@ void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase
   b.p[BASE_X] = const_cast<float*>(static_cast<const float*>(x));
   b.p[BASE_T] = env.tbuf.as<float>();
   b.p[BASE_Y] = static_cast<float*>(y);
+  b.p[BASE_WORK] = env.work.as<float>();
   for (int ph = 1; ph <= 2; ++ph) {
     if (phase != 0 && phase != ph) continue;
-    for (const GemmLaunch& L : ph == 1 ? env.plan.phase1 : env.plan.phase2) {
+    for (const GemmLaunch& L : ph == 1 ? P.phase1 : P.phase2) {
       hipError_t e = precision == LCC_FP32
                          ? launch_gemm_f32(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
                                            L.n_tiles, L.ta, L.tb, L.shape, b, st)
@@ -765,6 +854,10 @@ void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase
                                               L.n_tiles, L.ta, L.tb, L.shape, b, st);
       check_hip(e, "gemm low-precision launch");
     }
+    if (ph == 2)
+      check_hip(launch_reduce_f32(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
+                                  P.n_reduce_tiles, b, st),
+                "reduce launch");
   }
 }
 

@@ -56,7 +56,7 @@ std::string build_mpo(const HamDesc& d, Mpo& out);
 // every call: base 0 = environment data, 1 = input vector, 2 = intermediate, 3 = output,
 // 4 = merged environment blocks, 5 = MPS data.
 // ----------------------------------------------------------------------------------------
-enum { BASE_ENV = 0, BASE_X = 1, BASE_T = 2, BASE_Y = 3, BASE_MERGED = 4, BASE_MPS = 5, NUM_BASES = 6 };
+enum { BASE_ENV = 0, BASE_X = 1, BASE_T = 2, BASE_Y = 3, BASE_MERGED = 4, BASE_MPS = 5, BASE_WORK = 6, NUM_BASES = 7 };
 
 struct GemmTerm {
   int64_t a_off, b_off;
@@ -92,13 +92,25 @@ struct MixTile {
   int32_t group, chunk;
 };
 
+// Split-K reduction: dst[r*ldc + c] = sum_{p < parts} src[p*m*n + r*n + c], p ascending.
+struct ReduceGroup {
+  int64_t dst_off, src_off;
+  int32_t ldc, m, n, parts;
+};
+struct ReduceTile {
+  int32_t group, chunk;
+};
+
 template <class T>
 struct Bases {
   T* p[NUM_BASES];
 };
 
-// Tile shapes of the grouped GEMM (output rows x cols per workgroup).
-enum TileShape { TILE_64x64 = 0, TILE_32x32 = 1 };
+// Tile shapes of the grouped GEMM: output rows x cols per workgroup of four waves.
+constexpr int kNumTileShapes = 8;
+constexpr int kTileShapes[kNumTileShapes][2] = {{64, 64}, {16, 64}, {64, 16}, {32, 32},
+                                                {128, 64}, {64, 128}, {32, 64}, {64, 32}};
+enum TileShape { TILE_64x64 = 0, TILE_16x64 = 1 };
 
 // Launchers (kernels.hip).  All asynchronous on `stream`.
 hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
@@ -110,6 +122,11 @@ hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const
 hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                               int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
                               hipStream_t stream);
+hipError_t launch_reduce_f64(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
+                             const Bases<double>& b, hipStream_t stream);
+hipError_t launch_reduce_f32(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
+                             const Bases<float>& b, hipStream_t stream);
+constexpr int kReduceChunk = 1024;
 hipError_t launch_mix_f64(const MixTerm* terms, const MixGroup* groups, const MixTile* tiles,
                           int n_tiles, const Bases<double>& b, hipStream_t stream);
 

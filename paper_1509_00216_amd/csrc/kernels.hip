@@ -58,6 +58,45 @@ struct Mfma<1> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Operand staging shared by the kernels: each thread holds NA elements of the next A chunk
+// and NB of the next B chunk in registers, so the global loads of chunk i+1 are in flight
+// while the MFMAs of chunk i run.  Element e of a chunk maps to (row, k) so that consecutive
+// threads read consecutive addresses of the stored (row-major) operand.
+template <class T, bool TA, int BM, int BK>
+struct ALoader {
+  static constexpr int N = BM * BK / kThreads;
+  static __device__ __forceinline__ void coords(int e, int& mm, int& kk) {
+    if (!TA) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
+  }
+  static __device__ __forceinline__ void load(T (&r)[N], const T* __restrict__ A, int lda, int row0, int m,
+                                              int k0, int K) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      int mm, kk;
+      coords(threadIdx.x + i * kThreads, mm, kk);
+      const int gr = row0 + mm, gk = k0 + kk;
+      r[i] = (gr < m && gk < K) ? (TA ? A[(int64_t)gk * lda + gr] : A[(int64_t)gr * lda + gk]) : (T)0;
+    }
+  }
+};
+template <class T, bool TB, int BN, int BK>
+struct BLoader {
+  static constexpr int N = BN * BK / kThreads;
+  static __device__ __forceinline__ void coords(int e, int& nn, int& kk) {
+    if (!TB) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+  }
+  static __device__ __forceinline__ void load(T (&r)[N], const T* __restrict__ B, int ldb, int col0, int n,
+                                              int k0, int K) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      int nn, kk;
+      coords(threadIdx.x + i * kThreads, nn, kk);
+      const int gc = col0 + nn, gk = k0 + kk;
+      r[i] = (gc < n && gk < K) ? (TB ? B[(int64_t)gc * ldb + gk] : B[(int64_t)gk * ldb + gc]) : (T)0;
+    }
+  }
+};
+
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(kThreads)
 gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
@@ -70,6 +109,8 @@ gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   static_assert(WM * WN == kThreads / 64, "four waves");
+  typedef ALoader<T, TA, BM, BK> LA;
+  typedef BLoader<T, TB, BN, BK> LB;
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
 
@@ -91,49 +132,45 @@ gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  for (int t = g.term_begin; t < g.term_end; ++t) {
-    const GemmTerm term = terms[t];
-    const T* __restrict__ A = bases.p[term.a_base] + term.a_off;
-    const T* __restrict__ B = bases.p[term.b_base] + term.b_off;
+  // chunk iterator over (term, k0); registers hold the chunk that is staged next
+  T ra[LA::N], rb[LB::N];
+  int t = g.term_begin, k0 = 0;
+  GemmTerm term;
+  if (t < g.term_end) {
+    term = terms[t];
+    LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, 0, term.k);
+    LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, 0, term.k);
+  }
+  while (t < g.term_end) {
     const T alpha = (T)term.alpha;
-    const int K = term.k;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      __syncthreads();
-      // stage alpha * op(A)[row0 .. row0+BM, k0 .. k0+BK) as As[k][m]
-      if (!TA) {
+    const int kmax = min(BK, term.k - k0);
+    __syncthreads();
 #pragma unroll
-        for (int e = tid; e < BM * BK; e += kThreads) {
-          const int kk = e % BK, mm = e / BK;
-          const int gr = row0 + mm, gk = k0 + kk;
-          As[kk][mm] = (gr < g.m && gk < K) ? alpha * A[(int64_t)gr * term.lda + gk] : (T)0;
-        }
-      } else {
+    for (int i = 0; i < LA::N; ++i) {
+      int mm, kk;
+      LA::coords(tid + i * kThreads, mm, kk);
+      As[kk][mm] = alpha * ra[i];
+    }
 #pragma unroll
-        for (int e = tid; e < BM * BK; e += kThreads) {
-          const int mm = e % BM, kk = e / BM;
-          const int gr = row0 + mm, gk = k0 + kk;
-          As[kk][mm] = (gr < g.m && gk < K) ? alpha * A[(int64_t)gk * term.lda + gr] : (T)0;
-        }
-      }
-      // stage op(B)[k0 .. k0+BK, col0 .. col0+BN) as Bs[k][n]
-      if (!TB) {
+    for (int i = 0; i < LB::N; ++i) {
+      int nn, kk;
+      LB::coords(tid + i * kThreads, nn, kk);
+      Bs[kk][nn] = rb[i];
+    }
+    __syncthreads();
+    k0 += BK;
+    if (k0 >= term.k) {
+      ++t;
+      k0 = 0;
+      if (t < g.term_end) term = terms[t];
+    }
+    if (t < g.term_end) {
+      LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, k0, term.k);
+      LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, k0, term.k);
+    }
 #pragma unroll
-        for (int e = tid; e < BN * BK; e += kThreads) {
-          const int nn = e % BN, kk = e / BN;
-          const int gc = col0 + nn, gk = k0 + kk;
-          Bs[kk][nn] = (gc < g.n && gk < K) ? B[(int64_t)gk * term.ldb + gc] : (T)0;
-        }
-      } else {
-#pragma unroll
-        for (int e = tid; e < BN * BK; e += kThreads) {
-          const int kk = e % BK, nn = e / BK;
-          const int gc = col0 + nn, gk = k0 + kk;
-          Bs[kk][nn] = (gc < g.n && gk < K) ? B[(int64_t)gc * term.ldb + gk] : (T)0;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
+    for (int kk = 0; kk < BK; kk += 4) {
+      if (kk < kmax) {
         T a[TM], b[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) a[i] = As[kk + (lane >> 4)][wm * (BM / WM) + i * 16 + (lane & 15)];
@@ -179,6 +216,8 @@ gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restri
   constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
+  typedef ALoader<float, TA, BM, BK> LA;
+  typedef BLoader<float, TB, BN, BK> LB;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
@@ -200,59 +239,67 @@ gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restri
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int t = g.term_begin; t < g.term_end; ++t) {
-    const GemmTerm term = terms[t];
-    const float* __restrict__ A = bases.p[term.a_base] + term.a_off;
-    const float* __restrict__ B = bases.p[term.b_base] + term.b_off;
+  float ra[LA::N], rb[LB::N];
+  int t = g.term_begin, k0 = 0;
+  GemmTerm term;
+  if (t < g.term_end) {
+    term = terms[t];
+    LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, 0, term.k);
+    LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, 0, term.k);
+  }
+  while (t < g.term_end) {
     const float alpha = (float)term.alpha;
-    const int K = term.k;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-      __syncthreads();
+    __syncthreads();
 #pragma unroll
-      for (int e = tid; e < BM * BK; e += kThreads) {
-        int kk, mm;
-        if (!TA) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-        const int gr = row0 + mm, gk = k0 + kk;
-        float v = 0.f;
-        if (gr < g.m && gk < K) v = alpha * (TA ? A[(int64_t)gk * term.lda + gr] : A[(int64_t)gr * term.lda + gk]);
-        const __bf16 h = (__bf16)v;
-        Ah[mm][kk] = h;
-        Al[mm][kk] = (__bf16)(v - (float)h);
-      }
+    for (int i = 0; i < LA::N; ++i) {
+      int mm, kk;
+      LA::coords(tid + i * kThreads, mm, kk);
+      const float v = alpha * ra[i];
+      const __bf16 h = (__bf16)v;
+      Ah[mm][kk] = h;
+      Al[mm][kk] = (__bf16)(v - (float)h);
+    }
 #pragma unroll
-      for (int e = tid; e < BN * BK; e += kThreads) {
-        int kk, nn;
-        if (!TB) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
-        const int gc = col0 + nn, gk = k0 + kk;
-        float v = 0.f;
-        if (gc < g.n && gk < K) v = TB ? B[(int64_t)gc * term.ldb + gk] : B[(int64_t)gk * term.ldb + gc];
-        const __bf16 h = (__bf16)v;
-        Bh[nn][kk] = h;
-        Bl[nn][kk] = (__bf16)(v - (float)h);
-      }
-      __syncthreads();
-      bf8 ah[TM], al[TM], bh[TN], bl[TN];
+    for (int i = 0; i < LB::N; ++i) {
+      int nn, kk;
+      LB::coords(tid + i * kThreads, nn, kk);
+      const float v = rb[i];
+      const __bf16 h = (__bf16)v;
+      Bh[nn][kk] = h;
+      Bl[nn][kk] = (__bf16)(v - (float)h);
+    }
+    __syncthreads();
+    k0 += BK;
+    if (k0 >= term.k) {
+      ++t;
+      k0 = 0;
+      if (t < g.term_end) term = terms[t];
+    }
+    if (t < g.term_end) {
+      LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, k0, term.k);
+      LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, k0, term.k);
+    }
+    bf8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = wm * (BM / WM) + i * 16 + (lane & 15);
-        ah[i] = *reinterpret_cast<const bf8*>(&Ah[r][8 * (lane >> 4)]);
-        al[i] = *reinterpret_cast<const bf8*>(&Al[r][8 * (lane >> 4)]);
-      }
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * (BM / WM) + i * 16 + (lane & 15);
+      ah[i] = *reinterpret_cast<const bf8*>(&Ah[r][8 * (lane >> 4)]);
+      al[i] = *reinterpret_cast<const bf8*>(&Al[r][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = wn * (BN / WN) + j * 16 + (lane & 15);
+      bh[j] = *reinterpret_cast<const bf8*>(&Bh[c][8 * (lane >> 4)]);
+      bl[j] = *reinterpret_cast<const bf8*>(&Bl[c][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const int c = wn * (BN / WN) + j * 16 + (lane & 15);
-        bh[j] = *reinterpret_cast<const bf8*>(&Bh[c][8 * (lane >> 4)]);
-        bl[j] = *reinterpret_cast<const bf8*>(&Bl[c][8 * (lane >> 4)]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    }
   }
 
   float* __restrict__ C = bases.p[g.c_base] + g.c_off;
@@ -272,8 +319,8 @@ gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restri
 }
 
 // ------------------------------------------------------------------------------------------
-// Launchers.  Tile shape 0: 64x64 (2x2 waves of 32x32); shape 1: 32x32... realised as 16x64
-// (1x4 waves of 16x16), which suits the short-row blocks of small sectors.
+// Launchers.  The tile shape (rows x cols per workgroup, wave grid) is chosen per group by the
+// planner from the block sizes; see kTileShapes in internal.h.
 // ------------------------------------------------------------------------------------------
 template <int MODE, int BM, int BN, int WM, int WN>
 static hipError_t launch_mfma_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
@@ -308,23 +355,69 @@ static hipError_t launch_bf_shape(const GemmTerm* terms, const GemmGroup* groups
   return hipGetLastError();
 }
 
+#define LCC_SHAPE_SWITCH(FN, ...)                                   \
+  switch (shape) {                                                  \
+    case 0: return FN<__VA_ARGS__ 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    case 1: return FN<__VA_ARGS__ 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    case 2: return FN<__VA_ARGS__ 64, 16, 4, 1>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    case 3: return FN<__VA_ARGS__ 32, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    case 4: return FN<__VA_ARGS__ 128, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);  \
+    case 5: return FN<__VA_ARGS__ 64, 128, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);  \
+    case 6: return FN<__VA_ARGS__ 32, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    case 7: return FN<__VA_ARGS__ 64, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    default: return hipErrorInvalidValue;                           \
+  }
+
 hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                            int n_tiles, bool ta, bool tb, int shape, const Bases<double>& b,
                            hipStream_t stream) {
-  if (shape == TILE_64x64) return launch_mfma_shape<0, 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
-  return launch_mfma_shape<0, 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+  LCC_SHAPE_SWITCH(launch_mfma_shape, 0, )
 }
 hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                            int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
                            hipStream_t stream) {
-  if (shape == TILE_64x64) return launch_mfma_shape<1, 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
-  return launch_mfma_shape<1, 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+  LCC_SHAPE_SWITCH(launch_mfma_shape, 1, )
 }
 hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                               int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
                               hipStream_t stream) {
-  if (shape == TILE_64x64) return launch_bf_shape<64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
-  return launch_bf_shape<16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);
+  LCC_SHAPE_SWITCH(launch_bf_shape, )
+}
+#undef LCC_SHAPE_SWITCH
+
+// ------------------------------------------------------------------------------------------
+// Split-K reduction of partial output tiles, in a fixed order (deterministic).
+// ------------------------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+reduce_kernel(const ReduceGroup* __restrict__ groups, const ReduceTile* __restrict__ tiles, Bases<T> bases) {
+  const ReduceTile tile = tiles[blockIdx.x];
+  const ReduceGroup g = groups[tile.group];
+  const int64_t mn = (int64_t)g.m * g.n;
+  const T* __restrict__ src = bases.p[BASE_WORK] + g.src_off;
+  T* __restrict__ dst = bases.p[BASE_Y] + g.dst_off;
+#pragma unroll
+  for (int i = 0; i < kReduceChunk / kThreads; ++i) {
+    const int64_t e = (int64_t)tile.chunk * kReduceChunk + i * kThreads + threadIdx.x;
+    if (e < mn) {
+      T s = 0;
+      for (int p = 0; p < g.parts; ++p) s += src[p * mn + e];
+      const int r = (int)(e / g.n), c = (int)(e % g.n);
+      dst[(int64_t)r * g.ldc + c] = s;
+    }
+  }
+}
+hipError_t launch_reduce_f64(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
+                             const Bases<double>& b, hipStream_t stream) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel<double>, dim3(n_tiles), dim3(kThreads), 0, stream, groups, tiles, b);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_f32(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
+                             const Bases<float>& b, hipStream_t stream) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel<float>, dim3(n_tiles), dim3(kThreads), 0, stream, groups, tiles, b);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------

@@ -94,6 +94,8 @@ struct GemmLaunch {
 
 struct Plan {
   std::vector<GemmLaunch> phase1, phase2;  // one launch per tile shape
+  DevBuf reduce_groups, reduce_tiles;      // split-K reduction of phase 2
+  int n_reduce_tiles = 0;
   double flops1 = 0, flops2 = 0;
 };
 
@@ -116,8 +118,8 @@ struct Env {
   std::vector<lcc_block_entry> layout;
   int64_t n_elements = 0;
   // device data: [L blocks | R blocks] in FP64 (+ FP32 copy), merged blocks (+ FP32 copy)
-  DevBuf env64, env32, merged64, merged32, tbuf;
-  int64_t env_elems = 0, merged_elems = 0, t_elems = 0;
+  DevBuf env64, env32, merged64, merged32, tbuf, work;
+  int64_t env_elems = 0, merged_elems = 0, t_elems = 0, work_elems = 0;
   Plan plan;
   // CG workspace
   DevBuf w64[6], w32[6];
