@@ -39,6 +39,45 @@ def shift_for(spec, env, name):
     return theta - max(0.5, 2.0 * res), f"lanczos theta={theta:.12f} res={res:.3e}, minus max(0.5, 2 res)"
 
 
+def source_digest() -> str:
+    """sha1 of the sources that determine the GEMM kernels and the plan they run."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("kernels.hip", "env.cpp", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1509_00216_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_name(precision: str, launch: dict) -> str:
+    if launch["kind"] == "reduce":
+        return "reduce_kernel<%s>" % ("double" if precision == "fp64" else "float")
+    tb = "true" if launch["phase"] == 2 else "false"
+    bm, bn = launch["tile"]
+    waves = {(64, 64): (2, 2), (16, 64): (1, 4), (64, 16): (4, 1), (32, 32): (2, 2), (128, 64): (2, 2),
+             (64, 128): (2, 2), (32, 64): (2, 2), (64, 32): (2, 2)}[(bm, bn)]
+    if precision == "bf16x3":
+        return f"gemm_bf16x3_kernel<false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
+    mode = 0 if precision == "fp64" else 1
+    return f"gemm_mfma_kernel<{mode}, false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
+
+
+def measured_traffic(kname: str, workload: str):
+    """HBM bytes per launch of `kname` from the committed PMC summary, if the kernel sources
+    have not changed since the counters were taken (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("source_sha1") != source_digest():
+        return None
+    ent = rec.get("kernels", {}).get(kname)
+    return None if ent is None else ent.get("traffic_bytes")
+
+
 def cpu_baseline(sample_seconds_target=20.0):
     """The oracle (plain numpy FP64, prefix-automaton MPO) on a bounded sample of the ab initio
     family, with the product's algorithmic flop count of the same H_eff x as the work unit."""
@@ -185,17 +224,21 @@ def main():
                 "hylleraas": info64["hylleraas"], "status": info64["status"]}
         log(f"[bench] fp64 solve: {info64}")
 
-    # --- roofline of the dominant kernel of the timed precision
-    a = applies[args.precision]
-    dom = "phase1" if a["ms_phase1"] >= a["ms_phase2"] else "phase2"
-    fdom = f1 if dom == "phase1" else f2
-    msdom = a["ms_" + dom]
+    # --- roofline of the dominant kernel launch of the timed precision (HIP events per launch)
+    xx = x64 if args.precision == "fp64" else x64.float()
+    yy = torch.empty_like(xx)
+    launches = env.profile_launches(xx, yy, args.precision, reps=args.apply_reps)
+    dom = max(launches, key=lambda r: r["ms"])
     mult = 3.0 if args.precision == "bf16x3" else 1.0
     peak = PEAK_TFLOPS["bf16" if args.precision == "bf16x3" else "fp32"]
-    achieved = mult * fdom / (msdom * 1e-3) / 1e12
+    achieved = mult * dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    kname = kernel_name(args.precision, dom)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": f"gemm_{args.precision}_{dom}",
-                "note": "bf16x3 counts the three bf16 MFMA products per flop" if mult == 3.0 else ""}
+                "traffic": measured_traffic(kname, args.workload), "kernel": kname,
+                "launch_ms": dom["ms"], "launch_flops": dom["flops"], "launch_algorithmic_bytes": dom["bytes"],
+                "launches_per_apply": len(launches),
+                "note": ("bf16x3 counts the three bf16 MFMA products per algorithmic flop" if mult == 3.0 else
+                         "achieved = the launch's algorithmic flops / its mean HIP-event duration")}
 
     out = {
         "metric": "H_eff·x GFLOP/s + local LCC solve ms at M=1000, mixed vs FP64, 1 MI355X",

@@ -70,6 +70,11 @@ void lcc_context_destroy(lcc_context ctx);
 const char* lcc_last_error(lcc_context ctx);
 /* Wait for all work queued on the context's stream. */
 lcc_status lcc_context_synchronize(lcc_context ctx);
+/* Upper bound, in bytes of FP64 data, of the intermediate (left-enlarged operator times x)
+ * that environments built afterwards on this context keep per channel chunk; larger
+ * contractions are executed chunk by chunk over the middle-bond channels (default 16 GiB).
+ * Smaller values trade launches for memory (e.g. for many environments in one batch). */
+lcc_status lcc_context_set_intermediate_limit(lcc_context ctx, int64_t bytes);
 
 /* ---------------------------------------------------------------------------------------
  * Hamiltonian (Theory section, partitioned-Hamiltonian equation, read with the usual 1/2):
@@ -164,6 +169,25 @@ lcc_status lcc_apply_heff(lcc_env env, lcc_precision precision, const void* x_de
 lcc_status lcc_env_profile_apply(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev,
                                  int32_t reps, float* ms_phase1, float* ms_phase2);
 
+/* Per-launch timing of lcc_apply_heff: every kernel launch of one application (phase-1
+ * GEMMs per tile shape, phase-2 GEMMs per tile shape, the phase-2 split-K reduction) is
+ * bracketed by HIP events on the context stream, `reps` times.  Call with out == NULL to get
+ * *count.  Synchronous. */
+typedef struct {
+  int32_t phase;    /* 1 or 2 */
+  int32_t kind;     /* 0 = grouped GEMM, 1 = split-K reduction */
+  int32_t tile_m;   /* workgroup tile rows (GEMM) */
+  int32_t tile_n;   /* workgroup tile columns (GEMM) */
+  int32_t n_tiles;  /* workgroups in the launch */
+  int32_t reserved;
+  double flops;     /* algorithmic flops of the launch (2 m n k over its block products) */
+  double bytes;     /* algorithmic bytes: operands read once + outputs written once */
+  float ms;         /* mean duration */
+  float pad;
+} lcc_launch_profile;
+lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev,
+                                    int32_t reps, int32_t* count, lcc_launch_profile* out);
+
 /* Lowest eigenvalue of H_eff by Lanczos with full re-orthogonalisation in FP64 (the DMRG
  * energy functional, Implementation section): `steps` Krylov vectors from a start vector
  * drawn by a counter-based generator from `seed`.  Returns the lowest Ritz value and the
@@ -173,19 +197,22 @@ lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, doub
 
 /* ---------------------------------------------------------------------------------------
  * Local LCC solve:  Q (H_eff - e0) Q x = Q b,  Q = 1 - v v^T (v unit norm) or Q = 1.
- * Conjugate gradients (Implementation section).  precision selects the inner operator;
- * LCC_FP64 runs plain FP64 CG; LCC_FP32 / LCC_BF16X3 run an FP64 iterative refinement whose
- * correction equations are solved by CG with the low-precision operator.  Dot products,
- * scalars, the residual r = Q b - A x of every refinement step and the energy are FP64.
+ * Conjugate gradients (Implementation section).  precision selects the operator of the
+ * iterations: LCC_FP64 runs plain FP64 CG; LCC_FP32 / LCC_BF16X3 run one CG recurrence with
+ * the low-precision operator and "reliable updates": whenever the recurrence residual has
+ * dropped by inner_tol since the last refresh, the accumulated correction is added to the
+ * FP64 solution and the true residual r = Q b - A x is recomputed with the FP64 operator
+ * (FP64 iterative refinement that keeps the search direction).  Dot products, scalars, the
+ * refreshed residuals and the energy are FP64.
  * Synchronous.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
   lcc_precision precision;
   int32_t max_iter;      /* CG iterations in total (default 1000 when <= 0) */
   double tol;            /* stop when ||Q b - A x|| <= tol ||Q b|| in FP64 (default 1e-10) */
-  double inner_tol;      /* relative tolerance of each low-precision correction solve
-                            (default 1e-6 FP32, 1e-4 BF16X3) */
-  int32_t max_outer;     /* refinement steps (default 20) */
+  double inner_tol;      /* mixed precision: residual reduction between two FP64 refreshes
+                            (default 0.1) */
+  int32_t max_outer;     /* mixed precision: maximum FP64 refreshes (default 200) */
   int32_t replace_every; /* FP64 CG: recompute r = Q b - A x every this many iterations (default 50) */
 } lcc_solve_opts;
 typedef struct {
@@ -202,6 +229,30 @@ typedef struct {
  * and the solution on return.  v_dev may be NULL. */
 lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const double* b_dev,
                                double e0, const double* v_dev, double* x_dev, lcc_solve_info* info);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched local solves (many independent two-site problems, e.g. the sites of several sweeps
+ * or several perturbation orders).  A batch merges the plans of n environments of one
+ * context: each GEMM phase of H_eff x is one launch per tile shape covering every problem,
+ * the CG scalars of all problems live on the device with per-problem active flags (converged
+ * problems skip all work), and one iteration is captured in a HIP graph and replayed.  The
+ * method per problem is the reliable-update mixed-precision CG of lcc_solve_local_lcc
+ * (opts->precision must be LCC_FP32 or LCC_BF16X3).
+ * ------------------------------------------------------------------------------------- */
+typedef struct lcc_batch_s* lcc_batch;
+/* The environments must stay alive while the batch exists.  Synchronous. */
+lcc_status lcc_batch_create(lcc_context ctx, int32_t n, const lcc_env* envs, lcc_batch* out);
+void lcc_batch_destroy(lcc_batch batch);
+/* Arrays of n device pointers (b[i], x[i] double*, length of problem i; v may be NULL or hold
+ * NULL entries) and n shifts e0[i] (host).  x[i] holds the initial guess on entry and the
+ * solution on return; infos (n entries, may be NULL) per problem.  Returns the most severe
+ * per-problem status.  Synchronous. */
+lcc_status lcc_batch_solve(lcc_batch batch, const lcc_solve_opts* opts, const double* const* b, const double* e0,
+                           const double* const* v, double* const* x, lcc_solve_info* infos);
+/* One-shot form: creates a batch of the n environments, solves, destroys it. */
+lcc_status lcc_solve_local_lcc_batched(int32_t n, const lcc_env* envs, const lcc_solve_opts* opts,
+                                       const double* const* b, const double* e0, const double* const* v,
+                                       double* const* x, lcc_solve_info* infos);
 
 #ifdef __cplusplus
 }

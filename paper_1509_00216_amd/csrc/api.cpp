@@ -100,6 +100,13 @@ lcc_status lcc_context_synchronize(lcc_context ctx) {
   });
 }
 
+lcc_status lcc_context_set_intermediate_limit(lcc_context ctx, int64_t bytes) {
+  if (!ctx) return fail(nullptr, LCC_ERR_ARG, "ctx is NULL");
+  if (bytes < 8) return fail(ctx, LCC_ERR_ARG, "limit must hold at least one element");
+  ctx->c.t_budget_elems = bytes / 8;
+  return LCC_OK;
+}
+
 lcc_status lcc_create_hamiltonian(lcc_context ctx, const lcc_ham_desc* d, lcc_hamiltonian* out) {
   if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -241,6 +248,29 @@ lcc_status lcc_env_profile_apply(lcc_env env, lcc_precision precision, const voi
   });
 }
 
+lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const void* x, void* y, int32_t reps,
+                                    int32_t* count, lcc_launch_profile* out) {
+  if (!env || !count) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    const Plan& P = env->e->plan;
+    int n = 1;
+    for (const Plan::Chunk& C : P.chunks) n += (int)(C.phase1.size() + C.phase2.size());
+    if (!out) {
+      *count = n;
+      return LCC_OK;
+    }
+    if (*count < n) throw Error{LCC_ERR_ARG, "output array too small"};
+    if (!x || !y || x == y) throw Error{LCC_ERR_ARG, "invalid buffers"};
+    if (precision != LCC_FP64 && precision != LCC_FP32 && precision != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    std::vector<lcc_launch_profile> v = profile_launches(*env->e, precision, x, y, reps);
+    for (size_t i = 0; i < v.size(); ++i) out[i] = v[i];
+    *count = (int32_t)v.size();
+    return LCC_OK;
+  });
+}
+
 lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual) {
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
   lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
@@ -263,6 +293,57 @@ lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const do
     if (opts) o = *opts;
     return solve_local(*env->e, o, b, e0, v, x, info);
   });
+}
+
+lcc_status lcc_batch_create(lcc_context ctx, int32_t n, const lcc_env* envs, lcc_batch* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    if (n < 1 || !envs) throw Error{LCC_ERR_ARG, "need at least one environment"};
+    std::vector<Env*> v;
+    for (int i = 0; i < n; ++i) {
+      if (!envs[i]) throw Error{LCC_ERR_ARG, "NULL environment"};
+      v.push_back(envs[i]->e.get());
+    }
+    std::unique_ptr<lcc_batch_s> b(new lcc_batch_s());
+    b->b = batch_create(&ctx->c, v);
+    b->ctx = &ctx->c;
+    *out = b.release();
+    return LCC_OK;
+  });
+}
+
+void lcc_batch_destroy(lcc_batch batch) {
+  if (!batch) return;
+  (void)hipSetDevice(batch->ctx->device);
+  delete batch;
+}
+
+lcc_status lcc_batch_solve(lcc_batch batch, const lcc_solve_opts* opts, const double* const* b, const double* e0,
+                           const double* const* v, double* const* x, lcc_solve_info* infos) {
+  if (!batch) return fail(nullptr, LCC_ERR_ARG, "batch is NULL");
+  lcc_context ctx = static_cast<lcc_context>(batch->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!b || !e0 || !x) throw Error{LCC_ERR_ARG, "NULL argument"};
+    check_hip(hipSetDevice(batch->ctx->device), "hipSetDevice");
+    lcc_solve_opts o{};
+    if (opts) o = *opts;
+    return batch_solve(*batch->b, o, b, e0, v, x, infos);
+  });
+}
+
+lcc_status lcc_solve_local_lcc_batched(int32_t n, const lcc_env* envs, const lcc_solve_opts* opts,
+                                       const double* const* b, const double* e0, const double* const* v,
+                                       double* const* x, lcc_solve_info* infos) {
+  if (n < 1 || !envs || !envs[0]) return fail(nullptr, LCC_ERR_ARG, "need at least one environment");
+  lcc_context ctx = static_cast<lcc_context>(envs[0]->e->ctx->handle);
+  lcc_batch batch = nullptr;
+  lcc_status st = lcc_batch_create(ctx, n, envs, &batch);
+  if (st != LCC_OK) return st;
+  st = lcc_batch_solve(batch, opts, b, e0, v, x, infos);
+  lcc_batch_destroy(batch);
+  return st;
 }
 
 }  // extern "C"

@@ -42,14 +42,6 @@ void DevBuf::alloc(size_t n) {
   bytes = n;
 }
 
-template <class T>
-void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
-  buf.alloc(v.size() * sizeof(T));
-  if (!v.empty()) check_hip(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
-  check_hip(hipStreamSynchronize(s), "upload sync");
-}
-template void upload<double>(DevBuf&, const std::vector<double>&, hipStream_t);
-template void upload<float>(DevBuf&, const std::vector<float>&, hipStream_t);
 
 namespace {
 
@@ -133,64 +125,22 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
     L.tb = tb;
     L.shape = shape;
     L.n_tiles = (int)tiles.size();
+    {
+      std::set<std::pair<int, int64_t>> seen;
+      for (const GemmGroup& g : groups) {
+        L.elems_written += (double)g.m * g.n;
+        for (int t = g.term_begin; t < g.term_end; ++t) {
+          const GemmTerm& tm = terms[t];
+          L.flops += 2.0 * g.m * (double)g.n * tm.k;
+          if (seen.insert({tm.a_base, tm.a_off}).second) L.elems_read += (double)g.m * tm.k;
+          if (seen.insert({tm.b_base, tm.b_off}).second) L.elems_read += (double)tm.k * g.n;
+        }
+      }
+    }
     upload(L.terms, terms, s);
     upload(L.groups, groups, s);
     upload(L.tiles, tiles, s);
     out.push_back(std::move(L));
-  }
-  return out;
-}
-
-// Split-K: a group whose accumulation chain is longer than `k_per_part` is cut into parts of
-// about equal total k; each part writes its own partial tile into the workspace and a
-// reduction adds the parts in order.  This keeps every CU busy when there are few output
-// blocks with long chains (phase 2 sums over every middle-bond channel).
-GemmBuilder split_k(const GemmBuilder& in, int64_t k_per_part, int max_parts, std::vector<ReduceGroup>& red,
-                    int64_t& work_elems) {
-  GemmBuilder out;
-  out.flops = in.flops;
-  for (const GemmGroup& g : in.groups) {
-    int64_t ksum = 0;
-    for (int t = g.term_begin; t < g.term_end; ++t) ksum += in.terms[t].k;
-    const int nterms = g.term_end - g.term_begin;
-    int parts = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + k_per_part - 1) / k_per_part), max_parts);
-    parts = std::min(parts, std::max(1, nterms));
-    if (parts <= 1 || g.accumulate) {
-      GemmGroup c = g;
-      c.term_begin = (int32_t)out.terms.size();
-      for (int t = g.term_begin; t < g.term_end; ++t) out.terms.push_back(in.terms[t]);
-      c.term_end = (int32_t)out.terms.size();
-      out.groups.push_back(c);
-      continue;
-    }
-    const int64_t mn = (int64_t)g.m * g.n;
-    const int64_t woff = work_elems;
-    int made = 0;
-    int t = g.term_begin;
-    int64_t acc = 0;
-    for (int p = 0; p < parts; ++p) {
-      GemmGroup c = g;
-      c.c_base = BASE_WORK;
-      c.c_off = woff + (int64_t)p * mn;
-      c.ldc = g.n;
-      c.accumulate = 0;
-      c.term_begin = (int32_t)out.terms.size();
-      const int64_t goal = (ksum * (p + 1)) / parts;
-      const int left_parts = parts - p - 1;
-      // take terms until the goal, always at least one, leaving one per remaining part
-      do {
-        acc += in.terms[t].k;
-        out.terms.push_back(in.terms[t]);
-        ++t;
-      } while (t < g.term_end && acc < goal && (g.term_end - t) > left_parts);
-      if (p == parts - 1)
-        while (t < g.term_end) { out.terms.push_back(in.terms[t]); ++t; }
-      c.term_end = (int32_t)out.terms.size();
-      out.groups.push_back(c);
-      ++made;
-    }
-    work_elems += (int64_t)made * mn;
-    red.push_back(ReduceGroup{g.c_off, woff, g.ldc, g.m, g.n, made});
   }
   return out;
 }
@@ -714,30 +664,51 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
     const int w1 = std::get<0>(kv.first);
     for (const auto& src : kv.second) ract[(size_t)w1 * nsec + col_at[{std::get<0>(src), std::get<1>(src)}].first] = 1;
   }
+  // Channels are taken in order and cut into chunks whose intermediates fit the workspace
+  // budget; each chunk reuses the same intermediate buffer (and, when small, stays in the
+  // last-level cache between its two phases).
+  const int64_t budget = std::max<int64_t>(ctx->t_budget_elems, 1);
   std::vector<int64_t> t_off((size_t)D * nsec, -1);
-  int64_t t_total = 0;
-  for (int w1 = 0; w1 < D; ++w1)
+  std::vector<int> chunk_of(D, 0);
+  int nchunks = 1;
+  int64_t used = 0, t_max = 0;
+  for (int w1 = 0; w1 < D; ++w1) {
+    int64_t need = 0;
     for (int m = 0; m < nsec; ++m) {
       if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
       auto it = sec_index.find(env->sectors[m].q + mpo.dq[mid][w1]);
       if (it == sec_index.end()) continue;
-      t_off[(size_t)w1 * nsec + m] = t_total;
-      t_total += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
+      need += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
     }
-  env->t_elems = t_total;
-  env->tbuf.alloc(sizeof(double) * std::max<int64_t>(t_total, 1));
+    if (used > 0 && used + need > budget) {
+      ++nchunks;
+      used = 0;
+    }
+    chunk_of[w1] = nchunks - 1;
+    for (int m = 0; m < nsec; ++m) {
+      if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
+      auto it = sec_index.find(env->sectors[m].q + mpo.dq[mid][w1]);
+      if (it == sec_index.end()) continue;
+      t_off[(size_t)w1 * nsec + m] = used;
+      used += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
+    }
+    t_max = std::max(t_max, used);
+  }
+  env->t_elems = t_max;
+  env->tbuf.alloc(sizeof(double) * std::max<int64_t>(t_max, 1));
 
   // ---- phase 1: T_{w1,m}[(a',s1') rows] = sum Lt^{w1}[(a',s1'),(a,s1)] X_m[(a,s1) rows]
-  GemmBuilder p1;
+  std::vector<GemmBuilder> p1(nchunks);
   for (int w1 = 0; w1 < D; ++w1)
     for (int m = 0; m < nsec; ++m) {
       const int64_t to = t_off[(size_t)w1 * nsec + m];
       if (to < 0) continue;
+      GemmBuilder& B1 = p1[chunk_of[w1]];
       const MiddleSector& S = env->sectors[m];
       const MiddleSector& Sp = env->sectors[sec_index[S.q + mpo.dq[mid][w1]]];
       for (size_t i = 0; i < Sp.rows.size(); ++i) {
         const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
-        p1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
+        B1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
         auto it = lt.find(std::make_tuple(w1, ap, sp));
         if (it == lt.end()) continue;
         for (const auto& src : it->second) {
@@ -745,17 +716,24 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
           if (ra.first != m) continue;
           const Ref& ref = std::get<2>(src);
           const int ka = bl.dim[std::get<0>(src)];
-          p1.term(ref.base, ref.off, ka, BASE_X, S.off + (int64_t)S.row_off[ra.second] * S.ncols, S.ncols, ka, ref.alpha);
+          B1.term(ref.base, ref.off, ka, BASE_X, S.off + (int64_t)S.row_off[ra.second] * S.ncols, S.ncols, ka, ref.alpha);
         }
       }
     }
   // ---- phase 2: Y_{m'}[:, (s2',b')] = sum_{w1,(s2,b)} T_{w1,m}[:, (s2,b)] Rt^{w1}[(s2',b'),(s2,b)]^T
-  GemmBuilder p2;
+  // Each output block's chain is cut at chunk boundaries and, inside a chunk, into parts of
+  // about kSplitK; parts write partial tiles that one ordered reduction adds into y.
+  std::vector<GemmBuilder> p2(nchunks);
+  std::vector<ReduceGroup> red;
+  int64_t work = 0;
+  double flops2 = 0;
   for (int mp = 0; mp < nsec; ++mp) {
     const MiddleSector& Sp = env->sectors[mp];
     for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
       const int s2p = Sp.cols[jx].first, bp = Sp.cols[jx].second;
-      p2.group(BASE_Y, Sp.off + Sp.col_off[jx], Sp.ncols, Sp.nrows, br.dim[bp], false);
+      const int gm = Sp.nrows, gn = br.dim[bp];
+      const int64_t y_off = Sp.off + Sp.col_off[jx];
+      std::vector<std::vector<GemmTerm>> per(nchunks);
       for (int w1 = 0; w1 < D; ++w1) {
         auto si = sec_index.find(Sp.q - mpo.dq[mid][w1]);
         if (si == sec_index.end()) continue;
@@ -770,27 +748,91 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
           if (ca.first != m) continue;
           const Ref& ref = std::get<2>(src);
           const int kb = br.dim[std::get<1>(src)];
-          p2.term(BASE_T, to + S.col_off[ca.second], S.ncols, ref.base, ref.off, kb, kb, ref.alpha);
+          GemmTerm t{};
+          t.a_base = BASE_T;
+          t.a_off = to + S.col_off[ca.second];
+          t.lda = S.ncols;
+          t.b_base = ref.base;
+          t.b_off = ref.off;
+          t.ldb = kb;
+          t.k = kb;
+          t.alpha = ref.alpha;
+          per[chunk_of[w1]].push_back(t);
+          flops2 += 2.0 * gm * (double)gn * kb;
         }
       }
+      struct Part { int chunk; size_t b, e; };
+      std::vector<Part> parts;
+      for (int c = 0; c < nchunks; ++c) {
+        const auto& T = per[c];
+        if (T.empty()) continue;
+        int64_t ksum = 0;
+        for (const GemmTerm& t : T) ksum += t.k;
+        int np = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + kSplitK - 1) / kSplitK), 64);
+        np = std::min<int>(np, (int)T.size());
+        size_t i = 0;
+        int64_t acc = 0;
+        for (int p = 0; p < np; ++p) {
+          const size_t b0 = i;
+          const int64_t goal = (ksum * (p + 1)) / np;
+          const size_t left = (size_t)(np - p - 1);
+          do {
+            acc += T[i].k;
+            ++i;
+          } while (i < T.size() && acc < goal && (T.size() - i) > left);
+          if (p == np - 1) i = T.size();
+          parts.push_back(Part{c, b0, i});
+        }
+      }
+      if (parts.size() <= 1) {
+        const int c = parts.empty() ? 0 : parts[0].chunk;
+        p2[c].group(BASE_Y, y_off, Sp.ncols, gm, gn, false);
+        if (!parts.empty())
+          for (size_t i = parts[0].b; i < parts[0].e; ++i) {
+            p2[c].terms.push_back(per[c][i]);
+            p2[c].groups.back().term_end = (int32_t)p2[c].terms.size();
+          }
+        continue;
+      }
+      const int64_t mn = (int64_t)gm * gn;
+      const int64_t woff = work;
+      for (size_t p = 0; p < parts.size(); ++p) {
+        GemmBuilder& B2 = p2[parts[p].chunk];
+        B2.group(BASE_WORK, woff + (int64_t)p * mn, gn, gm, gn, false);
+        for (size_t i = parts[p].b; i < parts[p].e; ++i) {
+          B2.terms.push_back(per[parts[p].chunk][i]);
+          B2.groups.back().term_end = (int32_t)B2.terms.size();
+        }
+      }
+      work += (int64_t)parts.size() * mn;
+      ReduceGroup rg{};
+      rg.dst_off = y_off;
+      rg.src_off = woff;
+      rg.ldc = Sp.ncols;
+      rg.m = gm;
+      rg.n = gn;
+      rg.parts = (int32_t)parts.size();
+      red.push_back(rg);
     }
   }
-  env->plan.flops1 = p1.flops;
-  env->plan.flops2 = p2.flops;
-  env->plan.phase1 = finalize(p1, false, false, st);
+  double flops1 = 0;
+  for (const GemmBuilder& B1 : p1) flops1 += B1.flops;
+  env->plan.flops1 = flops1;
+  env->plan.flops2 = flops2;
+  env->plan.chunks.resize(nchunks);
+  for (int c = 0; c < nchunks; ++c) {
+    env->plan.chunks[c].phase1 = finalize(p1[c], false, false, st);
+    env->plan.chunks[c].phase2 = finalize(p2[c], false, true, st);
+  }
   {
-    std::vector<ReduceGroup> red;
-    int64_t work = 0;
-    GemmBuilder p2s = split_k(p2, kSplitK, 64, red, work);
-    env->plan.phase2 = finalize(p2s, false, true, st);
-    std::vector<ReduceTile> rt;
+    std::vector<ReduceTile> rtl;
     for (size_t g = 0; g < red.size(); ++g) {
       const int64_t mn = (int64_t)red[g].m * red[g].n;
-      for (int64_t c = 0; c * kReduceChunk < mn; ++c) rt.push_back(ReduceTile{(int32_t)g, (int32_t)c});
+      for (int64_t c = 0; c * kReduceChunk < mn; ++c) rtl.push_back(ReduceTile{(int32_t)g, (int32_t)c});
     }
     upload(env->plan.reduce_groups, red, st);
-    upload(env->plan.reduce_tiles, rt, st);
-    env->plan.n_reduce_tiles = (int)rt.size();
+    upload(env->plan.reduce_tiles, rtl, st);
+    env->plan.n_reduce_tiles = (int)rtl.size();
     env->work_elems = work;
     env->work.alloc(sizeof(double) * std::max<int64_t>(work, 1));
   }
@@ -814,51 +856,61 @@ void ensure_fp32(Env& env) {
   env.have32 = true;
 }
 
-void apply_heff(Env& env, int precision, const void* x, void* y) { apply_heff_phase(env, precision, x, y, 0); }
+namespace {
+void no_callback(void*, const LaunchRef&) {}
+}  // namespace
 
-void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase) {
+void apply_heff(Env& env, int precision, const void* x, void* y) {
+  apply_heff_each(env, precision, x, y, no_callback, nullptr);
+}
+
+// Every launch of one H_eff x in order: for each channel chunk its phase-1 launches (one per
+// tile shape) then its phase-2 launches, and finally the split-K reduction into y.
+void apply_heff_each(Env& env, int precision, const void* x, void* y,
+                     void (*after_each)(void*, const LaunchRef&), void* user) {
   hipStream_t st = env.ctx->stream;
   const Plan& P = env.plan;
+  if (precision != LCC_FP64) ensure_fp32(env);
+  Bases<double> b64{};
+  Bases<float> b32{};
   if (precision == LCC_FP64) {
-    Bases<double> b{};
-    b.p[BASE_ENV] = env.env64.as<double>();
-    b.p[BASE_MERGED] = env.merged64.as<double>();
-    b.p[BASE_X] = const_cast<double*>(static_cast<const double*>(x));
-    b.p[BASE_T] = env.tbuf.as<double>();
-    b.p[BASE_Y] = static_cast<double*>(y);
-    b.p[BASE_WORK] = env.work.as<double>();
-    if (phase != 2) run_gemm64(P.phase1, b, st);
-    if (phase != 1) {
-      run_gemm64(P.phase2, b, st);
-      check_hip(launch_reduce_f64(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
-                                  P.n_reduce_tiles, b, st),
-                "reduce launch");
-    }
-    return;
+    b64.p[BASE_ENV] = env.env64.as<double>();
+    b64.p[BASE_MERGED] = env.merged64.as<double>();
+    b64.p[BASE_X] = const_cast<double*>(static_cast<const double*>(x));
+    b64.p[BASE_T] = env.tbuf.as<double>();
+    b64.p[BASE_Y] = static_cast<double*>(y);
+    b64.p[BASE_WORK] = env.work.as<double>();
+  } else {
+    b32.p[BASE_ENV] = env.env32.as<float>();
+    b32.p[BASE_MERGED] = env.merged32.as<float>();
+    b32.p[BASE_X] = const_cast<float*>(static_cast<const float*>(x));
+    b32.p[BASE_T] = env.tbuf.as<float>();
+    b32.p[BASE_Y] = static_cast<float*>(y);
+    b32.p[BASE_WORK] = env.work.as<float>();
   }
-  ensure_fp32(env);
-  Bases<float> b{};
-  b.p[BASE_ENV] = env.env32.as<float>();
-  b.p[BASE_MERGED] = env.merged32.as<float>();
-  b.p[BASE_X] = const_cast<float*>(static_cast<const float*>(x));
-  b.p[BASE_T] = env.tbuf.as<float>();
-  b.p[BASE_Y] = static_cast<float*>(y);
-  b.p[BASE_WORK] = env.work.as<float>();
-  for (int ph = 1; ph <= 2; ++ph) {
-    if (phase != 0 && phase != ph) continue;
-    for (const GemmLaunch& L : ph == 1 ? P.phase1 : P.phase2) {
-      hipError_t e = precision == LCC_FP32
-                         ? launch_gemm_f32(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
-                                           L.n_tiles, L.ta, L.tb, L.shape, b, st)
-                         : launch_gemm_bf16x3(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
-                                              L.n_tiles, L.ta, L.tb, L.shape, b, st);
-      check_hip(e, "gemm low-precision launch");
-    }
-    if (ph == 2)
-      check_hip(launch_reduce_f32(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
-                                  P.n_reduce_tiles, b, st),
-                "reduce launch");
-  }
+  for (const Plan::Chunk& C : P.chunks)
+    for (int ph = 1; ph <= 2; ++ph)
+      for (const GemmLaunch& L : ph == 1 ? C.phase1 : C.phase2) {
+        hipError_t e;
+        if (precision == LCC_FP64)
+          e = launch_gemm_f64(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(), L.n_tiles,
+                              L.ta, L.tb, L.shape, b64, st);
+        else if (precision == LCC_FP32)
+          e = launch_gemm_f32(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(), L.n_tiles,
+                              L.ta, L.tb, L.shape, b32, st);
+        else
+          e = launch_gemm_bf16x3(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
+                                 L.n_tiles, L.ta, L.tb, L.shape, b32, st);
+        check_hip(e, "gemm launch");
+        after_each(user, LaunchRef{ph, 0, &L});
+      }
+  hipError_t e = precision == LCC_FP64
+                     ? launch_reduce_f64(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
+                                         P.n_reduce_tiles, b64, st)
+                     : launch_reduce_f32(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
+                                         P.n_reduce_tiles, b32, st);
+  check_hip(e, "reduce launch");
+  after_each(user, LaunchRef{2, 1, nullptr});
 }
 
 }  // namespace lcc

@@ -71,7 +71,7 @@ struct GemmGroup {
   int32_t term_begin, term_end;
   int8_t c_base, accumulate;
   int16_t pad0;
-  int32_t pad1;
+  int32_t problem;  // index into the base-pointer table of a batched launch (0 otherwise)
 };
 struct GemmTile {
   int32_t group, tile;
@@ -96,6 +96,7 @@ struct MixTile {
 struct ReduceGroup {
   int64_t dst_off, src_off;
   int32_t ldc, m, n, parts;
+  int32_t problem, pad;
 };
 struct ReduceTile {
   int32_t group, chunk;
@@ -115,17 +116,22 @@ enum TileShape { TILE_64x64 = 0, TILE_16x64 = 1 };
 // Launchers (kernels.hip).  All asynchronous on `stream`.
 hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                            int n_tiles, bool ta, bool tb, int shape, const Bases<double>& b,
-                           hipStream_t stream);
+                           hipStream_t stream, const Bases<double>* table = nullptr,
+                           const int* active = nullptr);
 hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                            int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                           hipStream_t stream);
+                           hipStream_t stream, const Bases<float>* table = nullptr,
+                           const int* active = nullptr);
 hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                               int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                              hipStream_t stream);
+                              hipStream_t stream, const Bases<float>* table = nullptr,
+                           const int* active = nullptr);
 hipError_t launch_reduce_f64(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
-                             const Bases<double>& b, hipStream_t stream);
+                             const Bases<double>& b, hipStream_t stream, const Bases<double>* table = nullptr,
+                             const int* active = nullptr);
 hipError_t launch_reduce_f32(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
-                             const Bases<float>& b, hipStream_t stream);
+                             const Bases<float>& b, hipStream_t stream, const Bases<float>* table = nullptr,
+                             const int* active = nullptr);
 constexpr int kReduceChunk = 1024;
 hipError_t launch_mix_f64(const MixTerm* terms, const MixGroup* groups, const MixTile* tiles,
                           int n_tiles, const Bases<double>& b, hipStream_t stream);
@@ -154,4 +160,16 @@ hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 
 namespace lcc {
 hipError_t launch_random_fill_f64(double* x, int64_t n, uint64_t seed, hipStream_t s);
+
+// Segmented (batched) vector operations: block b covers arena elements [begin, end) of one problem.
+struct SegBlock {
+  int32_t problem, pad;
+  int64_t begin, end;
+};
+template <class T>
+hipError_t launch_seg_dot(const T* a, const T* b, const SegBlock* blocks, int n_blocks, const int32_t* first_block,
+                          int n_problems, double* partial, double* out, const int* mask, hipStream_t s);
+template <class TX, class TY>
+hipError_t launch_seg_axpby(const SegBlock* blocks, int n_blocks, const double* ca, double ka, const TX* x,
+                            const double* cb, double kb, TY* y, const int* mask, hipStream_t s);
 }  // namespace lcc

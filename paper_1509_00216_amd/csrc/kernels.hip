@@ -101,10 +101,11 @@ template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(kThreads)
 gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
                  const GemmTile* __restrict__ tiles, int n_tiles,
-                 Bases<typename Mfma<MODE>::T> bases) {
+                 Bases<typename Mfma<MODE>::T> bases, const Bases<typename Mfma<MODE>::T>* __restrict__ table,
+                 const int* __restrict__ active) {
   typedef typename Mfma<MODE>::T T;
   typedef typename Mfma<MODE>::Acc Acc;
-  constexpr int BK = 16;
+  constexpr int BK = 128 / (int)sizeof(T);  // one 128-byte line of a row per chunk
   constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
@@ -121,6 +122,10 @@ gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
+  if (table) {  // batched launch: per-problem operands, converged problems skipped
+    if (active && !active[g.problem]) return;
+    bases = table[g.problem];
+  }
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
 
@@ -211,7 +216,8 @@ gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(kThreads)
 gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
-                   const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases) {
+                   const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
+                   const Bases<float>* __restrict__ table, const int* __restrict__ active) {
   constexpr int BK = 32;
   constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
   constexpr int TM = BM / WM / 16;
@@ -230,6 +236,10 @@ gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restri
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
+  if (table) {  // batched launch: per-problem operands, converged problems skipped
+    if (active && !active[g.problem]) return;
+    bases = table[g.problem];
+  }
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
 
@@ -325,62 +335,64 @@ gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restri
 template <int MODE, int BM, int BN, int WM, int WN>
 static hipError_t launch_mfma_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                                     int n_tiles, bool ta, bool tb,
-                                    const Bases<typename Mfma<MODE>::T>& b, hipStream_t s) {
+                                    const Bases<typename Mfma<MODE>::T>& b, hipStream_t s,
+                                    const Bases<typename Mfma<MODE>::T>* table, const int* active) {
   if (n_tiles <= 0) return hipSuccess;
   dim3 grid(n_tiles), block(kThreads);
   if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   else
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   return hipGetLastError();
 }
 
 template <int BM, int BN, int WM, int WN>
 static hipError_t launch_bf_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                                  int n_tiles, bool ta, bool tb, const Bases<float>& b, hipStream_t s) {
+                                  int n_tiles, bool ta, bool tb, const Bases<float>& b, hipStream_t s,
+                                  const Bases<float>* table, const int* active) {
   if (n_tiles <= 0) return hipSuccess;
   dim3 grid(n_tiles), block(kThreads);
   if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   else
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b);
+    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
   return hipGetLastError();
 }
 
 #define LCC_SHAPE_SWITCH(FN, ...)                                   \
   switch (shape) {                                                  \
-    case 0: return FN<__VA_ARGS__ 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
-    case 1: return FN<__VA_ARGS__ 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
-    case 2: return FN<__VA_ARGS__ 64, 16, 4, 1>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
-    case 3: return FN<__VA_ARGS__ 32, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
-    case 4: return FN<__VA_ARGS__ 128, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);  \
-    case 5: return FN<__VA_ARGS__ 64, 128, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);  \
-    case 6: return FN<__VA_ARGS__ 32, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
-    case 7: return FN<__VA_ARGS__ 64, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream);   \
+    case 0: return FN<__VA_ARGS__ 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
+    case 1: return FN<__VA_ARGS__ 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
+    case 2: return FN<__VA_ARGS__ 64, 16, 4, 1>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
+    case 3: return FN<__VA_ARGS__ 32, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
+    case 4: return FN<__VA_ARGS__ 128, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);  \
+    case 5: return FN<__VA_ARGS__ 64, 128, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);  \
+    case 6: return FN<__VA_ARGS__ 32, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
+    case 7: return FN<__VA_ARGS__ 64, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
     default: return hipErrorInvalidValue;                           \
   }
 
 hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                            int n_tiles, bool ta, bool tb, int shape, const Bases<double>& b,
-                           hipStream_t stream) {
+                           hipStream_t stream, const Bases<double>* table, const int* active) {
   LCC_SHAPE_SWITCH(launch_mfma_shape, 0, )
 }
 hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                            int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                           hipStream_t stream) {
+                           hipStream_t stream, const Bases<float>* table, const int* active) {
   LCC_SHAPE_SWITCH(launch_mfma_shape, 1, )
 }
 hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
                               int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                              hipStream_t stream) {
+                              hipStream_t stream, const Bases<float>* table, const int* active) {
   LCC_SHAPE_SWITCH(launch_bf_shape, )
 }
 #undef LCC_SHAPE_SWITCH
@@ -390,9 +402,14 @@ hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, co
 // ------------------------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(kThreads)
-reduce_kernel(const ReduceGroup* __restrict__ groups, const ReduceTile* __restrict__ tiles, Bases<T> bases) {
+reduce_kernel(const ReduceGroup* __restrict__ groups, const ReduceTile* __restrict__ tiles, Bases<T> bases,
+              const Bases<T>* __restrict__ table, const int* __restrict__ active) {
   const ReduceTile tile = tiles[blockIdx.x];
   const ReduceGroup g = groups[tile.group];
+  if (table) {
+    if (active && !active[g.problem]) return;
+    bases = table[g.problem];
+  }
   const int64_t mn = (int64_t)g.m * g.n;
   const T* __restrict__ src = bases.p[BASE_WORK] + g.src_off;
   T* __restrict__ dst = bases.p[BASE_Y] + g.dst_off;
@@ -408,15 +425,17 @@ reduce_kernel(const ReduceGroup* __restrict__ groups, const ReduceTile* __restri
   }
 }
 hipError_t launch_reduce_f64(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
-                             const Bases<double>& b, hipStream_t stream) {
+                             const Bases<double>& b, hipStream_t stream, const Bases<double>* table,
+                             const int* active) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel<double>, dim3(n_tiles), dim3(kThreads), 0, stream, groups, tiles, b);
+  hipLaunchKernelGGL(reduce_kernel<double>, dim3(n_tiles), dim3(kThreads), 0, stream, groups, tiles, b, table, active);
   return hipGetLastError();
 }
 hipError_t launch_reduce_f32(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
-                             const Bases<float>& b, hipStream_t stream) {
+                             const Bases<float>& b, hipStream_t stream, const Bases<float>* table,
+                             const int* active) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel<float>, dim3(n_tiles), dim3(kThreads), 0, stream, groups, tiles, b);
+  hipLaunchKernelGGL(reduce_kernel<float>, dim3(n_tiles), dim3(kThreads), 0, stream, groups, tiles, b, table, active);
   return hipGetLastError();
 }
 
@@ -598,4 +617,83 @@ hipError_t launch_random_fill_f64(double* x, int64_t n, uint64_t seed, hipStream
   hipLaunchKernelGGL(random_fill_kernel, grid_for(n), dim3(kThreads), 0, s, x, n, seed);
   return hipGetLastError();
 }
+}  // namespace lcc
+
+// ------------------------------------------------------------------------------------------
+// Segmented vector operations for batched solves.  The vectors of all problems live in one
+// arena; SegBlock b covers elements [begin, end) of problem b.problem.  Per-problem scalars
+// are device arrays, so a whole CG iteration runs without the host and can be captured in a
+// graph.  mask (may be null) switches problems off.
+// ------------------------------------------------------------------------------------------
+namespace lcc {
+
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+seg_dot_partial_kernel(const T* __restrict__ a, const T* __restrict__ b, const SegBlock* __restrict__ blocks,
+                       double* __restrict__ partial, const int* __restrict__ mask) {
+  const SegBlock blk = blocks[blockIdx.x];
+  double s = 0.0;
+  if (!mask || mask[blk.problem])
+    for (int64_t i = blk.begin + threadIdx.x; i < blk.end; i += kThreads) s += (double)a[i] * (double)b[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[p] = sum of the partials of problem p, in block order (one thread per problem)
+__global__ void seg_dot_final_kernel(const double* __restrict__ partial, const int32_t* __restrict__ first_block,
+                                     int n_problems, double* __restrict__ out, const int* __restrict__ mask) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_problems || (mask && !mask[p])) return;
+  double s = 0.0;
+  for (int b = first_block[p]; b < first_block[p + 1]; ++b) s += partial[b];
+  out[p] = s;
+}
+
+template <class T>
+hipError_t launch_seg_dot(const T* a, const T* b, const SegBlock* blocks, int n_blocks, const int32_t* first_block,
+                          int n_problems, double* partial, double* out, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL(seg_dot_partial_kernel<T>, dim3(n_blocks), dim3(kThreads), 0, s, a, b, blocks, partial, mask);
+  hipLaunchKernelGGL(seg_dot_final_kernel, dim3((n_problems + 63) / 64), dim3(64), 0, s, partial, first_block,
+                     n_problems, out, mask);
+  return hipGetLastError();
+}
+template hipError_t launch_seg_dot<double>(const double*, const double*, const SegBlock*, int, const int32_t*, int,
+                                           double*, double*, const int*, hipStream_t);
+template hipError_t launch_seg_dot<float>(const float*, const float*, const SegBlock*, int, const int32_t*, int,
+                                          double*, double*, const int*, hipStream_t);
+
+// y = (ca ? ca[p] : 1) * ka * x + (cb ? cb[p] : 1) * kb * y
+template <class TX, class TY>
+__global__ void __launch_bounds__(kThreads)
+seg_axpby_kernel(const SegBlock* __restrict__ blocks, const double* __restrict__ ca, double ka,
+                 const TX* __restrict__ x, const double* __restrict__ cb, double kb, TY* __restrict__ y,
+                 const int* __restrict__ mask) {
+  const SegBlock blk = blocks[blockIdx.x];
+  if (mask && !mask[blk.problem]) return;
+  const double a = (ca ? ca[blk.problem] : 1.0) * ka;
+  const double b = (cb ? cb[blk.problem] : 1.0) * kb;
+  if (a == 0.0 && b == 0.0) {
+    for (int64_t i = blk.begin + threadIdx.x; i < blk.end; i += kThreads) y[i] = (TY)0;
+  } else if (b == 0.0) {
+    for (int64_t i = blk.begin + threadIdx.x; i < blk.end; i += kThreads) y[i] = (TY)(a * (double)x[i]);
+  } else {
+    for (int64_t i = blk.begin + threadIdx.x; i < blk.end; i += kThreads) y[i] = (TY)(a * (double)x[i] + b * (double)y[i]);
+  }
+}
+
+template <class TX, class TY>
+hipError_t launch_seg_axpby(const SegBlock* blocks, int n_blocks, const double* ca, double ka, const TX* x,
+                            const double* cb, double kb, TY* y, const int* mask, hipStream_t s) {
+  hipLaunchKernelGGL((seg_axpby_kernel<TX, TY>), dim3(n_blocks), dim3(kThreads), 0, s, blocks, ca, ka, x, cb, kb, y, mask);
+  return hipGetLastError();
+}
+template hipError_t launch_seg_axpby<double, double>(const SegBlock*, int, const double*, double, const double*,
+                                                     const double*, double, double*, const int*, hipStream_t);
+template hipError_t launch_seg_axpby<float, float>(const SegBlock*, int, const double*, double, const float*,
+                                                   const double*, double, float*, const int*, hipStream_t);
+template hipError_t launch_seg_axpby<float, double>(const SegBlock*, int, const double*, double, const float*,
+                                                    const double*, double, double*, const int*, hipStream_t);
+template hipError_t launch_seg_axpby<double, float>(const SegBlock*, int, const double*, double, const double*,
+                                                    const double*, double, float*, const int*, hipStream_t);
+
 }  // namespace lcc

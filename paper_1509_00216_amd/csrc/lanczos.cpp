@@ -116,32 +116,76 @@ void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double
   *residual = std::sqrt(dot(env, hu, hu)) / un;
 }
 
-void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2) {
-  hipStream_t st = env.ctx->stream;
-  if (reps < 1) throw Error{LCC_ERR_ARG, "reps must be >= 1"};
-  hipEvent_t e0, e1, e2;
-  check_hip(hipEventCreate(&e0), "event");
-  check_hip(hipEventCreate(&e1), "event");
-  check_hip(hipEventCreate(&e2), "event");
-  double t1 = 0, t2 = 0;
-  for (int r = 0; r < reps; ++r) {
-    check_hip(hipEventRecord(e0, st), "record");
-    apply_heff_phase(env, precision, x, y, 1);
-    check_hip(hipEventRecord(e1, st), "record");
-    apply_heff_phase(env, precision, x, y, 2);
-    check_hip(hipEventRecord(e2, st), "record");
-    check_hip(hipEventSynchronize(e2), "event sync");
-    float a = 0, b = 0;
-    check_hip(hipEventElapsedTime(&a, e0, e1), "elapsed");
-    check_hip(hipEventElapsedTime(&b, e1, e2), "elapsed");
-    t1 += a;
-    t2 += b;
+namespace {
+struct LaunchTimer {
+  hipStream_t st;
+  std::vector<hipEvent_t> events;
+  std::vector<LaunchRef> refs;
+  size_t next = 0;
+};
+void record_after(void* u, const LaunchRef& r) {
+  LaunchTimer* t = static_cast<LaunchTimer*>(u);
+  if (t->next >= t->events.size()) {
+    hipEvent_t e;
+    check_hip(hipEventCreate(&e), "event");
+    t->events.push_back(e);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  *ms1 = (float)(t1 / reps);
-  *ms2 = (float)(t2 / reps);
+  check_hip(hipEventRecord(t->events[t->next], t->st), "record");
+  if (t->refs.size() < t->events.size()) t->refs.push_back(r);
+  ++t->next;
+}
+}  // namespace
+
+std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const void* x, void* y, int reps) {
+  if (reps < 1) throw Error{LCC_ERR_ARG, "reps must be >= 1"};
+  LaunchTimer t;
+  t.st = env.ctx->stream;
+  hipEvent_t start;
+  check_hip(hipEventCreate(&start), "event");
+  std::vector<double> sum;
+  for (int r = 0; r < reps; ++r) {
+    t.next = 0;
+    check_hip(hipEventRecord(start, t.st), "record");
+    apply_heff_each(env, precision, x, y, record_after, &t);
+    check_hip(hipEventSynchronize(t.events[t.next - 1]), "sync");
+    sum.resize(t.next, 0.0);
+    for (size_t i = 0; i < t.next; ++i) {
+      float ms = 0;
+      check_hip(hipEventElapsedTime(&ms, i == 0 ? start : t.events[i - 1], t.events[i]), "elapsed");
+      sum[i] += ms;
+    }
+  }
+  const double esz = precision == LCC_FP64 ? 8.0 : 4.0;
+  std::vector<lcc_launch_profile> out;
+  for (size_t i = 0; i < t.refs.size(); ++i) {
+    lcc_launch_profile p{};
+    p.phase = t.refs[i].phase;
+    p.kind = t.refs[i].kind;
+    if (t.refs[i].gemm) {
+      const GemmLaunch& L = *t.refs[i].gemm;
+      p.tile_m = kTileShapes[L.shape][0];
+      p.tile_n = kTileShapes[L.shape][1];
+      p.n_tiles = L.n_tiles;
+      p.flops = L.flops;
+      p.bytes = (L.elems_read + L.elems_written) * esz;
+    } else {
+      p.n_tiles = env.plan.n_reduce_tiles;
+      p.bytes = (double)env.work_elems * esz + (double)env.n_elements * esz;
+    }
+    p.ms = (float)(sum[i] / reps);
+    out.push_back(p);
+  }
+  for (hipEvent_t e : t.events) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(start);
+  return out;
+}
+
+void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2) {
+  const std::vector<lcc_launch_profile> v = profile_launches(env, precision, x, y, reps);
+  double a = 0, b = 0;
+  for (const lcc_launch_profile& p : v) (p.phase == 1 ? a : b) += p.ms;
+  *ms1 = (float)a;
+  *ms2 = (float)b;
 }
 
 }  // namespace lcc

@@ -72,8 +72,8 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
   const int prec = o.precision;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
   const double tol = o.tol > 0 ? o.tol : 1e-10;
-  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : (prec == LCC_BF16X3 ? 1e-4 : 1e-6);
-  const int max_outer = o.max_outer > 0 ? o.max_outer : 20;
+  const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 0.1;
+  const int max_outer = o.max_outer > 0 ? o.max_outer : 200;
   const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
   if (prec != LCC_FP64 && prec != LCC_FP32 && prec != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
   if (!finite(e0)) throw Error{LCC_ERR_NAN, "e0 is not finite"};
@@ -154,19 +154,24 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
       check_hip(launch_convert_f64_f32(n, v, v32, st), "v32");
     }
     ops.v32 = v32;
+    // Reliable-update CG: one low-precision Krylov recurrence, with the FP64 true residual
+    // r = Q b - A x recomputed (and the accumulated correction folded into the FP64 x)
+    // whenever the recurrence residual has dropped by `inner_tol` since the last refresh.
+    // The search direction is kept across refreshes, so the iteration count stays close to
+    // FP64 CG while almost every operator product runs in low precision.  The low-precision
+    // vectors are kept in units of the last true residual norm (scale sc).
     int total_it = 0, outer = 0;
     double rnorm = residual64();
-    while (rnorm > tol * bn) {
-      if (outer >= max_outer || total_it >= max_iter) { status = LCC_NOT_CONVERGED; break; }
-      ++outer;
-      // inner: A d = r / ||r||, d0 = 0
+    if (rnorm > tol * bn) {
+      double sc = rnorm;
       check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
-      check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / rnorm, r32, st), "scale r32");
+      check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / sc, r32, st), "scale r32");
       check_hip(launch_fill_f32(d32, n, 0.0f, st), "d = 0");
       check_hip(hipMemcpyAsync(p32, r32, sizeof(float) * n, hipMemcpyDeviceToDevice, st), "p = r");
       double rr = ops.dot32(r32, r32);
-      const double r0 = std::sqrt(rr);
-      while (std::sqrt(rr) > inner_tol * r0 && total_it < max_iter) {
+      double rmax = std::sqrt(rr);
+      while (true) {
+        if (total_it >= max_iter || outer >= max_outer) { status = LCC_NOT_CONVERGED; break; }
         ops.A32(prec, p32, Ap32);
         const double pAp = ops.dot32(p32, Ap32);
         if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
@@ -174,15 +179,41 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
         const double alpha = rr / pAp;
         check_hip(launch_axpby_f32(n, alpha, p32, 1.0, d32, st), "d update");
         check_hip(launch_axpby_f32(n, -alpha, Ap32, 1.0, r32, st), "r update");
-        const double rr_new = ops.dot32(r32, r32);
+        double rr_new = ops.dot32(r32, r32);
         if (!finite(rr_new)) throw Error{LCC_ERR_NAN, "non-finite residual"};
+        ++total_it;
+        const double rn = std::sqrt(rr_new) * sc;
+        double p_scale = 1.0;
+        if (rn < inner_tol * rmax * sc || rn <= tol * bn) {
+          // refresh: x += sc d (FP64), true residual in FP64, continue in the new units
+          check_hip(launch_axpy_f32_into_f64(n, sc, d32, x, st), "x += d");
+          ops.project64(x);
+          check_hip(launch_fill_f32(d32, n, 0.0f, st), "d = 0");
+          rnorm = residual64();
+          ++outer;
+          if (rnorm <= tol * bn) break;
+          const double sc_new = rnorm;
+          check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
+          check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / sc_new, r32, st), "scale r32");
+          // beta from true residual norms; p rescaled to the new units
+          const double rr_true_old = rr * sc * sc;
+          const double rr_true_new = rnorm * rnorm;
+          const double beta = rr_true_new / rr_true_old;
+          p_scale = beta * sc / sc_new;
+          check_hip(launch_axpby_f32(n, 1.0, r32, p_scale, p32, st), "p update");
+          sc = sc_new;
+          rr = ops.dot32(r32, r32);
+          rmax = std::sqrt(rr);
+          continue;
+        }
         check_hip(launch_axpby_f32(n, 1.0, r32, rr_new / rr, p32, st), "p update");
         rr = rr_new;
-        ++total_it;
       }
-      check_hip(launch_axpy_f32_into_f64(n, rnorm, d32, x, st), "x += d");
-      ops.project64(x);
-      rnorm = residual64();
+      if (status == LCC_NOT_CONVERGED) {
+        check_hip(launch_axpy_f32_into_f64(n, sc, d32, x, st), "x += d");
+        ops.project64(x);
+        rnorm = residual64();
+      }
     }
     inf.iterations = total_it;
     inf.outer = outer;

@@ -39,10 +39,14 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+void check_hip(hipError_t e, const char* what);
 // Upload a host vector into a fresh device buffer (synchronous on `stream`).
 template <class T>
-void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t stream);
-void check_hip(hipError_t e, const char* what);
+void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
+  buf.alloc(v.size() * sizeof(T));
+  if (!v.empty()) check_hip(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+  check_hip(hipStreamSynchronize(s), "upload sync");
+}
 
 struct Context {
   void* handle = nullptr;  // the owning lcc_context_s
@@ -53,6 +57,7 @@ struct Context {
   // scratch for reductions
   DevBuf dot_partial, dot_out;
   double* host_scalar = nullptr;  // pinned
+  int64_t t_budget_elems = (int64_t)1 << 31;  // intermediate (phase-1 output) elements per environment
 };
 
 struct Bond {
@@ -89,11 +94,18 @@ struct GemmLaunch {
   bool ta = false, tb = false;
   int shape = TILE_64x64;
   int n_tiles = 0;
+  double flops = 0;          // 2 m n k over the launch's block products
+  double elems_read = 0;     // distinct operand blocks, each counted once
+  double elems_written = 0;  // output blocks
   DevBuf terms, groups, tiles;
 };
 
 struct Plan {
-  std::vector<GemmLaunch> phase1, phase2;  // one launch per tile shape
+  // channel chunks: phase 1 then phase 2 of each chunk, in order; one launch per tile shape
+  struct Chunk {
+    std::vector<GemmLaunch> phase1, phase2;
+  };
+  std::vector<Chunk> chunks;
   DevBuf reduce_groups, reduce_tiles;      // split-K reduction of phase 2
   int n_reduce_tiles = 0;
   double flops1 = 0, flops2 = 0;
@@ -137,11 +149,23 @@ struct Hamiltonian {
 Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);
 void ensure_fp32(Env& env);
 void apply_heff(Env& env, int precision, const void* x, void* y);
-// phase 0 = both, 1 = enlarged left operator into the intermediate, 2 = into y
-void apply_heff_phase(Env& env, int precision, const void* x, void* y, int phase);
+// one launch at a time: after_each(phase, kind, launch) runs after each launch is queued
+struct LaunchRef {
+  int phase, kind;
+  const GemmLaunch* gemm;  // null for the reduction
+};
+void apply_heff_each(Env& env, int precision, const void* x, void* y,
+                     void (*after_each)(void*, const LaunchRef&), void* user);
 // lanczos.cpp
 void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual);
 void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2);
+std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const void* x, void* y, int reps);
+// batch.hip
+struct Batch;
+Batch* batch_create(Context* ctx, const std::vector<Env*>& envs);
+void batch_destroy(Batch* b);
+lcc_status batch_solve(Batch& B, const lcc_solve_opts& o, const double* const* b, const double* e0,
+                       const double* const* v, double* const* x, lcc_solve_info* infos);
 // solver.cpp
 lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, double e0, const double* v,
                        double* x, lcc_solve_info* info);
@@ -156,4 +180,9 @@ struct lcc_hamiltonian_s {
 };
 struct lcc_env_s {
   std::unique_ptr<lcc::Env> e;
+};
+struct lcc_batch_s {
+  lcc::Batch* b = nullptr;
+  lcc::Context* ctx = nullptr;
+  ~lcc_batch_s() { lcc::batch_destroy(b); }
 };

@@ -24,7 +24,9 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_create_hamiltonian", "lcc_hamiltonian_destroy", "lcc_hamiltonian_bond_dims",
            "lcc_hamiltonian_channels", "lcc_hamiltonian_site_mpo", "lcc_build_environments",
            "lcc_env_destroy", "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
-           "lcc_env_profile_apply", "lcc_lowest_eigenvalue"]
+           "lcc_env_profile_apply", "lcc_lowest_eigenvalue", "lcc_env_profile_launches", "lcc_batch_create",
+           "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
+           "lcc_context_set_intermediate_limit"]
 
 
 class LccError(RuntimeError):
@@ -73,6 +75,12 @@ class SolveInfo(C.Structure):
                 ("e2", C.c_double), ("ms_total", C.c_double)]
 
 
+class LaunchProfile(C.Structure):
+    _fields_ = [("phase", C.c_int32), ("kind", C.c_int32), ("tile_m", C.c_int32), ("tile_n", C.c_int32),
+                ("n_tiles", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double), ("bytes", C.c_double),
+                ("ms", C.c_float), ("pad", C.c_float)]
+
+
 _lib = None
 
 
@@ -106,6 +114,16 @@ def library() -> C.CDLL:
                                               C.POINTER(C.c_float)]),
         "lcc_lowest_eigenvalue": (C.c_int32, [P, C.c_int32, C.c_uint64, C.POINTER(C.c_double),
                                               C.POINTER(C.c_double)]),
+        "lcc_env_profile_launches": (C.c_int32, [P, C.c_int32, P, P, C.c_int32, C.POINTER(C.c_int32),
+                                                 C.POINTER(LaunchProfile)]),
+        "lcc_batch_create": (C.c_int32, [P, C.c_int32, C.POINTER(P), C.POINTER(P)]),
+        "lcc_context_set_intermediate_limit": (C.c_int32, [P, C.c_int64]),
+        "lcc_batch_destroy": (None, [P]),
+        "lcc_batch_solve": (C.c_int32, [P, C.POINTER(SolveOpts), C.POINTER(P), C.POINTER(C.c_double), C.POINTER(P),
+                                        C.POINTER(P), C.POINTER(SolveInfo)]),
+        "lcc_solve_local_lcc_batched": (C.c_int32, [C.c_int32, C.POINTER(P), C.POINTER(SolveOpts), C.POINTER(P),
+                                                    C.POINTER(C.c_double), C.POINTER(P), C.POINTER(P),
+                                                    C.POINTER(SolveInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -164,6 +182,9 @@ class Context:
 
     def synchronize(self):
         _check(library().lcc_context_synchronize(self.handle), self.handle)
+
+    def set_intermediate_limit(self, nbytes: int):
+        _check(library().lcc_context_set_intermediate_limit(self.handle, int(nbytes)), self.handle)
 
     def create_hamiltonian(self, spec: dict, switch_bond: int = -1) -> "Hamiltonian":
         return create_hamiltonian(self, spec, switch_bond)
@@ -323,6 +344,19 @@ class Env:
                self.ctx.handle)
         return a.value, b.value
 
+    def profile_launches(self, x, y, precision: str = "fp64", reps: int = 10) -> list:
+        """Per-launch mean duration (HIP events) with the launch's algorithmic flops and bytes."""
+        dt = "fp64" if precision == "fp64" else "fp32"
+        lib = library()
+        cnt = C.c_int32(0)
+        _check(lib.lcc_env_profile_launches(self.handle, PRECISIONS[precision], None, None, 1, C.byref(cnt), None),
+               self.ctx.handle)
+        arr = (LaunchProfile * cnt.value)()
+        _check(lib.lcc_env_profile_launches(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n),
+                                            _tensor_ptr(y, dt, self.n), reps, C.byref(cnt), arr), self.ctx.handle)
+        return [{"phase": a.phase, "kind": "gemm" if a.kind == 0 else "reduce", "tile": (a.tile_m, a.tile_n),
+                 "n_tiles": a.n_tiles, "flops": a.flops, "bytes": a.bytes, "ms": a.ms} for a in arr[: cnt.value]]
+
     def lowest_eigenvalue(self, steps: int = 60, seed: int = 1):
         th, res = C.c_double(), C.c_double()
         _check(library().lcc_lowest_eigenvalue(self.handle, steps, seed, C.byref(th), C.byref(res)),
@@ -352,3 +386,51 @@ def build_environments(ctx: Context, ham: Hamiltonian, mps: dict, site: int | No
     _check(library().lcc_build_environments(ctx.handle, ham.handle, C.byref(desc), site, C.byref(out)), ctx.handle)
     del keep
     return Env(out, ctx)
+
+
+def _info_dict(code, info):
+    return {"status": STATUS[code] if code in STATUS else code, "iterations": info.iterations, "outer": info.outer,
+            "applies_fp64": info.applies_fp64, "applies_low": info.applies_low, "rel_residual": info.rel_residual,
+            "hylleraas": info.hylleraas, "e2": info.e2, "ms_total": info.ms_total}
+
+
+class Batch:
+    """lcc_batch: independent local problems solved together (merged launches, device-side
+    scalars and flags, graph-replayed iterations)."""
+
+    def __init__(self, ctx: Context, envs: list):
+        self.ctx = ctx
+        self.envs = list(envs)
+        arr = (C.c_void_p * len(envs))(*[e.handle for e in envs])
+        h = C.c_void_p()
+        _check(library().lcc_batch_create(ctx.handle, len(envs), arr, C.byref(h)), ctx.handle)
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            library().lcc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs: list, e0s: list, xs: list, vs: list | None = None, precision: str = "fp32",
+              tol: float = 1e-10, max_iter: int = 1000, inner_tol: float = 0.0, max_outer: int = 0):
+        n = len(self.envs)
+        opts = SolveOpts(PRECISIONS[precision], max_iter, tol, inner_tol, max_outer, 0)
+        P = C.c_void_p
+        barr = (P * n)(*[_tensor_ptr(b, "fp64", e.n) for b, e in zip(bs, self.envs)])
+        xarr = (P * n)(*[_tensor_ptr(x, "fp64", e.n) for x, e in zip(xs, self.envs)])
+        varr = None
+        if vs is not None:
+            varr = (P * n)(*[(_tensor_ptr(v, "fp64", e.n) if v is not None else None) for v, e in zip(vs, self.envs)])
+        e0 = (C.c_double * n)(*[float(v) for v in e0s])
+        infos = (SolveInfo * n)()
+        code = library().lcc_batch_solve(self.handle, C.byref(opts), barr, e0, varr, xarr, infos)
+        if code < 0:
+            _check(code, self.ctx.handle)
+        return STATUS[code], [_info_dict(0, i) for i in infos]
+

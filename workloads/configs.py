@@ -50,3 +50,27 @@ def lower_bound_shift(spec: dict, gamma: float = 0.5) -> float:
     n, tsz = spec["n_elec"], spec["two_sz"]
     n_up, n_dn = (n + tsz) // 2, (n - tsz) // 2
     return free_fermion_energy(spec["h"], n_up, n_dn) + spec["e_const"] - gamma
+
+
+BATCH_PARENTS = ("hubbard2d_4x4_m500", "abinitio_k24_m1000", "threeband_4x2_m2000")
+
+
+def batch_members(n: int = 64, seed: int = 1005, m_range=(128, 1500), parents=BATCH_PARENTS) -> list:
+    """(parent workload, M, seed) of n independent local problems: parents uniform over the
+    lattice / ab initio families, M uniform in m_range, per-problem seed = seed*1000 + i."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        parent = parents[int(rng.integers(len(parents)))]
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        out.append((parent, m, seed * 1000 + i))
+    return out
+
+
+def make_member(parent: str, m_max: int, seed: int, jitter_sigma: float = 0.5):
+    """A batch member: the parent's Hamiltonian and an MPS whose bond weights carry a
+    lognormal(sigma) jitter per sector, so the block histograms differ between members."""
+    factory, _, _ = WORKLOADS[parent]
+    spec = factory()
+    mps = M.random_mps(spec["n_orb"], spec["n_elec"], spec["two_sz"], m_max, seed, jitter_sigma=jitter_sigma)
+    return spec, mps
