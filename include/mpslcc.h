@@ -231,6 +231,40 @@ lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const do
                                double e0, const double* v_dev, double* x_dev, lcc_solve_info* info);
 
 /* ---------------------------------------------------------------------------------------
+ * Sweep (Implementation section: one local problem at a time, sweeping over the sites).
+ * A left-to-right sweep of two-site blocks starting at `first_site`: right environments of
+ * every bond are built once; after each local solve the two-site tensor is split by an SVD per
+ * middle-bond sector (rocSOLVER), the m_max largest singular values over all sectors are kept
+ * (ties: sector (N, 2Sz) ascending, then index), the left factor becomes the new
+ * left-canonical site tensor, the left environment is extended by it on the device, and
+ * S V^T times the next site's right-canonical tensor becomes the initial guess of the next
+ * local problem.
+ * ------------------------------------------------------------------------------------- */
+typedef struct lcc_sweep_s* lcc_sweep;
+typedef struct {
+  int32_t site;               /* left site of the block that was split */
+  int32_t kept;               /* states kept on the new bond */
+  int32_t n_singular;         /* singular values over all sectors */
+  int32_t reserved;
+  double discarded_weight;    /* sum of discarded s^2 / sum of all s^2 */
+  double largest_discarded;   /* largest discarded singular value (0 if none) */
+} lcc_sweep_info;
+/* MPS as for lcc_build_environments with the block at first_site.  Synchronous. */
+lcc_status lcc_sweep_create(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t first_site,
+                            lcc_sweep* out);
+void lcc_sweep_destroy(lcc_sweep sweep);
+/* Environment of the current block (layout, apply, solve).  Borrowed: valid until the next
+ * lcc_sweep_advance; lcc_env_destroy on it is a no-op. */
+lcc_status lcc_sweep_env(lcc_sweep sweep, lcc_env* out);
+/* Copy the initial guess of the current block into x_dev (zeros before the first advance). */
+lcc_status lcc_sweep_guess(lcc_sweep sweep, double* x_dev);
+/* Split the solved tensor x_dev (current block's layout), truncate to m_max, move one site
+ * to the right.  Fails with LCC_ERR_STATE at the last block.  Synchronous. */
+lcc_status lcc_sweep_advance(lcc_sweep sweep, const double* x_dev, int32_t m_max, lcc_sweep_info* info);
+/* Singular values of the last split, all sectors, descending: call with out == NULL for *count. */
+lcc_status lcc_sweep_singular_values(lcc_sweep sweep, int32_t* count, double* out);
+
+/* ---------------------------------------------------------------------------------------
  * Batched local solves (many independent two-site problems, e.g. the sites of several sweeps
  * or several perturbation orders).  A batch merges the plans of n environments of one
  * context: each GEMM phase of H_eff x is one launch per tile shape covering every problem,

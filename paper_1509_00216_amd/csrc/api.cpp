@@ -186,14 +186,14 @@ lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lc
     require_device(ctx);
     if (!ham || !mps) throw Error{LCC_ERR_ARG, "NULL argument"};
     std::unique_ptr<lcc_env_s> e(new lcc_env_s());
-    e->e.reset(build_env(&ctx->c, ham->h, *mps, site));
+    e->e = build_env(&ctx->c, ham->h, *mps, site);
     *out = e.release();
     return LCC_OK;
   });
 }
 
 void lcc_env_destroy(lcc_env env) {
-  if (!env) return;
+  if (!env || !env->owned) return;
   if (env->e && env->e->ctx) {
     (void)hipSetDevice(env->e->ctx->device);
     (void)hipStreamSynchronize(env->e->ctx->stream);
@@ -304,7 +304,7 @@ lcc_status lcc_batch_create(lcc_context ctx, int32_t n, const lcc_env* envs, lcc
     std::vector<Env*> v;
     for (int i = 0; i < n; ++i) {
       if (!envs[i]) throw Error{LCC_ERR_ARG, "NULL environment"};
-      v.push_back(envs[i]->e.get());
+      v.push_back(envs[i]->e);
     }
     std::unique_ptr<lcc_batch_s> b(new lcc_batch_s());
     b->b = batch_create(&ctx->c, v);
@@ -344,6 +344,71 @@ lcc_status lcc_solve_local_lcc_batched(int32_t n, const lcc_env* envs, const lcc
   st = lcc_batch_solve(batch, opts, b, e0, v, x, infos);
   lcc_batch_destroy(batch);
   return st;
+}
+
+lcc_status lcc_sweep_create(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t first_site,
+                            lcc_sweep* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    if (!ham || !mps) throw Error{LCC_ERR_ARG, "NULL argument"};
+    std::unique_ptr<lcc_sweep_s> s(new lcc_sweep_s());
+    s->s = sweep_create(&ctx->c, ham->h, *mps, first_site);
+    s->ctx = &ctx->c;
+    s->view.owned = false;
+    s->view.e = sweep_env(*s->s);
+    *out = s.release();
+    return LCC_OK;
+  });
+}
+
+void lcc_sweep_destroy(lcc_sweep sweep) {
+  if (!sweep) return;
+  (void)hipSetDevice(sweep->ctx->device);
+  (void)hipStreamSynchronize(sweep->ctx->stream);
+  delete sweep;
+}
+
+lcc_status lcc_sweep_env(lcc_sweep sweep, lcc_env* out) {
+  if (!sweep || !out) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  sweep->view.e = sweep_env(*sweep->s);
+  *out = &sweep->view;
+  return LCC_OK;
+}
+
+lcc_status lcc_sweep_guess(lcc_sweep sweep, double* x) {
+  if (!sweep || !x) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_copy_guess(*sweep->s, x);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_advance(lcc_sweep sweep, const double* x, int32_t m_max, lcc_sweep_info* info) {
+  if (!sweep || !x) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_advance(*sweep->s, x, m_max, info);
+    sweep->view.e = sweep_env(*sweep->s);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_singular_values(lcc_sweep sweep, int32_t* count, double* out) {
+  if (!sweep || !count) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  const std::vector<double>& v = sweep_singular_values(*sweep->s);
+  if (!out) {
+    *count = (int32_t)v.size();
+    return LCC_OK;
+  }
+  if (*count < (int32_t)v.size()) return fail(nullptr, LCC_ERR_ARG, "output array too small");
+  std::memcpy(out, v.data(), sizeof(double) * v.size());
+  *count = (int32_t)v.size();
+  return LCC_OK;
 }
 
 }  // extern "C"

@@ -189,17 +189,8 @@ void run_mix(const MixBuilder& mb, const Bases<double>& b, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 // MPS on the device
 // ---------------------------------------------------------------------------------------
-struct SiteBlock {
-  int l, s, r;
-  int64_t off;
-  int rows, cols;
-};
-struct DeviceMps {
-  int K = 0;
-  std::vector<Bond> bonds;
-  std::vector<std::vector<SiteBlock>> sites;
-  DevBuf data;
-};
+
+}  // namespace
 
 void load_mps(const lcc_mps_desc& d, int N, int two_sz, hipStream_t s, DeviceMps& out) {
   if (d.n_sites < 2 || !d.bond_offsets || !d.sectors || !d.block_offsets || !d.blocks)
@@ -259,7 +250,7 @@ void load_mps(const lcc_mps_desc& d, int N, int two_sz, hipStream_t s, DeviceMps
 // ---------------------------------------------------------------------------------------
 // Environment steps
 // ---------------------------------------------------------------------------------------
-inline double wcoef(const MpoEntry& e, int sp, int s) { return e.m[sp * 4 + s]; }
+static inline double wcoef(const MpoEntry& e, int sp, int s) { return e.m[sp * 4 + s]; }
 
 // L_{j+1}^{w'}[a', a] = sum_{w,s',s} W_j^{w,w'}[s',s] (A^{s'T} L_j^w A^s)[a', a]
 Environment left_step(const Environment& L, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st) {
@@ -491,8 +482,6 @@ int channel_of_kind(const Mpo& mpo, int bond, int kind) {
   return -1;
 }
 
-}  // namespace
-
 // ---------------------------------------------------------------------------------------
 // build_env: environments, enlarged operators, vector layout, and the apply plan
 // ---------------------------------------------------------------------------------------
@@ -514,13 +503,19 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
   const int w_left_id = channel_of_kind(mpo, site, 0), w_right_id = channel_of_kind(mpo, site + 2, 1);
   if (site > 0 && w_left_id >= 0) check_identity(L, w_left_id, mps.bonds[site], st, "left");
   if (site + 2 < K && w_right_id >= 0) check_identity(R, w_right_id, mps.bonds[site + 2], st, "right");
+  return make_env(ctx, mpo, site, mps.bonds[site], mps.bonds[site + 2], L, R);
+}
 
+Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
+              const Environment& L, const Environment& R) {
+  hipStream_t st = ctx->stream;
+  const int K = mpo.K;
   std::unique_ptr<Env> env(new Env());
   env->ctx = ctx;
   env->site = site;
   env->K = K;
-  env->bl = mps.bonds[site];
-  env->br = mps.bonds[site + 2];
+  env->bl = bond_l;
+  env->br = bond_r;
   const Bond& bl = env->bl;
   const Bond& br = env->br;
   const int mid = site + 1;  // MPO bond between the two sites

@@ -145,6 +145,29 @@ struct Hamiltonian {
   Mpo mpo;
 };
 
+// MPS on the device: per site the blocks (left sector, s, right sector) of one FP64 buffer.
+struct SiteBlock {
+  int l, s, r;
+  int64_t off;
+  int rows, cols;
+};
+struct DeviceMps {
+  int K = 0;
+  std::vector<Bond> bonds;
+  std::vector<std::vector<SiteBlock>> sites;
+  DevBuf data;
+};
+void load_mps(const lcc_mps_desc& d, int N, int two_sz, hipStream_t s, DeviceMps& out);
+Environment unit_env(hipStream_t st);
+// one site of the left (right) environment recursion, on the device
+Environment left_step(const Environment& L, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st);
+Environment right_step(const Environment& R, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st);
+void check_identity(const Environment& E, int w_id, const Bond& bond, hipStream_t st, const char* which);
+int channel_of_kind(const Mpo& mpo, int bond, int kind);
+// enlarged operators, vector layout and apply plan of the two-site block (site, site+1)
+Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
+              const Environment& L, const Environment& R);
+
 // env.cpp
 Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);
 void ensure_fp32(Env& env);
@@ -166,6 +189,14 @@ Batch* batch_create(Context* ctx, const std::vector<Env*>& envs);
 void batch_destroy(Batch* b);
 lcc_status batch_solve(Batch& B, const lcc_solve_opts& o, const double* const* b, const double* e0,
                        const double* const* v, double* const* x, lcc_solve_info* infos);
+// sweep.hip
+struct Sweep;
+Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int first);
+void sweep_destroy(Sweep* s);
+Env* sweep_env(Sweep& s);
+void sweep_advance(Sweep& s, const double* x, int m_max, lcc_sweep_info* info);
+void sweep_copy_guess(Sweep& s, double* x);
+const std::vector<double>& sweep_singular_values(Sweep& s);
 // solver.cpp
 lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, double e0, const double* v,
                        double* x, lcc_solve_info* info);
@@ -179,7 +210,20 @@ struct lcc_hamiltonian_s {
   lcc::Hamiltonian h;
 };
 struct lcc_env_s {
-  std::unique_ptr<lcc::Env> e;
+  lcc::Env* e = nullptr;
+  bool owned = true;  // false for the environment a sweep lends out
+  ~lcc_env_s() {
+    if (owned) delete e;
+  }
+};
+struct lcc_sweep_s {
+  lcc::Sweep* s = nullptr;
+  lcc::Context* ctx = nullptr;
+  lcc_env_s view;  // non-owning handle of the current environment
+  ~lcc_sweep_s() {
+    view.e = nullptr;
+    lcc::sweep_destroy(s);
+  }
 };
 struct lcc_batch_s {
   lcc::Batch* b = nullptr;

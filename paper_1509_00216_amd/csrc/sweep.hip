@@ -1,0 +1,314 @@
+// Left-to-right sweep of two-site local solves (Implementation section: one tensor is
+// optimised at a time, the others fixed, sweeping over the sites).
+//
+// After the local problem at (l, l+1) is solved, the two-site tensor is split per middle-bond
+// sector by an SVD (X_q = U_q S_q V_q^T), the m_max largest singular values over all sectors
+// are kept, U becomes the new left-canonical tensor of site l, the left environment is
+// extended by that site on the device, and S V^T contracted with the right-canonical tensor of
+// site l+2 is the initial guess of the next local problem at (l+1, l+2).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "state.h"
+
+namespace lcc {
+namespace {
+
+// dst[i*cols + c] = s[i] * src[i*ld + c]  (i < rows)
+__global__ void scale_rows_kernel(double* __restrict__ dst, const double* __restrict__ src, const double* __restrict__ s,
+                                  int rows, int cols, int ld) {
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / cols), c = (int)(e % cols);
+    dst[e] = s[i] * src[(int64_t)i * ld + c];
+  }
+}
+
+void check_blas(rocblas_status s, const char* what) {
+  if (s != rocblas_status_success) throw Error{LCC_ERR_HIP, std::string(what) + ": rocBLAS/rocSOLVER status " + std::to_string((int)s)};
+}
+
+}  // namespace
+
+struct Sweep {
+  Context* ctx = nullptr;
+  const Hamiltonian* ham = nullptr;
+  DeviceMps mps;
+  std::vector<Environment> R;  // R[j]: right environment at MPS bond j (j >= first + 2)
+  Environment L;
+  Bond bl;  // current left bond of the block
+  int site = 0, first = 0;
+  std::unique_ptr<Env> env;
+  DevBuf guess;      // initial guess of the current local problem (n_elements), valid if have_guess
+  bool have_guess = false;
+  std::vector<double> last_sv;  // singular values of the last split, descending
+  rocblas_handle blas = nullptr;
+  ~Sweep() {
+    if (blas) (void)rocblas_destroy_handle(blas);
+  }
+};
+
+Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int first) {
+  hipStream_t st = ctx->stream;
+  const Mpo& mpo = ham.mpo;
+  const int K = mpo.K;
+  if (md.n_sites != K) throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
+  if (first < 0 || first + 1 >= K) throw Error{LCC_ERR_ARG, "first two-site block must satisfy 0 <= site < K-1"};
+  std::unique_ptr<Sweep> S(new Sweep());
+  S->ctx = ctx;
+  S->ham = &ham;
+  S->first = S->site = first;
+  load_mps(md, ham.desc.N, ham.desc.two_sz, st, S->mps);
+  S->L = unit_env(st);
+  for (int j = 0; j < first; ++j) S->L = left_step(S->L, S->mps, j, mpo, st);
+  S->R.resize(K + 1);
+  S->R[K] = unit_env(st);
+  for (int j = K - 1; j >= first + 2; --j) S->R[j] = right_step(S->R[j + 1], S->mps, j, mpo, st);
+  const int wl = channel_of_kind(mpo, first, 0), wr = channel_of_kind(mpo, first + 2, 1);
+  if (first > 0 && wl >= 0) check_identity(S->L, wl, S->mps.bonds[first], st, "left");
+  if (first + 2 < K && wr >= 0) check_identity(S->R[first + 2], wr, S->mps.bonds[first + 2], st, "right");
+  S->bl = S->mps.bonds[first];
+  S->env.reset(make_env(ctx, mpo, first, S->bl, S->mps.bonds[first + 2], S->L, S->R[first + 2]));
+  check_blas(rocblas_create_handle(&S->blas), "rocblas_create_handle");
+  check_blas(rocblas_set_stream(S->blas, st), "rocblas_set_stream");
+  return S.release();
+}
+
+void sweep_destroy(Sweep* s) { delete s; }
+Env* sweep_env(Sweep& s) { return s.env.get(); }
+
+void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
+  hipStream_t st = S.ctx->stream;
+  const Mpo& mpo = S.ham->mpo;
+  const int K = mpo.K;
+  if (S.site + 2 >= K) throw Error{LCC_ERR_STATE, "the sweep is already at the last two-site block"};
+  if (m_max < 1) throw Error{LCC_ERR_ARG, "m_max must be >= 1"};
+  Env& E = *S.env;
+  const int nsec = (int)E.sectors.size();
+  // ---- SVD per middle sector: X_q (row-major nrows x ncols) is the column-major matrix X_q^T;
+  // its SVD X_q^T = U' S V'^T gives V'^T (column-major r x nrows) = left vectors of X_q as a
+  // row-major nrows x r matrix, and U' (column-major ncols x r) = right vectors as a
+  // row-major r x ncols matrix.
+  struct Split { int r; int64_t a_off, s_off, u_off, v_off; };
+  std::vector<Split> sp(nsec);
+  int64_t a_tot = 0, s_tot = 0, u_tot = 0, v_tot = 0;
+  for (int q = 0; q < nsec; ++q) {
+    const MiddleSector& M = E.sectors[q];
+    Split& p = sp[q];
+    p.r = std::min(M.nrows, M.ncols);
+    p.a_off = a_tot; a_tot += (int64_t)M.nrows * M.ncols;
+    p.s_off = s_tot; s_tot += p.r;
+    p.u_off = u_tot; u_tot += (int64_t)M.ncols * p.r;
+    p.v_off = v_tot; v_tot += (int64_t)p.r * M.nrows;
+  }
+  DevBuf A, Sv, U, V, Ew, inf;
+  A.alloc(sizeof(double) * std::max<int64_t>(a_tot, 1));
+  Sv.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
+  U.alloc(sizeof(double) * std::max<int64_t>(u_tot, 1));
+  V.alloc(sizeof(double) * std::max<int64_t>(v_tot, 1));
+  Ew.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
+  inf.alloc(sizeof(rocblas_int) * std::max(nsec, 1));
+  check_hip(hipMemcpyAsync(A.p, x, sizeof(double) * E.n_elements, hipMemcpyDeviceToDevice, st), "copy x");
+  for (int q = 0; q < nsec; ++q) {
+    const MiddleSector& M = E.sectors[q];
+    const Split& p = sp[q];
+    check_blas(rocsolver_dgesvd(S.blas, rocblas_svect_singular, rocblas_svect_singular, M.ncols, M.nrows,
+                                A.as<double>() + M.off, M.ncols, Sv.as<double>() + p.s_off, U.as<double>() + p.u_off,
+                                M.ncols, V.as<double>() + p.v_off, p.r, Ew.as<double>() + p.s_off,
+                                rocblas_outofplace, inf.as<rocblas_int>() + q),
+               "rocsolver_dgesvd");
+  }
+  std::vector<double> hs(s_tot);
+  std::vector<rocblas_int> hinf(nsec);
+  check_hip(hipMemcpyAsync(hs.data(), Sv.p, sizeof(double) * s_tot, hipMemcpyDeviceToHost, st), "sv copy");
+  check_hip(hipMemcpyAsync(hinf.data(), inf.p, sizeof(rocblas_int) * nsec, hipMemcpyDeviceToHost, st), "info copy");
+  check_hip(hipStreamSynchronize(st), "svd");
+  for (int q = 0; q < nsec; ++q)
+    if (hinf[q] != 0) throw Error{LCC_ERR_NAN, "SVD did not converge in a sector"};
+  // ---- global truncation: the m_max largest singular values; ties by sector (N, 2Sz), then index
+  struct Cand { double v; int q, i; };
+  std::vector<Cand> cand;
+  for (int q = 0; q < nsec; ++q)
+    for (int i = 0; i < sp[q].r; ++i) cand.push_back(Cand{hs[sp[q].s_off + i], q, i});
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+    if (a.v != b.v) return a.v > b.v;
+    if (a.q != b.q) return a.q < b.q;
+    return a.i < b.i;
+  });
+  std::vector<int> keep(nsec, 0);
+  double total = 0, kept_w = 0, largest_dropped = 0;
+  for (size_t c = 0; c < cand.size(); ++c) {
+    total += cand[c].v * cand[c].v;
+    if ((int)c < m_max && cand[c].v > 0.0) {
+      keep[cand[c].q] = std::max(keep[cand[c].q], cand[c].i + 1);
+      kept_w += cand[c].v * cand[c].v;
+    } else if (largest_dropped == 0.0) {
+      largest_dropped = cand[c].v;
+    }
+  }
+  S.last_sv.clear();
+  for (const Cand& c : cand) S.last_sv.push_back(c.v);
+  // ---- new bond l+1 and the left-canonical site tensor A_l
+  Bond nb;
+  std::vector<int> new_index(nsec, -1);
+  for (int q = 0; q < nsec; ++q)
+    if (keep[q] > 0) {
+      new_index[q] = (int)nb.q.size();
+      nb.index[E.sectors[q].q] = (int)nb.q.size();
+      nb.q.push_back(E.sectors[q].q);
+      nb.dim.push_back(keep[q]);
+    }
+  if (nb.q.empty()) throw Error{LCC_ERR_ARG, "the two-site tensor is zero"};
+  DeviceMps one;
+  one.K = K;
+  one.bonds.resize(K + 1);
+  one.bonds[S.site] = S.bl;
+  one.bonds[S.site + 1] = nb;
+  one.sites.resize(K);
+  int64_t a_site = 0;
+  std::vector<std::pair<int, int>> src;  // (sector, row) of each block
+  for (int q = 0; q < nsec; ++q) {
+    if (keep[q] == 0) continue;
+    const MiddleSector& M = E.sectors[q];
+    for (size_t i = 0; i < M.rows.size(); ++i) {
+      const int a = M.rows[i].first, s1 = M.rows[i].second;
+      SiteBlock b{a, s1, new_index[q], a_site, S.bl.dim[a], keep[q]};
+      a_site += (int64_t)b.rows * b.cols;
+      one.sites[S.site].push_back(b);
+      src.push_back({q, (int)i});
+    }
+  }
+  one.data.alloc(sizeof(double) * std::max<int64_t>(a_site, 1));
+  for (size_t k = 0; k < src.size(); ++k) {
+    const SiteBlock& b = one.sites[S.site][k];
+    const MiddleSector& M = E.sectors[src[k].first];
+    const Split& p = sp[src[k].first];
+    // rows row_off .. row_off + M_a of the row-major nrows x r left-vector matrix, first keep columns
+    check_hip(hipMemcpy2DAsync(one.data.as<double>() + b.off, sizeof(double) * b.cols,
+                               V.as<double>() + p.v_off + (int64_t)M.row_off[src[k].second] * p.r, sizeof(double) * p.r,
+                               sizeof(double) * b.cols, b.rows, hipMemcpyDeviceToDevice, st),
+              "A block copy");
+  }
+  // ---- extend the left environment by the new site tensor
+  Environment Lnew = left_step(S.L, one, S.site, mpo, st);
+  // ---- next block (l+1, l+2)
+  const int next = S.site + 1;
+  std::unique_ptr<Env> nenv(make_env(S.ctx, mpo, next, nb, S.mps.bonds[next + 2], Lnew, S.R[next + 2]));
+  // ---- next guess: rows (q, s2) x cols (s3, c) = sum_b (S V^T)_q[:, (s2, b)] B_{l+2}^{s3}[b -> c]
+  DevBuf C;
+  std::vector<int64_t> c_off(nsec, -1);
+  int64_t c_tot = 0;
+  for (int q = 0; q < nsec; ++q)
+    if (keep[q] > 0) {
+      c_off[q] = c_tot;
+      c_tot += (int64_t)keep[q] * E.sectors[q].ncols;
+    }
+  C.alloc(sizeof(double) * std::max<int64_t>(c_tot, 1));
+  for (int q = 0; q < nsec; ++q) {
+    if (keep[q] == 0) continue;
+    const MiddleSector& M = E.sectors[q];
+    const int64_t n = (int64_t)keep[q] * M.ncols;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, st, C.as<double>() + c_off[q],
+                       U.as<double>() + sp[q].u_off, Sv.as<double>() + sp[q].s_off, keep[q], M.ncols, M.ncols);
+  }
+  check_hip(hipGetLastError(), "scale rows");
+  S.guess.alloc(sizeof(double) * std::max<int64_t>(nenv->n_elements, 1));
+  check_hip(launch_fill_f64(S.guess.as<double>(), nenv->n_elements, 0.0, st), "zero guess");
+  {
+    // site l+2 tensor blocks by (left sector b, s3)
+    std::map<std::pair<int, int>, const SiteBlock*> B;
+    for (const SiteBlock& b : S.mps.sites[next + 1]) B[{b.l, b.s}] = &b;
+    // column (s2, b) offsets of each old sector
+    std::vector<GemmTerm> terms;
+    std::vector<GemmGroup> groups;
+    std::vector<GemmTile> tiles;
+    for (const lcc_block_entry& e : nenv->layout) {
+      // e.left = new sector index (q), e.s1 = s2, e.s2 = s3, e.right = c
+      int q_old = -1;
+      for (int q = 0; q < nsec; ++q)
+        if (new_index[q] == e.left) q_old = q;
+      const MiddleSector& M = E.sectors[q_old];
+      const QN qc = S.mps.bonds[next + 2].q[e.right];
+      const QN qb = qc - local_qn(e.s2);
+      const int b = S.mps.bonds[next + 1].find(qb);
+      if (b < 0) continue;
+      auto it = B.find({b, e.s2});
+      if (it == B.end()) continue;
+      int col = -1;
+      for (size_t j = 0; j < M.cols.size(); ++j)
+        if (M.cols[j].first == e.s1 && M.cols[j].second == b) col = (int)j;
+      if (col < 0) continue;
+      const SiteBlock& Bb = *it->second;
+      GemmGroup g{};
+      g.c_off = e.offset;
+      g.ldc = e.ld;
+      g.m = e.rows;
+      g.n = e.cols;
+      g.c_base = BASE_Y;
+      g.tiles_n = (g.n + 63) / 64;
+      g.term_begin = (int32_t)terms.size();
+      GemmTerm t{};
+      t.a_base = BASE_X;
+      t.a_off = c_off[q_old] + M.col_off[col];
+      t.lda = M.ncols;
+      t.b_base = BASE_MPS;
+      t.b_off = Bb.off;
+      t.ldb = Bb.cols;
+      t.k = Bb.rows;
+      t.alpha = 1.0;
+      terms.push_back(t);
+      g.term_end = (int32_t)terms.size();
+      const int gi = (int)groups.size();
+      groups.push_back(g);
+      for (int tt = 0; tt < ((g.m + 63) / 64) * g.tiles_n; ++tt) tiles.push_back(GemmTile{gi, tt});
+    }
+    if (!tiles.empty()) {
+      DevBuf dt, dg, dl;
+      upload(dt, terms, st);
+      upload(dg, groups, st);
+      upload(dl, tiles, st);
+      Bases<double> bs{};
+      bs.p[BASE_X] = C.as<double>();
+      bs.p[BASE_MPS] = S.mps.data.as<double>();
+      bs.p[BASE_Y] = S.guess.as<double>();
+      check_hip(launch_gemm_f64(dt.as<GemmTerm>(), dg.as<GemmGroup>(), dl.as<GemmTile>(), (int)tiles.size(), false,
+                                false, TILE_64x64, bs, st),
+                "guess gemm");
+      check_hip(hipStreamSynchronize(st), "guess");
+    }
+  }
+  S.have_guess = true;
+  if (info) {
+    *info = lcc_sweep_info{};
+    info->site = S.site;
+    info->kept = 0;
+    for (int q = 0; q < nsec; ++q) info->kept += keep[q];
+    info->n_singular = (int32_t)cand.size();
+    info->discarded_weight = total > 0 ? (total - kept_w) / total : 0.0;
+    info->largest_discarded = largest_dropped;
+  }
+  S.L = std::move(Lnew);
+  S.bl = nb;
+  S.env = std::move(nenv);
+  S.site = next;
+}
+
+void sweep_copy_guess(Sweep& S, double* x) {
+  hipStream_t st = S.ctx->stream;
+  if (S.have_guess)
+    check_hip(hipMemcpyAsync(x, S.guess.p, sizeof(double) * S.env->n_elements, hipMemcpyDeviceToDevice, st), "guess");
+  else
+    check_hip(launch_fill_f64(x, S.env->n_elements, 0.0, st), "zero guess");
+  check_hip(hipStreamSynchronize(st), "guess sync");
+}
+
+const std::vector<double>& sweep_singular_values(Sweep& S) { return S.last_sv; }
+
+}  // namespace lcc

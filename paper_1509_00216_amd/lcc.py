@@ -26,7 +26,8 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_env_destroy", "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
            "lcc_env_profile_apply", "lcc_lowest_eigenvalue", "lcc_env_profile_launches", "lcc_batch_create",
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
-           "lcc_context_set_intermediate_limit"]
+           "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
+           "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values"]
 
 
 class LccError(RuntimeError):
@@ -81,6 +82,11 @@ class LaunchProfile(C.Structure):
                 ("ms", C.c_float), ("pad", C.c_float)]
 
 
+class SweepInfo(C.Structure):
+    _fields_ = [("site", C.c_int32), ("kept", C.c_int32), ("n_singular", C.c_int32), ("reserved", C.c_int32),
+                ("discarded_weight", C.c_double), ("largest_discarded", C.c_double)]
+
+
 _lib = None
 
 
@@ -118,6 +124,12 @@ def library() -> C.CDLL:
                                                  C.POINTER(LaunchProfile)]),
         "lcc_batch_create": (C.c_int32, [P, C.c_int32, C.POINTER(P), C.POINTER(P)]),
         "lcc_context_set_intermediate_limit": (C.c_int32, [P, C.c_int64]),
+        "lcc_sweep_create": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
+        "lcc_sweep_destroy": (None, [P]),
+        "lcc_sweep_env": (C.c_int32, [P, C.POINTER(P)]),
+        "lcc_sweep_guess": (C.c_int32, [P, P]),
+        "lcc_sweep_advance": (C.c_int32, [P, P, C.c_int32, C.POINTER(SweepInfo)]),
+        "lcc_sweep_singular_values": (C.c_int32, [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "lcc_batch_destroy": (None, [P]),
         "lcc_batch_solve": (C.c_int32, [P, C.POINTER(SolveOpts), C.POINTER(P), C.POINTER(C.c_double), C.POINTER(P),
                                         C.POINTER(P), C.POINTER(SolveInfo)]),
@@ -433,4 +445,52 @@ class Batch:
         if code < 0:
             _check(code, self.ctx.handle)
         return STATUS[code], [_info_dict(0, i) for i in infos]
+
+
+class Sweep:
+    """lcc_sweep: left-to-right two-site sweep (SVD split, truncation, environment update)."""
+
+    def __init__(self, ctx: Context, ham: Hamiltonian, mps: dict, first_site: int):
+        self.ctx = ctx
+        desc, keep = _mps_desc(mps)
+        h = C.c_void_p()
+        _check(library().lcc_sweep_create(ctx.handle, ham.handle, C.byref(desc), first_site, C.byref(h)), ctx.handle)
+        del keep
+        self.handle = h
+        self.ham = ham  # the sweep refers to the Hamiltonian's MPO
+
+    def close(self):
+        if self.handle:
+            library().lcc_sweep_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def env(self) -> "Env":
+        """The current block's environment (borrowed; valid until the next advance)."""
+        h = C.c_void_p()
+        _check(library().lcc_sweep_env(self.handle, C.byref(h)), self.ctx.handle)
+        return Env(h, self.ctx)
+
+    def guess(self, x):
+        _check(library().lcc_sweep_guess(self.handle, C.c_void_p(x.data_ptr())), self.ctx.handle)
+
+    def advance(self, x, m_max: int) -> dict:
+        info = SweepInfo()
+        _check(library().lcc_sweep_advance(self.handle, C.c_void_p(x.data_ptr()), int(m_max), C.byref(info)),
+               self.ctx.handle)
+        return {"site": info.site, "kept": info.kept, "n_singular": info.n_singular,
+                "discarded_weight": info.discarded_weight, "largest_discarded": info.largest_discarded}
+
+    def singular_values(self) -> np.ndarray:
+        lib = library()
+        n = C.c_int32(0)
+        _check(lib.lcc_sweep_singular_values(self.handle, C.byref(n), None))
+        out = np.zeros(n.value)
+        _check(lib.lcc_sweep_singular_values(self.handle, C.byref(n), _dptr(out)))
+        return out
 
