@@ -75,6 +75,10 @@ lcc_status lcc_context_synchronize(lcc_context ctx);
  * contractions are executed chunk by chunk over the middle-bond channels (default 16 GiB).
  * Smaller values trade launches for memory (e.g. for many environments in one batch). */
 lcc_status lcc_context_set_intermediate_limit(lcc_context ctx, int64_t bytes);
+/* Text file of autotuning results (one line per block-size histogram; created / appended by
+ * lcc_env_autotune, read by environment construction).  NULL or "" disables the cache.
+ * The path is copied. */
+lcc_status lcc_context_set_tune_cache(lcc_context ctx, const char* path);
 
 /* ---------------------------------------------------------------------------------------
  * Hamiltonian (Theory section, partitioned-Hamiltonian equation, read with the usual 1/2):
@@ -182,11 +186,35 @@ typedef struct {
   int32_t reserved;
   double flops;     /* algorithmic flops of the launch (2 m n k over its block products) */
   double bytes;     /* algorithmic bytes: operands read once + outputs written once */
+  double exec_flops; /* MFMA work issued, including tile padding and the 16-wide k groups */
   float ms;         /* mean duration */
   float pad;
 } lcc_launch_profile;
 lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev,
                                     int32_t reps, int32_t* count, lcc_launch_profile* out);
+
+/* Autotuning of the H_eff x plan for the block-size histogram of this environment (bond
+ * sectors and dimensions, MPO bond dimension).  Times on the device every candidate of the
+ * planner parameters (tile_overhead in {512, 2048, 8192}: per-tile cost, in output
+ * elements, of the tile-shape choice; split_k in {1024, 2048, 4096}: accumulation length of
+ * a phase-2 split-K part) and, per GEMM launch, both kernels (term walk / packed k), with
+ * `reps` timed applications of `precision` per measurement; keeps the fastest plan and
+ * chooses the kernels of all three precisions on it.  With a tuning cache set on the
+ * context (lcc_context_set_tune_cache) the choice is appended to it, and an entry already
+ * there for this histogram is applied without timing.  Environments built later on a
+ * context with a cache use a matching entry automatically.  Synchronous; allocates two
+ * vectors of workspace.  The environment's apply results do not depend on the choice
+ * beyond rounding order. */
+typedef struct {
+  double tile_overhead;       /* chosen planner parameters */
+  int64_t split_k;
+  int32_t candidates;         /* plans timed (0 when taken from the cache) */
+  int32_t launches;           /* GEMM launches of the chosen plan */
+  int32_t packed_launches;    /* ... of which use the packed-k kernel for `precision` */
+  int32_t from_cache;         /* 1 if the entry came from the cache */
+  float ms_before, ms_after;  /* one H_eff x of `precision`, summed launch times */
+} lcc_tune_info;
+lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, lcc_tune_info* info);
 
 /* Lowest eigenvalue of H_eff by Lanczos with full re-orthogonalisation in FP64 (the DMRG
  * energy functional, Implementation section): `steps` Krylov vectors from a start vector

@@ -107,6 +107,12 @@ lcc_status lcc_context_set_intermediate_limit(lcc_context ctx, int64_t bytes) {
   return LCC_OK;
 }
 
+lcc_status lcc_context_set_tune_cache(lcc_context ctx, const char* path) {
+  if (!ctx) return fail(nullptr, LCC_ERR_ARG, "ctx is NULL");
+  ctx->c.tune_cache = path ? std::string(path) : std::string();
+  return LCC_OK;
+}
+
 lcc_status lcc_create_hamiltonian(lcc_context ctx, const lcc_ham_desc* d, lcc_hamiltonian* out) {
   if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -267,6 +273,18 @@ lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const 
     std::vector<lcc_launch_profile> v = profile_launches(*env->e, precision, x, y, reps);
     for (size_t i = 0; i < v.size(); ++i) out[i] = v[i];
     *count = (int32_t)v.size();
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, lcc_tune_info* info) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (precision != LCC_FP64 && precision != LCC_FP32 && precision != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
+    if (reps < 1 || reps > 1000) throw Error{LCC_ERR_ARG, "reps must be in [1, 1000]"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    autotune(*env->e, precision, reps, info);
     return LCC_OK;
   });
 }

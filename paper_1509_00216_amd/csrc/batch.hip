@@ -144,7 +144,12 @@ __global__ void k_count_active(const int* __restrict__ active, int n, int* __res
 struct MergedLaunch {
   bool ta = false, tb = false;
   int shape = 0, n_tiles = 0;
-  DevBuf terms, groups, tiles;
+  DevBuf terms, slots, groups, tiles;
+  bool packed[3] = {false, false, false};
+  GemmDesc desc(int precision) const {
+    return GemmDesc{terms.as<GemmTerm>(), slots.as<SlotRec>(), groups.as<GemmGroup>(), tiles.as<GemmTile>(),
+                    n_tiles, shape, ta, tb, packed[precision]};
+  }
 };
 
 template <class T>
@@ -189,46 +194,57 @@ namespace {
 void merge_phase(const std::vector<Env*>& envs, int chunk, int phase, hipStream_t st, std::vector<MergedLaunch>& out) {
   for (int shape = 0; shape < kNumTileShapes; ++shape) {
     std::vector<GemmTerm> terms;
+    std::vector<SlotRec> slots;
     std::vector<GemmGroup> groups;
     std::vector<GemmTile> tiles;
-    bool ta = false, tb = phase == 2;
+    bool ta = false, tb = phase == 2, first = true;
+    bool packed[3] = {false, false, false};
     for (size_t p = 0; p < envs.size(); ++p) {
       if (chunk >= (int)envs[p]->plan.chunks.size()) continue;
       const Plan::Chunk& C = envs[p]->plan.chunks[chunk];
       const std::vector<GemmLaunch>& Ls = phase == 1 ? C.phase1 : C.phase2;
       for (const GemmLaunch& L : Ls) {
         if (L.shape != shape) continue;
-        const size_t nt = L.terms.bytes / sizeof(GemmTerm);
         const size_t ng = L.groups.bytes / sizeof(GemmGroup);
-        auto ht = download<GemmTerm>(L.terms, nt, st);
+        auto hs = download<SlotRec>(L.slots, (size_t)L.n_slots, st);
         auto hg = download<GemmGroup>(L.groups, ng, st);
         auto hl = download<GemmTile>(L.tiles, (size_t)L.n_tiles, st);
-        const int32_t tb0 = (int32_t)terms.size(), gb0 = (int32_t)groups.size();
-        // only the real entries (buffers are padded): tiles reference groups, groups term ranges
+        const int32_t sb0 = (int32_t)slots.size(), tb0 = (int32_t)terms.size(), gb0 = (int32_t)groups.size();
+        // only the real groups (buffers are padded): the ones the tiles reference
         int32_t max_group = -1;
         for (const GemmTile& t : hl) max_group = std::max(max_group, t.group);
-        int32_t max_term = 0;
-        for (int32_t gi = 0; gi <= max_group; ++gi) max_term = std::max(max_term, hg[gi].term_end);
-        terms.insert(terms.end(), ht.begin(), ht.begin() + std::min<size_t>(ht.size(), (size_t)max_term));
+        int32_t n_terms = 0;
+        for (int32_t gi = 0; gi <= max_group; ++gi) n_terms = std::max(n_terms, hg[gi].term_end);
+        auto ht = download<GemmTerm>(L.terms, (size_t)n_terms, st);
+        terms.insert(terms.end(), ht.begin(), ht.end());
+        slots.insert(slots.end(), hs.begin(), hs.end());
         for (int32_t gi = 0; gi <= max_group; ++gi) {
           GemmGroup g = hg[gi];
+          g.slot_begin += sb0;
+          g.slot_end += sb0;
           g.term_begin += tb0;
           g.term_end += tb0;
           g.problem = (int32_t)p;
           groups.push_back(g);
         }
+        if (first)
+          for (int q = 0; q < 3; ++q) packed[q] = L.packed[q];
+        first = false;
         for (const GemmTile& t : hl) tiles.push_back(GemmTile{t.group + gb0, t.tile});
         ta = L.ta;
         tb = L.tb;
       }
     }
     if (tiles.empty()) continue;
+    if (slots.size() > (size_t)INT32_MAX) throw Error{LCC_ERR_ARG, "batched plan too large"};
     MergedLaunch M;
     M.ta = ta;
     M.tb = tb;
     M.shape = shape;
     M.n_tiles = (int)tiles.size();
+    for (int q = 0; q < 3; ++q) M.packed[q] = packed[q];
     upload(M.terms, terms, st);
+    upload(M.slots, slots, st);
     upload(M.groups, groups, st);
     upload(M.tiles, tiles, st);
     out.push_back(std::move(M));
@@ -368,14 +384,11 @@ struct Runner {
         for (const MergedLaunch& L : ph == 1 ? B.phase1[c] : B.phase2[c]) {
         hipError_t e;
         if (fp64)
-          e = launch_gemm_f64(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(), L.n_tiles,
-                              L.ta, L.tb, L.shape, d64, s, B.table64.as<Bases<double>>(), mask);
+          e = launch_gemm_f64(L.desc(LCC_FP64), d64, s, B.table64.as<Bases<double>>(), mask);
         else if (prec == LCC_FP32)
-          e = launch_gemm_f32(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(), L.n_tiles,
-                              L.ta, L.tb, L.shape, d32, s, B.table32.as<Bases<float>>(), mask);
+          e = launch_gemm_f32(L.desc(LCC_FP32), d32, s, B.table32.as<Bases<float>>(), mask);
         else
-          e = launch_gemm_bf16x3(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
-                                 L.n_tiles, L.ta, L.tb, L.shape, d32, s, B.table32.as<Bases<float>>(), mask);
+          e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), d32, s, B.table32.as<Bases<float>>(), mask);
         check_hip(e, "batched gemm");
       }
     hipError_t e = fp64 ? launch_reduce_f64(B.reduce_groups.as<ReduceGroup>(), B.reduce_tiles.as<ReduceTile>(),

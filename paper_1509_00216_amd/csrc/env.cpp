@@ -43,101 +43,118 @@ void DevBuf::alloc(size_t n) {
 }
 
 
-namespace {
-
 // ---------------------------------------------------------------------------------------
 // Grouped GEMM launch construction
 // ---------------------------------------------------------------------------------------
-struct GemmBuilder {
-  std::vector<GemmTerm> terms;
-  std::vector<GemmGroup> groups;
-  double flops = 0;
-  void group(int8_t c_base, int64_t c_off, int ldc, int m, int n, bool accumulate) {
-    GemmGroup g{};
-    g.c_off = c_off;
-    g.ldc = ldc;
-    g.m = m;
-    g.n = n;
-    g.c_base = c_base;
-    g.accumulate = accumulate ? 1 : 0;
-    g.term_begin = g.term_end = (int32_t)terms.size();
-    groups.push_back(g);
-  }
-  void term(int8_t a_base, int64_t a_off, int lda, int8_t b_base, int64_t b_off, int ldb, int k, double alpha) {
-    GemmTerm t{};
-    t.a_base = a_base;
-    t.a_off = a_off;
-    t.lda = lda;
-    t.b_base = b_base;
-    t.b_off = b_off;
-    t.ldb = ldb;
-    t.k = k;
-    t.alpha = alpha;
-    terms.push_back(t);
-    GemmGroup& g = groups.back();
-    g.term_end = (int32_t)terms.size();
-    flops += 2.0 * g.m * (double)g.n * k;
-  }
-};
+void GemmBuilder::group(int8_t c_base, int64_t c_off, int ldc, int m, int n, bool accumulate) {
+  GemmGroup g{};
+  g.c_off = c_off;
+  g.ldc = ldc;
+  g.m = m;
+  g.n = n;
+  g.c_base = c_base;
+  g.accumulate = accumulate ? 1 : 0;
+  g.term_begin = g.term_end = (int32_t)terms.size();
+  groups.push_back(g);
+}
+
+void GemmBuilder::term(int8_t a_base, int64_t a_off, int lda, int8_t b_base, int64_t b_off, int ldb, int k,
+                       double alpha) {
+  GemmTerm t{};
+  t.a_base = a_base;
+  t.a_off = a_off;
+  t.lda = lda;
+  t.b_base = b_base;
+  t.b_off = b_off;
+  t.ldb = ldb;
+  t.k = k;
+  t.alpha = alpha;
+  terms.push_back(t);
+  GemmGroup& g = groups.back();
+  g.term_end = (int32_t)terms.size();
+  flops += 2.0 * g.m * (double)g.n * k;
+}
+
+namespace {
 
 // Tile shape of a group: the one with the least padded output area plus a fixed per-tile
 // cost (staging, descriptor loads, epilogue), so tiny blocks get small tiles and large
 // blocks get large ones.
-constexpr double kTileOverhead = 2048.0;  // in output elements
-// accumulation length (sum of k over terms) above which a group is split across workgroups
-constexpr int64_t kSplitK = 2048;
-int shape_for(int m, int n) {
+int shape_for(int m, int n, double tile_overhead) {
   int best = TILE_64x64;
   double best_cost = 1e300;
   for (int s = 0; s < kNumTileShapes; ++s) {
     const int bm = kTileShapes[s][0], bn = kTileShapes[s][1];
     const double tiles = (double)((m + bm - 1) / bm) * ((n + bn - 1) / bn);
-    const double cost = tiles * (bm * (double)bn + kTileOverhead);
+    const double cost = tiles * (bm * (double)bn + tile_overhead);
     if (cost < best_cost) { best_cost = cost; best = s; }
   }
   return best;
 }
 
-std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s) {
+}  // namespace
+
+// One launch per tile shape.  Each term is cut into k-quads (SlotRec) whose A / B offsets
+// point at the quad's first k, so the kernel walks a group's terms as one packed k stream.
+std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s, double tile_overhead) {
   std::vector<GemmLaunch> out;
   for (int shape = 0; shape < kNumTileShapes; ++shape) {
     const int bm = kTileShapes[shape][0], bn = kTileShapes[shape][1];
     std::vector<GemmTerm> terms;
+    std::vector<SlotRec> slots;
     std::vector<GemmGroup> groups;
     std::vector<GemmTile> tiles;
+    GemmLaunch L;
+    std::set<std::pair<int, int64_t>> seen;
     for (const GemmGroup& g0 : b.groups) {
       if (g0.m <= 0 || g0.n <= 0) continue;
-      if (shape_for(g0.m, g0.n) != shape) continue;
+      if (shape_for(g0.m, g0.n, tile_overhead) != shape) continue;
       GemmGroup g = g0;
+      g.slot_begin = (int32_t)slots.size();
       g.term_begin = (int32_t)terms.size();
-      for (int t = g0.term_begin; t < g0.term_end; ++t) terms.push_back(b.terms[t]);
+      for (int t = g0.term_begin; t < g0.term_end; ++t) {
+        const GemmTerm& tm = b.terms[t];
+        terms.push_back(tm);
+        for (int k0 = 0; k0 < tm.k; k0 += 4) {
+          SlotRec r{};
+          r.a_off = tm.a_off + (ta ? (int64_t)k0 * tm.lda : k0);
+          r.b_off = tm.b_off + (tb ? k0 : (int64_t)k0 * tm.ldb);
+          r.lda = tm.lda;
+          r.ldb = tm.ldb;
+          r.alpha = tm.alpha;
+          r.a_base = tm.a_base;
+          r.b_base = tm.b_base;
+          r.kv = (int8_t)std::min(4, tm.k - k0);
+          slots.push_back(r);
+        }
+        L.flops += 2.0 * g.m * (double)g.n * tm.k;
+        if (seen.insert({tm.a_base, tm.a_off}).second) L.elems_read += (double)g.m * tm.k;
+        if (seen.insert({tm.b_base, tm.b_off}).second) L.elems_read += (double)tm.k * g.n;
+      }
+      if (slots.size() > (size_t)INT32_MAX) throw Error{LCC_ERR_ARG, "plan too large"};
+      g.slot_end = (int32_t)slots.size();
       g.term_end = (int32_t)terms.size();
       g.tiles_n = (g.n + bn - 1) / bn;
       const int tiles_m = (g.m + bm - 1) / bm;
       const int gi = (int)groups.size();
       groups.push_back(g);
       for (int t = 0; t < tiles_m * g.tiles_n; ++t) tiles.push_back(GemmTile{gi, t});
+      const int64_t kpad = ((int64_t)(g.slot_end - g.slot_begin) * 4 + 15) / 16 * 16;
+      L.exec_flops += 2.0 * tiles_m * g.tiles_n * (double)bm * bn * kpad;
+      L.elems_written += (double)g.m * g.n;
     }
     if (tiles.empty()) continue;
     if (tiles.size() > (size_t)INT32_MAX) throw Error{LCC_ERR_ARG, "plan too large"};
-    GemmLaunch L;
     L.ta = ta;
     L.tb = tb;
     L.shape = shape;
     L.n_tiles = (int)tiles.size();
-    {
-      std::set<std::pair<int, int64_t>> seen;
-      for (const GemmGroup& g : groups) {
-        L.elems_written += (double)g.m * g.n;
-        for (int t = g.term_begin; t < g.term_end; ++t) {
-          const GemmTerm& tm = terms[t];
-          L.flops += 2.0 * g.m * (double)g.n * tm.k;
-          if (seen.insert({tm.a_base, tm.a_off}).second) L.elems_read += (double)g.m * tm.k;
-          if (seen.insert({tm.b_base, tm.b_off}).second) L.elems_read += (double)tm.k * g.n;
-        }
-      }
-    }
+    L.n_slots = (int64_t)slots.size();
+    // small tiles stage little per chunk: packing short terms into shared chunks pays there
+    const bool small = bm * bn <= 1024;
+    for (int p = 0; p < 3; ++p) L.packed[p] = small;
     upload(L.terms, terms, s);
+    upload(L.slots, slots, s);
     upload(L.groups, groups, s);
     upload(L.tiles, tiles, s);
     out.push_back(std::move(L));
@@ -147,10 +164,10 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
 
 void run_gemm64(const std::vector<GemmLaunch>& Ls, const Bases<double>& b, hipStream_t s) {
   for (const GemmLaunch& L : Ls)
-    check_hip(launch_gemm_f64(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
-                              L.n_tiles, L.ta, L.tb, L.shape, b, s),
-              "gemm f64 launch");
+    check_hip(launch_gemm_f64(L.desc(LCC_FP64), b, s), "gemm f64 launch");
 }
+
+namespace {
 
 struct MixBuilder {
   std::vector<MixTerm> terms;
@@ -506,147 +523,23 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
   return make_env(ctx, mpo, site, mps.bonds[site], mps.bonds[site + 2], L, R);
 }
 
-Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
-              const Environment& L, const Environment& R) {
+// The contraction plan of an environment for given planner parameters: channel chunks and
+// the intermediate layout, the phase-1 and phase-2 grouped GEMMs, the split-K reduction and
+// the workspaces.  Replaces any previous plan.
+void plan_env(Env& E, const PlanParams& pp) {
+  Env* env = &E;
+  Context* ctx = E.ctx;
   hipStream_t st = ctx->stream;
-  const int K = mpo.K;
-  std::unique_ptr<Env> env(new Env());
-  env->ctx = ctx;
-  env->site = site;
-  env->K = K;
-  env->bl = bond_l;
-  env->br = bond_r;
-  const Bond& bl = env->bl;
-  const Bond& br = env->br;
-  const int mid = site + 1;  // MPO bond between the two sites
-  env->D_mid = (int)mpo.dq[mid].size();
-
-  // ---- middle-bond sectors and the vector layout
-  std::map<QN, MiddleSector> secs;
-  for (size_t a = 0; a < bl.q.size(); ++a)
-    for (int s1 = 0; s1 < 4; ++s1) secs[bl.q[a] + local_qn(s1)].rows.push_back({(int)a, s1});
-  for (int s2 = 0; s2 < 4; ++s2)
-    for (size_t b = 0; b < br.q.size(); ++b) {
-      auto it = secs.find(br.q[b] - local_qn(s2));
-      if (it != secs.end()) it->second.cols.push_back({s2, (int)b});
-    }
-  std::map<QN, int> sec_index;
-  for (auto& kv : secs) {
-    MiddleSector& m = kv.second;
-    if (m.rows.empty() || m.cols.empty()) continue;
-    m.q = kv.first;
-    for (auto& r : m.rows) { m.row_off.push_back(m.nrows); m.nrows += bl.dim[r.first]; }
-    for (auto& c : m.cols) { m.col_off.push_back(m.ncols); m.ncols += br.dim[c.second]; }
-    m.off = env->n_elements;
-    env->n_elements += (int64_t)m.nrows * m.ncols;
-    sec_index[m.q] = (int)env->sectors.size();
-    env->sectors.push_back(m);
-  }
-  for (const MiddleSector& m : env->sectors)
-    for (size_t i = 0; i < m.rows.size(); ++i)
-      for (size_t jx = 0; jx < m.cols.size(); ++jx) {
-        lcc_block_entry e;
-        e.left = m.rows[i].first;
-        e.s1 = m.rows[i].second;
-        e.s2 = m.cols[jx].first;
-        e.right = m.cols[jx].second;
-        e.offset = m.off + (int64_t)m.row_off[i] * m.ncols + m.col_off[jx];
-        e.ld = m.ncols;
-        e.rows = bl.dim[e.left];
-        e.cols = br.dim[e.right];
-        env->layout.push_back(e);
-      }
-  // row / column lookup: (a, s1) -> (sector, row index); (s2, b) -> (sector, col index)
-  std::map<std::pair<int, int>, std::pair<int, int>> row_at, col_at;
-  for (size_t m = 0; m < env->sectors.size(); ++m) {
-    for (size_t i = 0; i < env->sectors[m].rows.size(); ++i) row_at[env->sectors[m].rows[i]] = {(int)m, (int)i};
-    for (size_t i = 0; i < env->sectors[m].cols.size(); ++i) col_at[env->sectors[m].cols[i]] = {(int)m, (int)i};
-  }
-
-  // ---- environment data on the device: [L | R]
-  env->env_elems = L.size + R.size;
-  env->env64.alloc(sizeof(double) * std::max<int64_t>(env->env_elems, 1));
-  check_hip(hipMemcpyAsync(env->env64.p, L.data.p, sizeof(double) * L.size, hipMemcpyDeviceToDevice, st), "env copy");
-  check_hip(hipMemcpyAsync(env->env64.as<double>() + L.size, R.data.p, sizeof(double) * R.size, hipMemcpyDeviceToDevice, st),
-            "env copy");
-  const int64_t r_base = L.size;
-
-  // ---- enlarged operators.  A reference is (base, offset, coefficient).
-  struct Ref { int8_t base; int64_t off; double alpha; };
-  // Lt: key (w1, row (a',s1'), src row (a,s1)) -> contributions (L block, coef)
-  std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> lt_terms;
-  std::vector<std::vector<int>> L_by_w(mpo.dq[site].size());
-  for (size_t i = 0; i < L.blocks.size(); ++i) L_by_w[L.blocks[i].w].push_back((int)i);
-  for (const MpoEntry& e : mpo.W[site])
-    for (int bi : L_by_w[e.win]) {
-      const EnvBlock& lb = L.blocks[bi];
-      for (int sp = 0; sp < 4; ++sp)
-        for (int s = 0; s < 4; ++s) {
-          const double c = e.m[sp * 4 + s];
-          if (c == 0.0) continue;
-          if (!row_at.count({lb.r, sp}) || !row_at.count({lb.c, s})) continue;
-          lt_terms[std::make_tuple(e.wout, lb.r, sp, lb.c, s)].push_back({bi, c});
-        }
-    }
-  std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> rt_terms;
-  std::vector<std::vector<int>> R_by_w(mpo.dq[site + 2].size());
-  for (size_t i = 0; i < R.blocks.size(); ++i) R_by_w[R.blocks[i].w].push_back((int)i);
-  for (const MpoEntry& e : mpo.W[site + 1])
-    for (int bi : R_by_w[e.wout]) {
-      const EnvBlock& rb = R.blocks[bi];
-      for (int sp = 0; sp < 4; ++sp)
-        for (int s = 0; s < 4; ++s) {
-          const double c = e.m[sp * 4 + s];
-          if (c == 0.0) continue;
-          if (!col_at.count({sp, rb.r}) || !col_at.count({s, rb.c})) continue;
-          rt_terms[std::make_tuple(e.win, sp, rb.r, s, rb.c)].push_back({bi, c});
-        }
-    }
-  // references, merging multi-term entries
-  MixBuilder merge;
-  int64_t merged = 0;
-  // Lt index: (w1, a', s1') -> list of (a, s1, ref)
-  std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, Ref>>> lt;
-  for (const auto& kv : lt_terms) {
-    int w1, ap, sp, a, s;
-    std::tie(w1, ap, sp, a, s) = kv.first;
-    Ref ref;
-    if (kv.second.size() == 1) {
-      ref = Ref{BASE_ENV, L.blocks[kv.second[0].first].off, kv.second[0].second};
-    } else {
-      const EnvBlock& b0 = L.blocks[kv.second[0].first];
-      merge.group(BASE_MERGED, merged, b0.rows * b0.cols, BASE_ENV);
-      for (const auto& c : kv.second) merge.term(L.blocks[c.first].off, c.second);
-      ref = Ref{BASE_MERGED, merged, 1.0};
-      merged += (int64_t)b0.rows * b0.cols;
-    }
-    lt[std::make_tuple(w1, ap, sp)].push_back(std::make_tuple(a, s, ref));
-  }
-  std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, Ref>>> rt;  // (w1, s2', b') -> (s2, b, ref)
-  for (const auto& kv : rt_terms) {
-    int w1, sp, bp, s, b;
-    std::tie(w1, sp, bp, s, b) = kv.first;
-    Ref ref;
-    if (kv.second.size() == 1) {
-      ref = Ref{BASE_ENV, r_base + R.blocks[kv.second[0].first].off, kv.second[0].second};
-    } else {
-      const EnvBlock& b0 = R.blocks[kv.second[0].first];
-      merge.group(BASE_MERGED, merged, b0.rows * b0.cols, BASE_ENV);
-      for (const auto& c : kv.second) merge.term(r_base + R.blocks[c.first].off, c.second);
-      ref = Ref{BASE_MERGED, merged, 1.0};
-      merged += (int64_t)b0.rows * b0.cols;
-    }
-    rt[std::make_tuple(w1, sp, bp)].push_back(std::make_tuple(s, b, ref));
-  }
-  env->merged_elems = merged;
-  env->merged64.alloc(sizeof(double) * std::max<int64_t>(merged, 1));
-  {
-    Bases<double> b{};
-    b.p[BASE_ENV] = env->env64.as<double>();
-    b.p[BASE_MERGED] = env->merged64.as<double>();
-    run_mix(merge, b, st);
-  }
-
+  const Bond& bl = E.bl;
+  const Bond& br = E.br;
+  auto& sec_index = E.in.sec_index;
+  auto& row_at = E.in.row_at;
+  auto& col_at = E.in.col_at;
+  auto& lt = E.in.lt;
+  auto& rt = E.in.rt;
+  const std::vector<QN>& dq_mid = E.in.dq_mid;
+  E.params = pp;
+  E.plan = Plan();
   // ---- active (w1, source sector) pairs and the intermediate layout
   const int D = env->D_mid;
   const int nsec = (int)env->sectors.size();
@@ -671,7 +564,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
     int64_t need = 0;
     for (int m = 0; m < nsec; ++m) {
       if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
-      auto it = sec_index.find(env->sectors[m].q + mpo.dq[mid][w1]);
+      auto it = sec_index.find(env->sectors[m].q + dq_mid[w1]);
       if (it == sec_index.end()) continue;
       need += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
     }
@@ -682,7 +575,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
     chunk_of[w1] = nchunks - 1;
     for (int m = 0; m < nsec; ++m) {
       if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
-      auto it = sec_index.find(env->sectors[m].q + mpo.dq[mid][w1]);
+      auto it = sec_index.find(env->sectors[m].q + dq_mid[w1]);
       if (it == sec_index.end()) continue;
       t_off[(size_t)w1 * nsec + m] = used;
       used += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
@@ -700,7 +593,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
       if (to < 0) continue;
       GemmBuilder& B1 = p1[chunk_of[w1]];
       const MiddleSector& S = env->sectors[m];
-      const MiddleSector& Sp = env->sectors[sec_index[S.q + mpo.dq[mid][w1]]];
+      const MiddleSector& Sp = env->sectors[sec_index[S.q + dq_mid[w1]]];
       for (size_t i = 0; i < Sp.rows.size(); ++i) {
         const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
         B1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
@@ -709,7 +602,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         for (const auto& src : it->second) {
           const auto ra = row_at[{std::get<0>(src), std::get<1>(src)}];
           if (ra.first != m) continue;
-          const Ref& ref = std::get<2>(src);
+          const OperandRef& ref = std::get<2>(src);
           const int ka = bl.dim[std::get<0>(src)];
           B1.term(ref.base, ref.off, ka, BASE_X, S.off + (int64_t)S.row_off[ra.second] * S.ncols, S.ncols, ka, ref.alpha);
         }
@@ -717,7 +610,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
     }
   // ---- phase 2: Y_{m'}[:, (s2',b')] = sum_{w1,(s2,b)} T_{w1,m}[:, (s2,b)] Rt^{w1}[(s2',b'),(s2,b)]^T
   // Each output block's chain is cut at chunk boundaries and, inside a chunk, into parts of
-  // about kSplitK; parts write partial tiles that one ordered reduction adds into y.
+  // about pp.split_k; parts write partial tiles that one ordered reduction adds into y.
   std::vector<GemmBuilder> p2(nchunks);
   std::vector<ReduceGroup> red;
   int64_t work = 0;
@@ -730,7 +623,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
       const int64_t y_off = Sp.off + Sp.col_off[jx];
       std::vector<std::vector<GemmTerm>> per(nchunks);
       for (int w1 = 0; w1 < D; ++w1) {
-        auto si = sec_index.find(Sp.q - mpo.dq[mid][w1]);
+        auto si = sec_index.find(Sp.q - dq_mid[w1]);
         if (si == sec_index.end()) continue;
         const int m = si->second;
         const int64_t to = t_off[(size_t)w1 * nsec + m];
@@ -741,7 +634,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         for (const auto& src : it->second) {
           const auto ca = col_at[{std::get<0>(src), std::get<1>(src)}];
           if (ca.first != m) continue;
-          const Ref& ref = std::get<2>(src);
+          const OperandRef& ref = std::get<2>(src);
           const int kb = br.dim[std::get<1>(src)];
           GemmTerm t{};
           t.a_base = BASE_T;
@@ -763,7 +656,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         if (T.empty()) continue;
         int64_t ksum = 0;
         for (const GemmTerm& t : T) ksum += t.k;
-        int np = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + kSplitK - 1) / kSplitK), 64);
+        int np = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + pp.split_k - 1) / pp.split_k), 64);
         np = std::min<int>(np, (int)T.size());
         size_t i = 0;
         int64_t acc = 0;
@@ -816,8 +709,8 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
   env->plan.flops2 = flops2;
   env->plan.chunks.resize(nchunks);
   for (int c = 0; c < nchunks; ++c) {
-    env->plan.chunks[c].phase1 = finalize(p1[c], false, false, st);
-    env->plan.chunks[c].phase2 = finalize(p2[c], false, true, st);
+    env->plan.chunks[c].phase1 = finalize(p1[c], false, false, st, pp.tile_overhead);
+    env->plan.chunks[c].phase2 = finalize(p2[c], false, true, st, pp.tile_overhead);
   }
   {
     std::vector<ReduceTile> rtl;
@@ -831,9 +724,156 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
     env->work_elems = work;
     env->work.alloc(sizeof(double) * std::max<int64_t>(work, 1));
   }
+  check_hip(hipStreamSynchronize(st), "plan");
+}
+
+Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
+              const Environment& L, const Environment& R) {
+  hipStream_t st = ctx->stream;
+  const int K = mpo.K;
+  std::unique_ptr<Env> env(new Env());
+  env->ctx = ctx;
+  env->site = site;
+  env->K = K;
+  env->bl = bond_l;
+  env->br = bond_r;
+  const Bond& bl = env->bl;
+  const Bond& br = env->br;
+  const int mid = site + 1;  // MPO bond between the two sites
+  env->D_mid = (int)mpo.dq[mid].size();
+
+  // ---- middle-bond sectors and the vector layout
+  std::map<QN, MiddleSector> secs;
+  for (size_t a = 0; a < bl.q.size(); ++a)
+    for (int s1 = 0; s1 < 4; ++s1) secs[bl.q[a] + local_qn(s1)].rows.push_back({(int)a, s1});
+  for (int s2 = 0; s2 < 4; ++s2)
+    for (size_t b = 0; b < br.q.size(); ++b) {
+      auto it = secs.find(br.q[b] - local_qn(s2));
+      if (it != secs.end()) it->second.cols.push_back({s2, (int)b});
+    }
+  std::map<QN, int>& sec_index = env->in.sec_index;
+  for (auto& kv : secs) {
+    MiddleSector& m = kv.second;
+    if (m.rows.empty() || m.cols.empty()) continue;
+    m.q = kv.first;
+    for (auto& r : m.rows) { m.row_off.push_back(m.nrows); m.nrows += bl.dim[r.first]; }
+    for (auto& c : m.cols) { m.col_off.push_back(m.ncols); m.ncols += br.dim[c.second]; }
+    m.off = env->n_elements;
+    env->n_elements += (int64_t)m.nrows * m.ncols;
+    sec_index[m.q] = (int)env->sectors.size();
+    env->sectors.push_back(m);
+  }
+  for (const MiddleSector& m : env->sectors)
+    for (size_t i = 0; i < m.rows.size(); ++i)
+      for (size_t jx = 0; jx < m.cols.size(); ++jx) {
+        lcc_block_entry e;
+        e.left = m.rows[i].first;
+        e.s1 = m.rows[i].second;
+        e.s2 = m.cols[jx].first;
+        e.right = m.cols[jx].second;
+        e.offset = m.off + (int64_t)m.row_off[i] * m.ncols + m.col_off[jx];
+        e.ld = m.ncols;
+        e.rows = bl.dim[e.left];
+        e.cols = br.dim[e.right];
+        env->layout.push_back(e);
+      }
+  // row / column lookup: (a, s1) -> (sector, row index); (s2, b) -> (sector, col index)
+  auto& row_at = env->in.row_at;
+  auto& col_at = env->in.col_at;
+  for (size_t m = 0; m < env->sectors.size(); ++m) {
+    for (size_t i = 0; i < env->sectors[m].rows.size(); ++i) row_at[env->sectors[m].rows[i]] = {(int)m, (int)i};
+    for (size_t i = 0; i < env->sectors[m].cols.size(); ++i) col_at[env->sectors[m].cols[i]] = {(int)m, (int)i};
+  }
+
+  // ---- environment data on the device: [L | R]
+  env->env_elems = L.size + R.size;
+  env->env64.alloc(sizeof(double) * std::max<int64_t>(env->env_elems, 1));
+  check_hip(hipMemcpyAsync(env->env64.p, L.data.p, sizeof(double) * L.size, hipMemcpyDeviceToDevice, st), "env copy");
+  check_hip(hipMemcpyAsync(env->env64.as<double>() + L.size, R.data.p, sizeof(double) * R.size, hipMemcpyDeviceToDevice, st),
+            "env copy");
+  const int64_t r_base = L.size;
+
+  // ---- enlarged operators.  A reference is (base, offset, coefficient).
+  // Lt: key (w1, row (a',s1'), src row (a,s1)) -> contributions (L block, coef)
+  std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> lt_terms;
+  std::vector<std::vector<int>> L_by_w(mpo.dq[site].size());
+  for (size_t i = 0; i < L.blocks.size(); ++i) L_by_w[L.blocks[i].w].push_back((int)i);
+  for (const MpoEntry& e : mpo.W[site])
+    for (int bi : L_by_w[e.win]) {
+      const EnvBlock& lb = L.blocks[bi];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s = 0; s < 4; ++s) {
+          const double c = e.m[sp * 4 + s];
+          if (c == 0.0) continue;
+          if (!row_at.count({lb.r, sp}) || !row_at.count({lb.c, s})) continue;
+          lt_terms[std::make_tuple(e.wout, lb.r, sp, lb.c, s)].push_back({bi, c});
+        }
+    }
+  std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> rt_terms;
+  std::vector<std::vector<int>> R_by_w(mpo.dq[site + 2].size());
+  for (size_t i = 0; i < R.blocks.size(); ++i) R_by_w[R.blocks[i].w].push_back((int)i);
+  for (const MpoEntry& e : mpo.W[site + 1])
+    for (int bi : R_by_w[e.wout]) {
+      const EnvBlock& rb = R.blocks[bi];
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s = 0; s < 4; ++s) {
+          const double c = e.m[sp * 4 + s];
+          if (c == 0.0) continue;
+          if (!col_at.count({sp, rb.r}) || !col_at.count({s, rb.c})) continue;
+          rt_terms[std::make_tuple(e.win, sp, rb.r, s, rb.c)].push_back({bi, c});
+        }
+    }
+  // references, merging multi-term entries
+  MixBuilder merge;
+  int64_t merged = 0;
+  // Lt index: (w1, a', s1') -> list of (a, s1, ref)
+  auto& lt = env->in.lt;
+  for (const auto& kv : lt_terms) {
+    int w1, ap, sp, a, s;
+    std::tie(w1, ap, sp, a, s) = kv.first;
+    OperandRef ref;
+    if (kv.second.size() == 1) {
+      ref = OperandRef{BASE_ENV, L.blocks[kv.second[0].first].off, kv.second[0].second};
+    } else {
+      const EnvBlock& b0 = L.blocks[kv.second[0].first];
+      merge.group(BASE_MERGED, merged, b0.rows * b0.cols, BASE_ENV);
+      for (const auto& c : kv.second) merge.term(L.blocks[c.first].off, c.second);
+      ref = OperandRef{BASE_MERGED, merged, 1.0};
+      merged += (int64_t)b0.rows * b0.cols;
+    }
+    lt[std::make_tuple(w1, ap, sp)].push_back(std::make_tuple(a, s, ref));
+  }
+  auto& rt = env->in.rt;  // (w1, s2', b') -> (s2, b, ref)
+  for (const auto& kv : rt_terms) {
+    int w1, sp, bp, s, b;
+    std::tie(w1, sp, bp, s, b) = kv.first;
+    OperandRef ref;
+    if (kv.second.size() == 1) {
+      ref = OperandRef{BASE_ENV, r_base + R.blocks[kv.second[0].first].off, kv.second[0].second};
+    } else {
+      const EnvBlock& b0 = R.blocks[kv.second[0].first];
+      merge.group(BASE_MERGED, merged, b0.rows * b0.cols, BASE_ENV);
+      for (const auto& c : kv.second) merge.term(r_base + R.blocks[c.first].off, c.second);
+      ref = OperandRef{BASE_MERGED, merged, 1.0};
+      merged += (int64_t)b0.rows * b0.cols;
+    }
+    rt[std::make_tuple(w1, sp, bp)].push_back(std::make_tuple(s, b, ref));
+  }
+  env->merged_elems = merged;
+  env->merged64.alloc(sizeof(double) * std::max<int64_t>(merged, 1));
+  {
+    Bases<double> b{};
+    b.p[BASE_ENV] = env->env64.as<double>();
+    b.p[BASE_MERGED] = env->merged64.as<double>();
+    run_mix(merge, b, st);
+  }
+
+  env->in.dq_mid = mpo.dq[mid];
+  plan_env(*env, ctx->plan_params);
   // CG workspace (FP64)
   for (auto& w : env->w64) w.alloc(sizeof(double) * std::max<int64_t>(env->n_elements, 1));
   env->flag.alloc(sizeof(int) * 4);
+  apply_tuned(*env);
   check_hip(hipStreamSynchronize(st), "build_env");
   return env.release();
 }
@@ -888,14 +928,11 @@ void apply_heff_each(Env& env, int precision, const void* x, void* y,
       for (const GemmLaunch& L : ph == 1 ? C.phase1 : C.phase2) {
         hipError_t e;
         if (precision == LCC_FP64)
-          e = launch_gemm_f64(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(), L.n_tiles,
-                              L.ta, L.tb, L.shape, b64, st);
+          e = launch_gemm_f64(L.desc(LCC_FP64), b64, st);
         else if (precision == LCC_FP32)
-          e = launch_gemm_f32(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(), L.n_tiles,
-                              L.ta, L.tb, L.shape, b32, st);
+          e = launch_gemm_f32(L.desc(LCC_FP32), b32, st);
         else
-          e = launch_gemm_bf16x3(L.terms.as<GemmTerm>(), L.groups.as<GemmGroup>(), L.tiles.as<GemmTile>(),
-                                 L.n_tiles, L.ta, L.tb, L.shape, b32, st);
+          e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), b32, st);
         check_hip(e, "gemm launch");
         after_each(user, LaunchRef{ph, 0, &L});
       }

@@ -68,10 +68,23 @@ struct GemmTerm {
 struct GemmGroup {
   int64_t c_off;
   int32_t ldc, m, n, tiles_n;
-  int32_t term_begin, term_end;
+  int32_t term_begin, term_end;  // host-side term range
   int8_t c_base, accumulate;
   int16_t pad0;
   int32_t problem;  // index into the base-pointer table of a batched launch (0 otherwise)
+  int32_t slot_begin, slot_end;  // the group's k-quads in the launch's slot array
+};
+// One k-quad of a term: four consecutive k (kv of them valid) of alpha * op(A) * op(B).
+// a_off / b_off are the element offsets of the quad's first k in the A and B base arrays
+// (row 0 of A, column 0 of B), so that a group's quads, taken in term order, form one packed
+// accumulation stream: terms with short k share the kernel's k chunks instead of each
+// padding its own.
+struct SlotRec {
+  int64_t a_off, b_off;
+  int32_t lda, ldb;
+  double alpha;
+  int8_t a_base, b_base, kv, pad0;
+  int32_t pad1;
 };
 struct GemmTile {
   int32_t group, tile;
@@ -114,18 +127,23 @@ constexpr int kTileShapes[kNumTileShapes][2] = {{64, 64}, {16, 64}, {64, 16}, {3
 enum TileShape { TILE_64x64 = 0, TILE_16x64 = 1 };
 
 // Launchers (kernels.hip).  All asynchronous on `stream`.
-hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                           int n_tiles, bool ta, bool tb, int shape, const Bases<double>& b,
-                           hipStream_t stream, const Bases<double>* table = nullptr,
-                           const int* active = nullptr);
-hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                           int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                           hipStream_t stream, const Bases<float>* table = nullptr,
-                           const int* active = nullptr);
-hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                              int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                              hipStream_t stream, const Bases<float>* table = nullptr,
-                           const int* active = nullptr);
+// One grouped-GEMM launch.  Two kernels implement it: the term walk (each term staged in
+// chunks of its own, `terms`) and the packed-k walk (the group's k-quads in shared chunks,
+// `slots`); `packed` selects which.
+struct GemmDesc {
+  const GemmTerm* terms;
+  const SlotRec* slots;
+  const GemmGroup* groups;
+  const GemmTile* tiles;
+  int n_tiles, shape;
+  bool ta, tb, packed;
+};
+hipError_t launch_gemm_f64(const GemmDesc& d, const Bases<double>& b, hipStream_t stream,
+                           const Bases<double>* table = nullptr, const int* active = nullptr);
+hipError_t launch_gemm_f32(const GemmDesc& d, const Bases<float>& b, hipStream_t stream,
+                           const Bases<float>* table = nullptr, const int* active = nullptr);
+hipError_t launch_gemm_bf16x3(const GemmDesc& d, const Bases<float>& b, hipStream_t stream,
+                              const Bases<float>* table = nullptr, const int* active = nullptr);
 hipError_t launch_reduce_f64(const ReduceGroup* groups, const ReduceTile* tiles, int n_tiles,
                              const Bases<double>& b, hipStream_t stream, const Bases<double>* table = nullptr,
                              const int* active = nullptr);

@@ -29,14 +29,6 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return start + local;
 }
 
-// ------------------------------------------------------------------------------------------
-// FP64 / FP32 MFMA 16x16x4 grouped GEMM.
-//   MODE 0: double operands, v_mfma_f64_16x16x4_f64: lane l holds A[l%16][l/16], B[l/16][l%16],
-//           accumulator element r at row l/16 + 4r, column l%16.
-//   MODE 1: float operands, v_mfma_f32_16x16x4_f32: same inputs, accumulator element r at
-//           row 4(l/16) + r, column l%16.
-// Waves are arranged WM x WN; each wave owns (BM/WM) x (BN/WN) = (16 TM) x (16 TN).
-// ------------------------------------------------------------------------------------------
 template <int MODE>
 struct Mfma;
 template <>
@@ -58,6 +50,445 @@ struct Mfma<1> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// ------------------------------------------------------------------------------------------
+// Packed-k operand staging.  A workgroup consumes its group's k-quads (SlotRec, four
+// consecutive k of one term) in chunks of BK/4 quads, so that terms with short k share a
+// chunk.  Before a chunk is loaded, BK/4 threads resolve its quads (pointers, leading
+// dimensions, valid count, alpha) into LDS, where every thread finds the quads of the elements
+// it stages.  An operand stored k-contiguous (KC: element (r, k) at p[r*ld + k]) is staged by
+// quads along k, otherwise (p[k*ld + r]) by quads along r; either way one 16-byte global load
+// (two for double) per full quad, element-aligned.  Elements outside the matrix or past a
+// quad's valid count are zeros.
+// ------------------------------------------------------------------------------------------
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct QuadRef {
+  const T* a;
+  const T* b;
+  int lda, ldb, kv;
+  T alpha;
+};
+
+template <class T>
+__device__ __forceinline__ T* pick_base(const Bases<T>& bs, int i) {
+  T* p = bs.p[0];
+#pragma unroll
+  for (int j = 1; j < NUM_BASES; ++j) p = (i == j) ? bs.p[j] : p;
+  return p;
+}
+
+template <class T>
+__device__ __forceinline__ void resolve_quad(QuadRef<T>& Q, const SlotRec& s, bool valid, const Bases<T>& bs) {
+  if (valid) {
+    Q.a = pick_base(bs, s.a_base) + s.a_off;
+    Q.b = pick_base(bs, s.b_base) + s.b_off;
+    Q.lda = s.lda;
+    Q.ldb = s.ldb;
+    Q.kv = s.kv;
+    Q.alpha = (T)s.alpha;
+  } else {
+    Q.a = nullptr;
+    Q.b = nullptr;
+    Q.lda = Q.ldb = Q.kv = 0;
+    Q.alpha = (T)0;
+  }
+}
+
+__device__ __forceinline__ void load_quad(float* v, const float* p) {
+  const f4u w = *reinterpret_cast<const f4u*>(p);
+  v[0] = w[0]; v[1] = w[1]; v[2] = w[2]; v[3] = w[3];
+}
+__device__ __forceinline__ void load_quad(double* v, const double* p) {
+  const d2u w0 = *reinterpret_cast<const d2u*>(p);
+  const d2u w1 = *reinterpret_cast<const d2u*>(p + 2);
+  v[0] = w0[0]; v[1] = w0[1]; v[2] = w1[0]; v[3] = w1[1];
+}
+// 16-byte-aligned LDS quads (two 16-byte accesses for double).
+__device__ __forceinline__ f4 lds_read_quad(const float* p) { return *reinterpret_cast<const f4*>(p); }
+__device__ __forceinline__ d4 lds_read_quad(const double* p) {
+  const d2 w0 = *reinterpret_cast<const d2*>(p);
+  const d2 w1 = *reinterpret_cast<const d2*>(p + 2);
+  return d4{w0[0], w0[1], w1[0], w1[1]};
+}
+__device__ __forceinline__ void lds_write_quad(float* p, float a, float b, float c, float d) {
+  *reinterpret_cast<f4*>(p) = f4{a, b, c, d};
+}
+__device__ __forceinline__ void lds_write_quad(double* p, double a, double b, double c, double d) {
+  *reinterpret_cast<d2*>(p) = d2{a, b};
+  *reinterpret_cast<d2*>(p + 2) = d2{c, d};
+}
+
+// OP 0: operand A (rows = output rows, scaled by the quad's alpha); OP 1: operand B.
+template <class T, bool KC, int R, int BK, int OP>
+struct Stager {
+  static constexpr int QUADS = R * BK / 4;
+  static constexpr int NQ = (QUADS + kThreads - 1) / kThreads;
+  static constexpr int SPC = BK / 4;
+  static constexpr int PAD = 16 / (int)sizeof(T);
+  // LDS tile of the FP64/FP32 kernel mirrors the stored layout: [R][BK] if KC, else [BK][R]
+  static constexpr int D0 = KC ? R : BK;
+  static constexpr int D1 = KC ? BK + PAD : R + PAD;
+  T v[NQ][4];
+  T scale[NQ];
+
+  static __device__ __forceinline__ bool live(int q) { return QUADS % kThreads == 0 || q < QUADS; }
+  // quad q -> (first row r, packed k kk): KC quads run along k, the others along r
+  static __device__ __forceinline__ void coords(int q, int& r, int& kk) {
+    if (KC) {
+      r = q / SPC;
+      kk = 4 * (q % SPC);
+    } else {
+      kk = q / (R / 4);
+      r = 4 * (q % (R / 4));
+    }
+  }
+  __device__ __forceinline__ void load(const QuadRef<T>* refs, int r0, int rmax) {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[i][j] = (T)0;
+      scale[i] = (T)1;
+      const int q = threadIdx.x + i * kThreads;
+      if (!live(q)) continue;
+      int r, kk;
+      coords(q, r, kk);
+      const QuadRef<T>& Q = refs[kk >> 2];
+      if (OP == 0) scale[i] = Q.alpha;
+      const T* P = OP == 0 ? Q.a : Q.b;
+      const int ld = OP == 0 ? Q.lda : Q.ldb;
+      const int gr = r0 + r;
+      if (KC) {
+        if (gr >= rmax || Q.kv == 0) continue;
+        const T* p = P + (int64_t)gr * ld;
+        if (Q.kv == 4) {
+          load_quad(v[i], p);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            if (j < Q.kv) v[i][j] = p[j];
+        }
+      } else {
+        const int jj = kk & 3;
+        if (jj >= Q.kv) continue;
+        const T* p = P + (int64_t)jj * ld + gr;
+        if (gr + 3 < rmax) {
+          load_quad(v[i], p);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 3; ++j)
+            if (gr + j < rmax) v[i][j] = p[j];
+        }
+      }
+    }
+  }
+  // FP64 / FP32 kernel: into the mirrored LDS tile
+  __device__ __forceinline__ void store(T (*S)[D1]) const {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = threadIdx.x + i * kThreads;
+      if (!live(q)) continue;
+      int r, kk;
+      coords(q, r, kk);
+      const T s = scale[i];
+      lds_write_quad(KC ? &S[r][kk] : &S[kk][r], v[i][0] * s, v[i][1] * s, v[i][2] * s, v[i][3] * s);
+    }
+  }
+  // BF16x3 kernel: into k-contiguous hi / lo tiles [R][KP]
+  template <int KP>
+  __device__ __forceinline__ void store_split(__bf16 (*H)[KP], __bf16 (*L)[KP]) const {
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const int q = threadIdx.x + i * kThreads;
+      if (!live(q)) continue;
+      int r, kk;
+      coords(q, r, kk);
+      bf4 h, l;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float x = (float)(v[i][j] * scale[i]);
+        h[j] = (__bf16)x;
+        l[j] = (__bf16)(x - (float)h[j]);
+      }
+      if (KC) {
+        *reinterpret_cast<bf4*>(&H[r][kk]) = h;
+        *reinterpret_cast<bf4*>(&L[r][kk]) = l;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          H[r + j][kk] = h[j];
+          L[r + j][kk] = l[j];
+        }
+      }
+    }
+  }
+};
+
+// The chunk walk of the kernels: resolve the quads of chunk 0, load it, prefetch the raw
+// records of chunk 1; then for each chunk c: store the staged chunk c to LDS, resolve chunk
+// c+1, load chunk c+1 into registers and prefetch the records of chunk c+2 while chunk c is
+// multiplied.
+
+// ------------------------------------------------------------------------------------------
+// FP64 / FP32 MFMA 16x16x4 grouped GEMM.
+//   MODE 0: double operands, v_mfma_f64_16x16x4_f64: lane l holds A[l%16][k(l/16)], B[k(l/16)][l%16],
+//           accumulator element r at row l/16 + 4r, column l%16.
+//   MODE 1: float operands, v_mfma_f32_16x16x4_f32: same inputs, accumulator element r at
+//           row 4(l/16) + r, column l%16.
+// The four MFMAs of a 16-wide k group take k(l/16) = 4(l/16) + s in step s (s = 0..3): the sum
+// over k is the same for any assignment that A and B share, and with it a lane fetches the
+// four k values of its row of a k-contiguous LDS tile with one 16-byte read (two for double);
+// from an r-contiguous tile it reads them one by one.
+// Waves are arranged WM x WN; each wave owns (BM/WM) x (BN/WN) = (16 TM) x (16 TN).
+// ------------------------------------------------------------------------------------------
+template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(kThreads)
+gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
+                 const GemmTile* __restrict__ tiles, int n_tiles,
+                 Bases<typename Mfma<MODE>::T> bases, const Bases<typename Mfma<MODE>::T>* __restrict__ table,
+                 const int* __restrict__ active) {
+  typedef typename Mfma<MODE>::T T;
+  typedef typename Mfma<MODE>::Acc Acc;
+  constexpr int BK = 128 / (int)sizeof(T);  // one 128-byte line of a row per chunk
+  constexpr int SPC = BK / 4;
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  static_assert(WM * WN == kThreads / 64, "four waves");
+  typedef Stager<T, !TA, BM, BK, 0> SA;
+  typedef Stager<T, TB, BN, BK, 1> SB;
+  __shared__ __attribute__((aligned(16))) T As[SA::D0][SA::D1];
+  __shared__ __attribute__((aligned(16))) T Bs[SB::D0][SB::D1];
+  __shared__ QuadRef<T> refs[SPC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+
+  const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
+  const GemmGroup g = groups[tile.group];
+  if (table) {  // batched launch: per-problem operands, converged problems skipped
+    if (active && !active[g.problem]) return;
+    bases = table[g.problem];
+  }
+  const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  Acc acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  SA sa;
+  SB sb;
+  const int nslots = g.slot_end - g.slot_begin;
+  const int nch = (nslots + SPC - 1) / SPC;
+  const SlotRec* __restrict__ gs = slots + g.slot_begin;
+  SlotRec pending{};
+  if (nch > 0) {
+    if (tid < SPC) {
+      const bool ok = tid < nslots;
+      if (ok) pending = gs[tid];
+      resolve_quad(refs[tid], pending, ok, bases);
+    }
+    __syncthreads();
+    sa.load(refs, row0, g.m);
+    sb.load(refs, col0, g.n);
+    if (tid < SPC && SPC + tid < nslots) pending = gs[SPC + tid];
+  }
+  for (int c = 0; c < nch; ++c) {
+    const int kmax = min(BK, 4 * (nslots - c * SPC));
+    __syncthreads();
+    sa.store(As);
+    sb.store(Bs);
+    if (tid < SPC) resolve_quad(refs[tid], pending, (c + 1) * SPC + tid < nslots, bases);
+    __syncthreads();
+    if (c + 1 < nch) {
+      sa.load(refs, row0, g.m);
+      sb.load(refs, col0, g.n);
+      if (tid < SPC && (c + 2) * SPC + tid < nslots) pending = gs[(c + 2) * SPC + tid];
+    }
+#pragma unroll
+    for (int kg = 0; kg < BK; kg += 16) {
+      if (kg < kmax) {
+        const int kq = kg + 4 * (lane >> 4);
+        T a[TM][4], b[TN][4];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const int r = wm * (BM / WM) + i * 16 + (lane & 15);
+          if (!TA) {
+            const auto q = lds_read_quad(&As[r][kq]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[i][s] = q[s];
+          } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[i][s] = As[kq + s][r];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int cc = wn * (BN / WN) + j * 16 + (lane & 15);
+          if (TB) {
+            const auto q = lds_read_quad(&Bs[cc][kq]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[j][s] = q[s];
+          } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[j][s] = Bs[kq + s][cc];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<MODE>::step(a[i][s], b[j][s], acc[i][j]);
+      }
+    }
+  }
+
+  T* __restrict__ C = bases.p[g.c_base] + g.c_off;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * (BM / WM) + i * 16 + Mfma<MODE>::row(lane, r);
+        const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
+        if (gr < g.m && gc < g.n) {
+          T* p = C + (int64_t)gr * g.ldc + gc;
+          *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+}
+
+// ------------------------------------------------------------------------------------------
+// BF16x3 split-product GEMM on v_mfma_f32_16x16x32_bf16.  FP32 operands are split while
+// staged: hi = bf16(x), lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi with FP32
+// accumulation (the lo*lo term is below the representation error of the split).
+// Lane l holds A[l%16][8(l/16) + i], B[8(l/16) + i][l%16] (i = 0..7); accumulator element r
+// at row 4(l/16) + r, column l%16.  LDS holds A as [m][k] and B as [n][k] so that each
+// lane's eight k values are contiguous.
+// ------------------------------------------------------------------------------------------
+template <bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(kThreads)
+gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
+                   const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
+                   const Bases<float>* __restrict__ table, const int* __restrict__ active) {
+  constexpr int BK = 32;
+  constexpr int SPC = BK / 4;
+  constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
+  constexpr int TM = BM / WM / 16;
+  constexpr int TN = BN / WN / 16;
+  typedef Stager<float, !TA, BM, BK, 0> SA;
+  typedef Stager<float, TB, BN, BK, 1> SB;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][KP];
+  __shared__ QuadRef<float> refs[SPC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+
+  const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
+  const GemmGroup g = groups[tile.group];
+  if (table) {  // batched launch: per-problem operands, converged problems skipped
+    if (active && !active[g.problem]) return;
+    bases = table[g.problem];
+  }
+  const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  SA sa;
+  SB sb;
+  const int nslots = g.slot_end - g.slot_begin;
+  const int nch = (nslots + SPC - 1) / SPC;
+  const SlotRec* __restrict__ gs = slots + g.slot_begin;
+  SlotRec pending{};
+  if (nch > 0) {
+    if (tid < SPC) {
+      const bool ok = tid < nslots;
+      if (ok) pending = gs[tid];
+      resolve_quad(refs[tid], pending, ok, bases);
+    }
+    __syncthreads();
+    sa.load(refs, row0, g.m);
+    sb.load(refs, col0, g.n);
+    if (tid < SPC && SPC + tid < nslots) pending = gs[SPC + tid];
+  }
+  for (int c = 0; c < nch; ++c) {
+    const int kmax = min(BK, 4 * (nslots - c * SPC));
+    __syncthreads();
+    sa.template store_split<KP>(Ah, Al);
+    sb.template store_split<KP>(Bh, Bl);
+    if (tid < SPC) resolve_quad(refs[tid], pending, (c + 1) * SPC + tid < nslots, bases);
+    __syncthreads();
+    if (c + 1 < nch) {
+      sa.load(refs, row0, g.m);
+      sb.load(refs, col0, g.n);
+      if (tid < SPC && (c + 2) * SPC + tid < nslots) pending = gs[(c + 2) * SPC + tid];
+    }
+    (void)kmax;
+    bf8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * (BM / WM) + i * 16 + (lane & 15);
+      ah[i] = *reinterpret_cast<const bf8*>(&Ah[r][8 * (lane >> 4)]);
+      al[i] = *reinterpret_cast<const bf8*>(&Al[r][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int cc = wn * (BN / WN) + j * 16 + (lane & 15);
+      bh[j] = *reinterpret_cast<const bf8*>(&Bh[cc][8 * (lane >> 4)]);
+      bl[j] = *reinterpret_cast<const bf8*>(&Bl[cc][8 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  }
+
+  float* __restrict__ C = bases.p[g.c_base] + g.c_off;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
+        if (gr < g.m && gc < g.n) {
+          float* p = C + (int64_t)gr * g.ldc + gc;
+          *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
+        }
+      }
+}
+
+// ------------------------------------------------------------------------------------------
+// Term-walk FP64 / FP32 grouped GEMM: a workgroup walks its group's terms one by one, each in
+// chunks of BK k (a term's last chunk is partial).  Lane layouts of the MFMAs as below; the LDS
+// tiles are [k][m] and [k][n] and every MFMA operand is one LDS read.
+// ------------------------------------------------------------------------------------------
 // Operand staging shared by the kernels: each thread holds NA elements of the next A chunk
 // and NB of the next B chunk in registers, so the global loads of chunk i+1 are in flight
 // while the MFMAs of chunk i run.  Element e of a chunk maps to (row, k) so that consecutive
@@ -99,7 +530,7 @@ struct BLoader {
 
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(kThreads)
-gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
+gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
                  const GemmTile* __restrict__ tiles, int n_tiles,
                  Bases<typename Mfma<MODE>::T> bases, const Bases<typename Mfma<MODE>::T>* __restrict__ table,
                  const int* __restrict__ active) {
@@ -206,7 +637,7 @@ gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict
 }
 
 // ------------------------------------------------------------------------------------------
-// BF16x3 split-product GEMM on v_mfma_f32_16x16x32_bf16.  FP32 operands are split while
+// Term-walk BF16x3 split-product GEMM on v_mfma_f32_16x16x32_bf16.  FP32 operands are split while
 // staged: hi = bf16(x), lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi with FP32
 // accumulation (the lo*lo term is below the representation error of the split).
 // Lane l holds A[l%16][8(l/16) + i], B[8(l/16) + i][l%16] (i = 0..7); accumulator element r
@@ -215,7 +646,7 @@ gemm_mfma_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict
 // ------------------------------------------------------------------------------------------
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(kThreads)
-gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
+gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
                    const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
                    const Bases<float>* __restrict__ table, const int* __restrict__ active) {
   constexpr int BK = 32;
@@ -332,67 +763,71 @@ gemm_bf16x3_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restri
 // Launchers.  The tile shape (rows x cols per workgroup, wave grid) is chosen per group by the
 // planner from the block sizes; see kTileShapes in internal.h.
 // ------------------------------------------------------------------------------------------
+template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
+static void fire_mfma(const GemmDesc& d, const Bases<typename Mfma<MODE>::T>& b, hipStream_t s,
+                      const Bases<typename Mfma<MODE>::T>* table, const int* active) {
+  if (d.packed)
+    hipLaunchKernelGGL((gemm_packed_kernel<MODE, TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+                       d.slots, d.groups, d.tiles, d.n_tiles, b, table, active);
+  else
+    hipLaunchKernelGGL((gemm_terms_kernel<MODE, TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+                       d.terms, d.groups, d.tiles, d.n_tiles, b, table, active);
+}
 template <int MODE, int BM, int BN, int WM, int WN>
-static hipError_t launch_mfma_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                                    int n_tiles, bool ta, bool tb,
-                                    const Bases<typename Mfma<MODE>::T>& b, hipStream_t s,
+static hipError_t launch_mfma_shape(const GemmDesc& d, const Bases<typename Mfma<MODE>::T>& b, hipStream_t s,
                                     const Bases<typename Mfma<MODE>::T>* table, const int* active) {
-  if (n_tiles <= 0) return hipSuccess;
-  dim3 grid(n_tiles), block(kThreads);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
-  else
-    hipLaunchKernelGGL((gemm_mfma_kernel<MODE, true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
+  if (d.n_tiles <= 0) return hipSuccess;
+  if (!d.ta && !d.tb) fire_mfma<MODE, false, false, BM, BN, WM, WN>(d, b, s, table, active);
+  else if (!d.ta && d.tb) fire_mfma<MODE, false, true, BM, BN, WM, WN>(d, b, s, table, active);
+  else if (d.ta && !d.tb) fire_mfma<MODE, true, false, BM, BN, WM, WN>(d, b, s, table, active);
+  else fire_mfma<MODE, true, true, BM, BN, WM, WN>(d, b, s, table, active);
   return hipGetLastError();
 }
 
+template <bool TA, bool TB, int BM, int BN, int WM, int WN>
+static void fire_bf(const GemmDesc& d, const Bases<float>& b, hipStream_t s, const Bases<float>* table,
+                    const int* active) {
+  if (d.packed)
+    hipLaunchKernelGGL((gemm_bf16x3_packed_kernel<TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+                       d.slots, d.groups, d.tiles, d.n_tiles, b, table, active);
+  else
+    hipLaunchKernelGGL((gemm_bf16x3_terms_kernel<TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+                       d.terms, d.groups, d.tiles, d.n_tiles, b, table, active);
+}
 template <int BM, int BN, int WM, int WN>
-static hipError_t launch_bf_shape(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                                  int n_tiles, bool ta, bool tb, const Bases<float>& b, hipStream_t s,
-                                  const Bases<float>* table, const int* active) {
-  if (n_tiles <= 0) return hipSuccess;
-  dim3 grid(n_tiles), block(kThreads);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
-  else
-    hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, BM, BN, WM, WN>), grid, block, 0, s, terms, groups, tiles, n_tiles, b, table, active);
+static hipError_t launch_bf_shape(const GemmDesc& d, const Bases<float>& b, hipStream_t s, const Bases<float>* table,
+                                  const int* active) {
+  if (d.n_tiles <= 0) return hipSuccess;
+  if (!d.ta && !d.tb) fire_bf<false, false, BM, BN, WM, WN>(d, b, s, table, active);
+  else if (!d.ta && d.tb) fire_bf<false, true, BM, BN, WM, WN>(d, b, s, table, active);
+  else if (d.ta && !d.tb) fire_bf<true, false, BM, BN, WM, WN>(d, b, s, table, active);
+  else fire_bf<true, true, BM, BN, WM, WN>(d, b, s, table, active);
   return hipGetLastError();
 }
 
-#define LCC_SHAPE_SWITCH(FN, ...)                                   \
-  switch (shape) {                                                  \
-    case 0: return FN<__VA_ARGS__ 64, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
-    case 1: return FN<__VA_ARGS__ 16, 64, 1, 4>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
-    case 2: return FN<__VA_ARGS__ 64, 16, 4, 1>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
-    case 3: return FN<__VA_ARGS__ 32, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
-    case 4: return FN<__VA_ARGS__ 128, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);  \
-    case 5: return FN<__VA_ARGS__ 64, 128, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);  \
-    case 6: return FN<__VA_ARGS__ 32, 64, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
-    case 7: return FN<__VA_ARGS__ 64, 32, 2, 2>(terms, groups, tiles, n_tiles, ta, tb, b, stream, table, active);   \
-    default: return hipErrorInvalidValue;                           \
+#define LCC_SHAPE_SWITCH(FN, ...)                                          \
+  switch (d.shape) {                                                       \
+    case 0: return FN<__VA_ARGS__ 64, 64, 2, 2>(d, b, stream, table, active);   \
+    case 1: return FN<__VA_ARGS__ 16, 64, 1, 4>(d, b, stream, table, active);   \
+    case 2: return FN<__VA_ARGS__ 64, 16, 4, 1>(d, b, stream, table, active);   \
+    case 3: return FN<__VA_ARGS__ 32, 32, 2, 2>(d, b, stream, table, active);   \
+    case 4: return FN<__VA_ARGS__ 128, 64, 2, 2>(d, b, stream, table, active);  \
+    case 5: return FN<__VA_ARGS__ 64, 128, 2, 2>(d, b, stream, table, active);  \
+    case 6: return FN<__VA_ARGS__ 32, 64, 2, 2>(d, b, stream, table, active);   \
+    case 7: return FN<__VA_ARGS__ 64, 32, 2, 2>(d, b, stream, table, active);   \
+    default: return hipErrorInvalidValue;                                  \
   }
 
-hipError_t launch_gemm_f64(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                           int n_tiles, bool ta, bool tb, int shape, const Bases<double>& b,
-                           hipStream_t stream, const Bases<double>* table, const int* active) {
+hipError_t launch_gemm_f64(const GemmDesc& d, const Bases<double>& b, hipStream_t stream, const Bases<double>* table,
+                           const int* active) {
   LCC_SHAPE_SWITCH(launch_mfma_shape, 0, )
 }
-hipError_t launch_gemm_f32(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                           int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                           hipStream_t stream, const Bases<float>* table, const int* active) {
+hipError_t launch_gemm_f32(const GemmDesc& d, const Bases<float>& b, hipStream_t stream, const Bases<float>* table,
+                           const int* active) {
   LCC_SHAPE_SWITCH(launch_mfma_shape, 1, )
 }
-hipError_t launch_gemm_bf16x3(const GemmTerm* terms, const GemmGroup* groups, const GemmTile* tiles,
-                              int n_tiles, bool ta, bool tb, int shape, const Bases<float>& b,
-                              hipStream_t stream, const Bases<float>* table, const int* active) {
+hipError_t launch_gemm_bf16x3(const GemmDesc& d, const Bases<float>& b, hipStream_t stream, const Bases<float>* table,
+                              const int* active) {
   LCC_SHAPE_SWITCH(launch_bf_shape, )
 }
 #undef LCC_SHAPE_SWITCH

@@ -167,6 +167,7 @@ std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const 
       p.tile_n = kTileShapes[L.shape][1];
       p.n_tiles = L.n_tiles;
       p.flops = L.flops;
+      p.exec_flops = L.exec_flops;
       p.bytes = (L.elems_read + L.elems_written) * esz;
     } else {
       p.n_tiles = env.plan.n_reduce_tiles;

@@ -1,7 +1,9 @@
 // Library state behind the opaque C handles.
 #pragma once
 
+#include <map>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -48,6 +50,12 @@ void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
   check_hip(hipStreamSynchronize(s), "upload sync");
 }
 
+// Planner parameters (the autotuner's search space besides the per-launch kernel choice).
+struct PlanParams {
+  double tile_overhead = 2048.0;  // per-tile cost, in output elements, of the tile-shape choice
+  int64_t split_k = 2048;         // accumulation length per phase-2 part (split-K)
+};
+
 struct Context {
   void* handle = nullptr;  // the owning lcc_context_s
   int device = -1;
@@ -58,6 +66,8 @@ struct Context {
   DevBuf dot_partial, dot_out;
   double* host_scalar = nullptr;  // pinned
   int64_t t_budget_elems = (int64_t)1 << 31;  // intermediate (phase-1 output) elements per environment
+  PlanParams plan_params;                      // defaults for new environments
+  std::string tune_cache;                      // autotuner cache file ("" = none)
 };
 
 struct Bond {
@@ -94,11 +104,30 @@ struct GemmLaunch {
   bool ta = false, tb = false;
   int shape = TILE_64x64;
   int n_tiles = 0;
+  int64_t n_slots = 0;
   double flops = 0;          // 2 m n k over the launch's block products
+  double exec_flops = 0;     // MFMA work including tile and k-group padding
   double elems_read = 0;     // distinct operand blocks, each counted once
   double elems_written = 0;  // output blocks
-  DevBuf terms, groups, tiles;
+  DevBuf terms, slots, groups, tiles;
+  bool packed[3] = {false, false, false};  // kernel per precision (lcc_precision index)
+  GemmDesc desc(int precision) const {
+    return GemmDesc{terms.as<GemmTerm>(), slots.as<SlotRec>(), groups.as<GemmGroup>(), tiles.as<GemmTile>(),
+                    n_tiles, shape, ta, tb, packed[precision]};
+  }
 };
+
+// Host-side list of output blocks ("groups") and their block products ("terms").
+struct GemmBuilder {
+  std::vector<GemmTerm> terms;
+  std::vector<GemmGroup> groups;
+  double flops = 0;
+  void group(int8_t c_base, int64_t c_off, int ldc, int m, int n, bool accumulate);
+  void term(int8_t a_base, int64_t a_off, int lda, int8_t b_base, int64_t b_off, int ldb, int k, double alpha);
+};
+// tile_overhead: per-tile cost (in output elements) of the shape choice, see shape_for
+std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s, double tile_overhead = 2048.0);
+void run_gemm64(const std::vector<GemmLaunch>& Ls, const Bases<double>& b, hipStream_t s);
 
 struct Plan {
   // channel chunks: phase 1 then phase 2 of each chunk, in order; one launch per tile shape
@@ -121,6 +150,21 @@ struct MiddleSector {
   std::vector<int> col_off;
 };
 
+// Reference to an operand block of the enlarged operators: base array, offset, coefficient.
+struct OperandRef {
+  int8_t base;
+  int64_t off;
+  double alpha;
+};
+// What the planner needs besides the environments themselves (kept for re-planning).
+struct PlanInputs {
+  std::map<QN, int> sec_index;
+  std::map<std::pair<int, int>, std::pair<int, int>> row_at, col_at;  // (a,s1) / (s2,b) -> (sector, index)
+  // Lt: (w1, a', s1') -> [(a, s1, ref)];  Rt: (w1, s2', b') -> [(s2, b, ref)]
+  std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, OperandRef>>> lt, rt;
+  std::vector<QN> dq_mid;
+};
+
 struct Env {
   Context* ctx = nullptr;
   int site = 0, K = 0;
@@ -133,6 +177,8 @@ struct Env {
   DevBuf env64, env32, merged64, merged32, tbuf, work;
   int64_t env_elems = 0, merged_elems = 0, t_elems = 0, work_elems = 0;
   Plan plan;
+  PlanParams params;
+  PlanInputs in;
   // CG workspace
   DevBuf w64[6], w32[6];
   DevBuf flag;
@@ -164,6 +210,12 @@ Environment left_step(const Environment& L, const DeviceMps& mps, int j, const M
 Environment right_step(const Environment& R, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st);
 void check_identity(const Environment& E, int w_id, const Bond& bond, hipStream_t st, const char* which);
 int channel_of_kind(const Mpo& mpo, int bond, int kind);
+// (re)plan an environment's H_eff x for the given planner parameters
+void plan_env(Env& env, const PlanParams& pp);
+// autotuner (tune.cpp): signature of the block-size histogram, cached choice, timed search
+uint64_t histogram_signature(const Env& env);
+bool apply_tuned(Env& env);
+void autotune(Env& env, int precision, int reps, lcc_tune_info* info);
 // enlarged operators, vector layout and apply plan of the two-site block (site, site+1)
 Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
               const Environment& L, const Environment& R);

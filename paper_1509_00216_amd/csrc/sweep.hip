@@ -225,10 +225,7 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     // site l+2 tensor blocks by (left sector b, s3)
     std::map<std::pair<int, int>, const SiteBlock*> B;
     for (const SiteBlock& b : S.mps.sites[next + 1]) B[{b.l, b.s}] = &b;
-    // column (s2, b) offsets of each old sector
-    std::vector<GemmTerm> terms;
-    std::vector<GemmGroup> groups;
-    std::vector<GemmTile> tiles;
+    GemmBuilder gb;
     for (const lcc_block_entry& e : nenv->layout) {
       // e.left = new sector index (q), e.s1 = s2, e.s2 = s3, e.right = c
       int q_old = -1;
@@ -246,41 +243,16 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
         if (M.cols[j].first == e.s1 && M.cols[j].second == b) col = (int)j;
       if (col < 0) continue;
       const SiteBlock& Bb = *it->second;
-      GemmGroup g{};
-      g.c_off = e.offset;
-      g.ldc = e.ld;
-      g.m = e.rows;
-      g.n = e.cols;
-      g.c_base = BASE_Y;
-      g.tiles_n = (g.n + 63) / 64;
-      g.term_begin = (int32_t)terms.size();
-      GemmTerm t{};
-      t.a_base = BASE_X;
-      t.a_off = c_off[q_old] + M.col_off[col];
-      t.lda = M.ncols;
-      t.b_base = BASE_MPS;
-      t.b_off = Bb.off;
-      t.ldb = Bb.cols;
-      t.k = Bb.rows;
-      t.alpha = 1.0;
-      terms.push_back(t);
-      g.term_end = (int32_t)terms.size();
-      const int gi = (int)groups.size();
-      groups.push_back(g);
-      for (int tt = 0; tt < ((g.m + 63) / 64) * g.tiles_n; ++tt) tiles.push_back(GemmTile{gi, tt});
+      gb.group(BASE_Y, e.offset, e.ld, e.rows, e.cols, false);
+      gb.term(BASE_X, c_off[q_old] + M.col_off[col], M.ncols, BASE_MPS, Bb.off, Bb.cols, Bb.rows, 1.0);
     }
-    if (!tiles.empty()) {
-      DevBuf dt, dg, dl;
-      upload(dt, terms, st);
-      upload(dg, groups, st);
-      upload(dl, tiles, st);
+    if (!gb.groups.empty()) {
+      const std::vector<GemmLaunch> Ls = finalize(gb, false, false, st);
       Bases<double> bs{};
       bs.p[BASE_X] = C.as<double>();
       bs.p[BASE_MPS] = S.mps.data.as<double>();
       bs.p[BASE_Y] = S.guess.as<double>();
-      check_hip(launch_gemm_f64(dt.as<GemmTerm>(), dg.as<GemmGroup>(), dl.as<GemmTile>(), (int)tiles.size(), false,
-                                false, TILE_64x64, bs, st),
-                "guess gemm");
+      run_gemm64(Ls, bs, st);
       check_hip(hipStreamSynchronize(st), "guess");
     }
   }

@@ -27,7 +27,8 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_env_profile_apply", "lcc_lowest_eigenvalue", "lcc_env_profile_launches", "lcc_batch_create",
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
-           "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values"]
+           "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
+           "lcc_env_autotune"]
 
 
 class LccError(RuntimeError):
@@ -79,7 +80,13 @@ class SolveInfo(C.Structure):
 class LaunchProfile(C.Structure):
     _fields_ = [("phase", C.c_int32), ("kind", C.c_int32), ("tile_m", C.c_int32), ("tile_n", C.c_int32),
                 ("n_tiles", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double), ("bytes", C.c_double),
-                ("ms", C.c_float), ("pad", C.c_float)]
+                ("exec_flops", C.c_double), ("ms", C.c_float), ("pad", C.c_float)]
+
+
+class TuneInfo(C.Structure):
+    _fields_ = [("tile_overhead", C.c_double), ("split_k", C.c_int64), ("candidates", C.c_int32),
+                ("launches", C.c_int32), ("packed_launches", C.c_int32), ("from_cache", C.c_int32),
+                ("ms_before", C.c_float), ("ms_after", C.c_float)]
 
 
 class SweepInfo(C.Structure):
@@ -124,6 +131,8 @@ def library() -> C.CDLL:
                                                  C.POINTER(LaunchProfile)]),
         "lcc_batch_create": (C.c_int32, [P, C.c_int32, C.POINTER(P), C.POINTER(P)]),
         "lcc_context_set_intermediate_limit": (C.c_int32, [P, C.c_int64]),
+        "lcc_context_set_tune_cache": (C.c_int32, [P, C.c_char_p]),
+        "lcc_env_autotune": (C.c_int32, [P, C.c_int32, C.c_int32, C.POINTER(TuneInfo)]),
         "lcc_sweep_create": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
         "lcc_sweep_destroy": (None, [P]),
         "lcc_sweep_env": (C.c_int32, [P, C.POINTER(P)]),
@@ -197,6 +206,11 @@ class Context:
 
     def set_intermediate_limit(self, nbytes: int):
         _check(library().lcc_context_set_intermediate_limit(self.handle, int(nbytes)), self.handle)
+
+    def set_tune_cache(self, path):
+        """Autotuning results file (read when environments are built, appended by autotune)."""
+        _check(library().lcc_context_set_tune_cache(self.handle, None if path is None else str(path).encode()),
+               self.handle)
 
     def create_hamiltonian(self, spec: dict, switch_bond: int = -1) -> "Hamiltonian":
         return create_hamiltonian(self, spec, switch_bond)
@@ -367,7 +381,16 @@ class Env:
         _check(lib.lcc_env_profile_launches(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n),
                                             _tensor_ptr(y, dt, self.n), reps, C.byref(cnt), arr), self.ctx.handle)
         return [{"phase": a.phase, "kind": "gemm" if a.kind == 0 else "reduce", "tile": (a.tile_m, a.tile_n),
-                 "n_tiles": a.n_tiles, "flops": a.flops, "bytes": a.bytes, "ms": a.ms} for a in arr[: cnt.value]]
+                 "n_tiles": a.n_tiles, "flops": a.flops, "bytes": a.bytes, "exec_flops": a.exec_flops, "ms": a.ms}
+                for a in arr[: cnt.value]]
+
+    def autotune(self, precision: str = "fp32", reps: int = 3) -> dict:
+        """Time the planner candidates and both GEMM kernels per launch; keep the fastest."""
+        info = TuneInfo()
+        _check(library().lcc_env_autotune(self.handle, PRECISIONS[precision], reps, C.byref(info)), self.ctx.handle)
+        return {"tile_overhead": info.tile_overhead, "split_k": info.split_k, "candidates": info.candidates,
+                "launches": info.launches, "packed_launches": info.packed_launches,
+                "from_cache": bool(info.from_cache), "ms_before": info.ms_before, "ms_after": info.ms_after}
 
     def lowest_eigenvalue(self, steps: int = 60, seed: int = 1):
         th, res = C.c_double(), C.c_double()
