@@ -43,7 +43,7 @@ def source_digest() -> str:
     """sha1 of the sources that determine the GEMM kernels and the plan they run."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("kernels.hip", "env.cpp", "internal.h"):
+    for f in ("kernels.hip", "env.cpp", "internal.h", "tune.cpp"):
         with open(os.path.join(ROOT, "paper_1509_00216_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -56,10 +56,11 @@ def kernel_name(precision: str, launch: dict) -> str:
     bm, bn = launch["tile"]
     waves = {(64, 64): (2, 2), (16, 64): (1, 4), (64, 16): (4, 1), (32, 32): (2, 2), (128, 64): (2, 2),
              (64, 128): (2, 2), (32, 64): (2, 2), (64, 32): (2, 2)}[(bm, bn)]
+    kind = "packed" if launch.get("packed") else "terms"
     if precision == "bf16x3":
-        return f"gemm_bf16x3_kernel<false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
+        return f"gemm_bf16x3_{kind}_kernel<false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
     mode = 0 if precision == "fp64" else 1
-    return f"gemm_mfma_kernel<{mode}, false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
+    return f"gemm_{kind}_kernel<{mode}, false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
 
 
 def measured_traffic(kname: str, workload: str):
@@ -118,6 +119,157 @@ def cpu_baseline(sample_seconds_target=20.0):
     }
 
 
+SHIPPED_TUNE_CACHE = os.path.join(ROOT, "paper_1509_00216_amd", "tune_cache.txt")
+
+
+def working_tune_cache(path: str) -> str:
+    """A private copy of the tuning cache (entries found by this run are appended there, the
+    shipped file is left as it is)."""
+    import shutil
+    import tempfile
+    fd, tmp = tempfile.mkstemp(prefix="lcc_tune_", suffix=".txt")
+    os.close(fd)
+    if path and os.path.exists(path):
+        shutil.copyfile(path, tmp)
+    return tmp
+
+
+def run_tune(args):
+    """Autotune the named workloads' environments and append the results to --tune-cache."""
+    import torch
+    from paper_1509_00216_amd import lcc
+    from workloads import configs as C
+    torch.cuda.init()
+    for name in args.tune_workloads.split(","):
+        spec, mps = C.make(name)
+        ctx = lcc.Context(0)
+        ctx.set_tune_cache(args.tune_cache)
+        env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
+        info = env.autotune("fp32", reps=5)
+        print(json.dumps({"mode": "tune", "workload": name, **info}), flush=True)
+        env.close()
+
+
+def run_batch(args):
+    """64 independent local problems (ab initio K=24, 4x4 Hubbard, 3-band cluster; M uniform in
+    [128, 1500], jittered sector weights): one batched mixed-precision solve (merged launches,
+    graph-replayed iterations) against the 64 problems solved one after another in FP64."""
+    import torch
+    from paper_1509_00216_amd import lcc
+    from workloads import configs as C
+    from workloads import mps as M
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    ctx = lcc.Context(0)
+    ctx.set_intermediate_limit(args.batch_intermediate_mib << 20)
+    members = C.batch_members(args.batch_n)
+    envs, bs, e0s, flops = [], [], [], []
+    hams = {}
+    t0 = time.perf_counter()
+    for i, (parent, m, seed) in enumerate(members):
+        spec, mps = C.make_member(parent, m, seed)
+        if parent not in hams:
+            hams[parent] = ctx.create_hamiltonian(spec)
+        env = ctx.build_environments(hams[parent], mps)
+        e0, _ = shift_for(spec, env, parent)
+        envs.append(env)
+        e0s.append(e0)
+        flops.append(env.flops_per_apply)
+        bs.append(torch.tensor(env.pack(M.random_two_site_vector(mps, seed + 7)), dtype=torch.float64, device=dev))
+        log(f"[batch] member {i}: {parent} M={m} n={env.n} F={env.flops_per_apply:.3e} E0={e0:.6f}")
+    t_setup = time.perf_counter() - t0
+    xs = [torch.zeros_like(b) for b in bs]
+    batch = lcc.Batch(ctx, envs)
+    status, infos = batch.solve(bs, e0s, xs, precision=args.precision, tol=1e-10, max_iter=5000)  # warm-up
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for x in xs:
+            x.zero_()
+        status, infos = batch.solve(bs, e0s, xs, precision=args.precision, tol=1e-10, max_iter=5000)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / reps
+    # sequential FP64 baseline on the same problems
+    seq = []
+    x1 = [torch.zeros_like(b) for b in bs]
+    envs[0].solve_local_lcc(bs[0], e0s[0], x1[0], precision="fp64", tol=1e-10, max_iter=5000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for env, b, e0, x in zip(envs, bs, e0s, x1):
+        x.zero_()
+        seq.append(env.solve_local_lcc(b, e0, x, precision="fp64", tol=1e-10, max_iter=5000))
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3
+    dE = [abs(a["hylleraas"] - b["hylleraas"]) for a, b in zip(infos, seq)]
+    applies = sum(i["applies_fp64"] + i["applies_low"] for i in infos) / len(infos)
+    out = {"mode": "batch", "problems": len(envs), "precision": args.precision, "status": status,
+           "ms_batched_mixed": ms_batch, "ms_sequential_fp64": ms_seq, "speedup": ms_seq / ms_batch,
+           "max_energy_diff": max(dE), "max_rel_residual": max(i["rel_residual"] for i in infos),
+           "mean_applies_per_problem": applies, "flops_per_apply_total": sum(flops),
+           "gflops_batched": sum(f * (i["applies_fp64"] + i["applies_low"]) for f, i in zip(flops, infos)) /
+           (ms_batch * 1e-3) / 1e9,
+           "setup_s": t_setup, "intermediate_limit_mib": args.batch_intermediate_mib,
+           "members": [{"parent": p, "m": m} for p, m, _ in members]}
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep(args):
+    """One left-to-right sweep of two-site local solves over the 4x4 Hubbard model (K=16,
+    M=500): solve, SVD split, truncation, left-environment update, next guess; FP64 solves
+    against mixed-precision solves (separate sweeps from the same start)."""
+    import torch
+    from paper_1509_00216_amd import lcc
+    from workloads import configs as C
+    from workloads import mps as M
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    name = "hubbard2d_4x4_m500"
+    spec, mps = C.make(name, center=0)
+    e0 = C.lower_bound_shift(spec, 0.5)
+    ctx = lcc.Context(0)
+    ctx.set_tune_cache(working_tune_cache(args.tune_cache))
+    ham = ctx.create_hamiltonian(spec)
+    m_max = C.WORKLOADS[name][1]
+    out = {"mode": "sweep", "workload": name, "m_max": m_max, "e0": e0}
+    for prec in ("fp64", args.precision):
+        sw = lcc.Sweep(ctx, ham, mps, 0)
+        env = sw.env()
+        b = torch.tensor(env.pack(M.random_two_site_vector(mps, 77)), dtype=torch.float64, device=dev)
+        sites = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        t_solve = 0.0
+        for l in range(spec["n_orb"] - 1):
+            x = torch.zeros_like(b)
+            t0 = time.perf_counter()
+            info = env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-10, max_iter=5000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            t_solve += dt
+            rec = {"site": l, "n": env.n, "ms": dt * 1e3, "iterations": info["iterations"], "J": info["hylleraas"],
+                   "status": info["status"]}
+            if l + 1 < spec["n_orb"] - 1:
+                split = sw.advance(x, m_max)
+                rec["kept"] = split["kept"]
+                rec["discarded_weight"] = split["discarded_weight"]
+                env = sw.env()
+                b = torch.empty(env.n, dtype=torch.float64, device=dev)
+                sw.guess(b)
+                b /= b.norm()
+            sites.append(rec)
+        torch.cuda.synchronize()
+        out[prec] = {"sweep_ms": (time.perf_counter() - t_start) * 1e3, "solve_ms": t_solve * 1e3, "sites": sites}
+        sw.close()
+        log(f"[sweep] {prec}: {out[prec]['sweep_ms']:.1f} ms")
+    a, b2 = out["fp64"]["sites"], out[args.precision]["sites"]
+    out["max_J_diff"] = max(abs(x["J"] - y["J"]) for x, y in zip(a, b2))
+    out["speedup_solves"] = out["fp64"]["solve_ms"] / out[args.precision]["solve_ms"]
+    out["speedup_sweep"] = out["fp64"]["sweep_ms"] / out[args.precision]["sweep_ms"]
+    print(json.dumps(out), flush=True)
+
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,10 +284,26 @@ def main():
                     help="profiling mode: build, run N plain H_eff x products of --apply-precision and a "
                          "256 MiB device copy (counter calibration), print timings, skip the solves")
     ap.add_argument("--apply-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "sweep", "tune"],
+                    help="solve: the headline local solve (default); batch: 64 independent problems, batched "
+                         "mixed vs sequential FP64; sweep: one sweep of the 4x4 Hubbard model; tune: autotune "
+                         "--tune-workloads into --tune-cache")
+    ap.add_argument("--tune-cache", default=SHIPPED_TUNE_CACHE)
+    ap.add_argument("--tune-workloads", default="abinitio_k24_m1000,threeband_4x2_m2000,hubbard2d_4x4_m500")
+    ap.add_argument("--no-tune", action="store_true", help="plan with the default planner parameters")
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--batch-intermediate-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "tune":
+        return run_tune(args)
+    if args.mode == "batch":
+        return run_batch(args)
+    if args.mode == "sweep":
+        return run_sweep(args)
 
     import torch
     from paper_1509_00216_amd import lcc
@@ -147,6 +315,8 @@ def main():
     log(f"[bench] workload {args.workload}: generating inputs")
     spec, mps = C.make(args.workload)
     ctx = lcc.Context(0)
+    if not args.no_tune:
+        ctx.set_tune_cache(working_tune_cache(args.tune_cache))
     t0 = time.perf_counter()
     ham = ctx.create_hamiltonian(spec)
     t_ham = time.perf_counter() - t0
@@ -157,6 +327,12 @@ def main():
     f1, f2 = env.flops()
     F = f1 + f2
     log(f"[bench] environments in {t_env:.2f}s: n={env.n} D_mid={env.mpo_bond_dim} F_alg={F:.4e} (phase1 {f1:.3e}, phase2 {f2:.3e})")
+    tune = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tune = env.autotune("fp32", reps=3)
+        tune["seconds"] = time.perf_counter() - t0
+        log(f"[bench] plan: {tune}")
     if args.apply_only > 0:
         prec = args.apply_precision
         xx = torch.tensor(env.pack(M.random_two_site_vector(mps, 17)), dtype=torch.float64, device=dev)
@@ -269,6 +445,7 @@ def main():
                       PEAK_TFLOPS["bf16" if p == "bf16x3" else p]}
                   for p, v in applies.items()},
         "roofline": roofline,
+        "plan": tune,
         "setup_s": {"mpo": t_ham, "environments": t_env},
     }
     if not args.no_cpu_baseline:

@@ -183,7 +183,7 @@ typedef struct {
   int32_t tile_m;   /* workgroup tile rows (GEMM) */
   int32_t tile_n;   /* workgroup tile columns (GEMM) */
   int32_t n_tiles;  /* workgroups in the launch */
-  int32_t reserved;
+  int32_t packed;   /* GEMM kernel: 0 = term walk, 1 = packed k */
   double flops;     /* algorithmic flops of the launch (2 m n k over its block products) */
   double bytes;     /* algorithmic bytes: operands read once + outputs written once */
   double exec_flops; /* MFMA work issued, including tile padding and the 16-wide k groups */

@@ -79,7 +79,7 @@ class SolveInfo(C.Structure):
 
 class LaunchProfile(C.Structure):
     _fields_ = [("phase", C.c_int32), ("kind", C.c_int32), ("tile_m", C.c_int32), ("tile_n", C.c_int32),
-                ("n_tiles", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double), ("bytes", C.c_double),
+                ("n_tiles", C.c_int32), ("packed", C.c_int32), ("flops", C.c_double), ("bytes", C.c_double),
                 ("exec_flops", C.c_double), ("ms", C.c_float), ("pad", C.c_float)]
 
 
@@ -381,7 +381,8 @@ class Env:
         _check(lib.lcc_env_profile_launches(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n),
                                             _tensor_ptr(y, dt, self.n), reps, C.byref(cnt), arr), self.ctx.handle)
         return [{"phase": a.phase, "kind": "gemm" if a.kind == 0 else "reduce", "tile": (a.tile_m, a.tile_n),
-                 "n_tiles": a.n_tiles, "flops": a.flops, "bytes": a.bytes, "exec_flops": a.exec_flops, "ms": a.ms}
+                 "n_tiles": a.n_tiles, "packed": bool(a.packed), "flops": a.flops, "bytes": a.bytes,
+                 "exec_flops": a.exec_flops, "ms": a.ms}
                 for a in arr[: cnt.value]]
 
     def autotune(self, precision: str = "fp32", reps: int = 3) -> dict:
