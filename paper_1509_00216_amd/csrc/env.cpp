@@ -106,7 +106,16 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
     std::vector<GemmTile> tiles;
     GemmLaunch L;
     std::set<std::pair<int, int64_t>> seen;
-    for (const GemmGroup& g0 : b.groups) {
+    // groups in order of decreasing accumulation length, so that the long tiles start first
+    // and the short ones fill the tail of the launch
+    std::vector<int64_t> gcost(b.groups.size(), 0);
+    for (size_t i = 0; i < b.groups.size(); ++i)
+      for (int t = b.groups[i].term_begin; t < b.groups[i].term_end; ++t) gcost[i] += (b.terms[t].k + 3) / 4 * 4;
+    std::vector<int> order(b.groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gcost[x] > gcost[y]; });
+    for (int oi : order) {
+      const GemmGroup& g0 = b.groups[oi];
       if (g0.m <= 0 || g0.n <= 0) continue;
       if (shape_for(g0.m, g0.n, tile_overhead) != shape) continue;
       GemmGroup g = g0;

@@ -20,13 +20,18 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;
 
-// Workgroups are dispatched round-robin over the 8 XCDs; renumber so that consecutive
-// logical tiles (which share operands) run on the same XCD and share its L2.
+// Workgroups are dispatched round-robin over the 8 XCDs.  Tiles are handed out in runs of
+// kTileRun consecutive tiles per XCD (run r goes to XCD r mod 8): consecutive tiles belong to
+// the same output block and share operand panels, which then meet in one XCD's L2, while the
+// interleaving of runs keeps the work of every XCD a uniform sample of the launch (a
+// contiguous slice per XCD leaves XCDs idle when block sizes vary along the tile list).  The
+// tail of the grid that does not fill whole rounds keeps the plain order.
+constexpr int kTileRun = 16;
 __device__ __forceinline__ int xcd_remap(int bid, int n) {
-  const int q = n >> 3, r = n & 7;
+  const int full = n / (8 * kTileRun) * (8 * kTileRun);
+  if (bid >= full) return bid;
   const int xcd = bid & 7, local = bid >> 3;
-  const int start = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
-  return start + local;
+  return ((local / kTileRun) * 8 + xcd) * kTileRun + (local % kTileRun);
 }
 
 template <int MODE>
