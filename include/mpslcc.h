@@ -197,7 +197,9 @@ lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const 
  * sectors and dimensions, MPO bond dimension).  Times on the device every candidate of the
  * planner parameters (tile_overhead in {512, 2048, 8192}: per-tile cost, in output
  * elements, of the tile-shape choice; split_k in {1024, 2048, 4096}: accumulation length of
- * a phase-2 split-K part) and, per GEMM launch, both kernels (term walk / packed k), with
+ * a phase-2 split-K part; p2_order in {0, 1}: phase-2 output blocks one after the other, or
+ * their parts interleaved by channel so that parts reading the same intermediate columns are
+ * neighbours) and, per GEMM launch, both kernels (term walk / packed k), with
  * `reps` timed applications of `precision` per measurement; keeps the fastest plan and
  * chooses the kernels of all three precisions on it.  With a tuning cache set on the
  * context (lcc_context_set_tune_cache) the choice is appended to it, and an entry already
@@ -212,6 +214,8 @@ typedef struct {
   int32_t launches;           /* GEMM launches of the chosen plan */
   int32_t packed_launches;    /* ... of which use the packed-k kernel for `precision` */
   int32_t from_cache;         /* 1 if the entry came from the cache */
+  int32_t p2_order;           /* phase-2 group order: 0 output-major, 1 channel-major */
+  int32_t reserved;
   float ms_before, ms_after;  /* one H_eff x of `precision`, summed launch times */
 } lcc_tune_info;
 lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, lcc_tune_info* info);

@@ -96,7 +96,8 @@ int shape_for(int m, int n, double tile_overhead) {
 
 // One launch per tile shape.  Each term is cut into k-quads (SlotRec) whose A / B offsets
 // point at the quad's first k, so the kernel walks a group's terms as one packed k stream.
-std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s, double tile_overhead) {
+std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s, double tile_overhead,
+                                 bool longest_first) {
   std::vector<GemmLaunch> out;
   for (int shape = 0; shape < kNumTileShapes; ++shape) {
     const int bm = kTileShapes[shape][0], bn = kTileShapes[shape][1];
@@ -106,14 +107,15 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
     std::vector<GemmTile> tiles;
     GemmLaunch L;
     std::set<std::pair<int, int64_t>> seen;
-    // groups in order of decreasing accumulation length, so that the long tiles start first
-    // and the short ones fill the tail of the launch
+    // longest_first: groups in order of decreasing accumulation length, so that the long tiles
+    // start first and the short ones fill the tail of the launch; else in the builder's order
     std::vector<int64_t> gcost(b.groups.size(), 0);
     for (size_t i = 0; i < b.groups.size(); ++i)
       for (int t = b.groups[i].term_begin; t < b.groups[i].term_end; ++t) gcost[i] += (b.terms[t].k + 3) / 4 * 4;
     std::vector<int> order(b.groups.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gcost[x] > gcost[y]; });
+    if (longest_first)
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gcost[x] > gcost[y]; });
     for (int oi : order) {
       const GemmGroup& g0 = b.groups[oi];
       if (g0.m <= 0 || g0.n <= 0) continue;
@@ -624,13 +626,23 @@ void plan_env(Env& E, const PlanParams& pp) {
   std::vector<ReduceGroup> red;
   int64_t work = 0;
   double flops2 = 0;
+  // A phase-2 group (one output block, or one split-K part of it) before emission.
+  struct Emit {
+    int chunk = 0, first_w1 = -1, jx = 0;
+    int8_t c_base = BASE_Y;
+    int64_t c_off = 0;
+    int ldc = 0, m = 0, n = 0;
+    std::vector<GemmTerm> terms;
+  };
   for (int mp = 0; mp < nsec; ++mp) {
     const MiddleSector& Sp = env->sectors[mp];
+    std::vector<Emit> emits;
     for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
       const int s2p = Sp.cols[jx].first, bp = Sp.cols[jx].second;
       const int gm = Sp.nrows, gn = br.dim[bp];
       const int64_t y_off = Sp.off + Sp.col_off[jx];
       std::vector<std::vector<GemmTerm>> per(nchunks);
+      std::vector<std::vector<int>> per_w1(nchunks);
       for (int w1 = 0; w1 < D; ++w1) {
         auto si = sec_index.find(Sp.q - dq_mid[w1]);
         if (si == sec_index.end()) continue;
@@ -655,6 +667,7 @@ void plan_env(Env& E, const PlanParams& pp) {
           t.k = kb;
           t.alpha = ref.alpha;
           per[chunk_of[w1]].push_back(t);
+          per_w1[chunk_of[w1]].push_back(w1);
           flops2 += 2.0 * gm * (double)gn * kb;
         }
       }
@@ -682,24 +695,34 @@ void plan_env(Env& E, const PlanParams& pp) {
         }
       }
       if (parts.size() <= 1) {
-        const int c = parts.empty() ? 0 : parts[0].chunk;
-        p2[c].group(BASE_Y, y_off, Sp.ncols, gm, gn, false);
+        Emit em;
+        em.chunk = parts.empty() ? 0 : parts[0].chunk;
+        em.first_w1 = parts.empty() || parts[0].b == parts[0].e ? -1 : per_w1[em.chunk][parts[0].b];
+        em.jx = (int)jx;
+        em.c_base = BASE_Y;
+        em.c_off = y_off;
+        em.ldc = Sp.ncols;
+        em.m = gm;
+        em.n = gn;
         if (!parts.empty())
-          for (size_t i = parts[0].b; i < parts[0].e; ++i) {
-            p2[c].terms.push_back(per[c][i]);
-            p2[c].groups.back().term_end = (int32_t)p2[c].terms.size();
-          }
+          em.terms.assign(per[em.chunk].begin() + parts[0].b, per[em.chunk].begin() + parts[0].e);
+        emits.push_back(std::move(em));
         continue;
       }
       const int64_t mn = (int64_t)gm * gn;
       const int64_t woff = work;
       for (size_t p = 0; p < parts.size(); ++p) {
-        GemmBuilder& B2 = p2[parts[p].chunk];
-        B2.group(BASE_WORK, woff + (int64_t)p * mn, gn, gm, gn, false);
-        for (size_t i = parts[p].b; i < parts[p].e; ++i) {
-          B2.terms.push_back(per[parts[p].chunk][i]);
-          B2.groups.back().term_end = (int32_t)B2.terms.size();
-        }
+        Emit em;
+        em.chunk = parts[p].chunk;
+        em.first_w1 = per_w1[em.chunk][parts[p].b];
+        em.jx = (int)jx;
+        em.c_base = BASE_WORK;
+        em.c_off = woff + (int64_t)p * mn;
+        em.ldc = gn;
+        em.m = gm;
+        em.n = gn;
+        em.terms.assign(per[em.chunk].begin() + parts[p].b, per[em.chunk].begin() + parts[p].e);
+        emits.push_back(std::move(em));
       }
       work += (int64_t)parts.size() * mn;
       ReduceGroup rg{};
@@ -711,6 +734,21 @@ void plan_env(Env& E, const PlanParams& pp) {
       rg.parts = (int32_t)parts.size();
       red.push_back(rg);
     }
+    // Emission order of the sector's groups.  Output-major (0): block by block, each block's
+    // parts in channel order.  Channel-major (1): by the first channel of each part, so that
+    // the parts of different output blocks that read the same intermediate columns are
+    // neighbours in the tile list (and in one XCD's L2).
+    if (pp.p2_order == 1)
+      std::stable_sort(emits.begin(), emits.end(), [](const Emit& a, const Emit& b) {
+        if (a.chunk != b.chunk) return a.chunk < b.chunk;
+        return a.first_w1 != b.first_w1 ? a.first_w1 < b.first_w1 : a.jx < b.jx;
+      });
+    for (Emit& em : emits) {
+      GemmBuilder& B2 = p2[em.chunk];
+      B2.group(em.c_base, em.c_off, em.ldc, em.m, em.n, false);
+      for (const GemmTerm& t : em.terms) B2.terms.push_back(t);
+      B2.groups.back().term_end = (int32_t)B2.terms.size();
+    }
   }
   double flops1 = 0;
   for (const GemmBuilder& B1 : p1) flops1 += B1.flops;
@@ -719,7 +757,7 @@ void plan_env(Env& E, const PlanParams& pp) {
   env->plan.chunks.resize(nchunks);
   for (int c = 0; c < nchunks; ++c) {
     env->plan.chunks[c].phase1 = finalize(p1[c], false, false, st, pp.tile_overhead);
-    env->plan.chunks[c].phase2 = finalize(p2[c], false, true, st, pp.tile_overhead);
+    env->plan.chunks[c].phase2 = finalize(p2[c], false, true, st, pp.tile_overhead, pp.p2_order == 0);
   }
   {
     std::vector<ReduceTile> rtl;

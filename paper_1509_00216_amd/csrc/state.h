@@ -54,6 +54,7 @@ void upload(DevBuf& buf, const std::vector<T>& v, hipStream_t s) {
 struct PlanParams {
   double tile_overhead = 2048.0;  // per-tile cost, in output elements, of the tile-shape choice
   int64_t split_k = 2048;         // accumulation length per phase-2 part (split-K)
+  int p2_order = 0;               // phase-2 group order: 0 output-major, 1 channel-major
 };
 
 struct Context {
@@ -126,7 +127,8 @@ struct GemmBuilder {
   void term(int8_t a_base, int64_t a_off, int lda, int8_t b_base, int64_t b_off, int ldb, int k, double alpha);
 };
 // tile_overhead: per-tile cost (in output elements) of the shape choice, see shape_for
-std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s, double tile_overhead = 2048.0);
+std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStream_t s, double tile_overhead = 2048.0,
+                                 bool longest_first = true);
 void run_gemm64(const std::vector<GemmLaunch>& Ls, const Bases<double>& b, hipStream_t s);
 
 struct Plan {

@@ -3,7 +3,7 @@
 // The block-size histogram of a two-site problem (bond sectors and their dimensions, the MPO
 // bond dimension) fixes the shapes of all block products.  For a histogram the tuner times,
 // on the device, every candidate of the planner parameters (the per-tile cost that picks tile
-// shapes, the split-K length of phase 2) and, for every launch of a plan, both GEMM kernels
+// shapes, the split-K length and the group order of phase 2) and, for every launch of a plan, both GEMM kernels
 // (term walk, packed k), then keeps the fastest plan and per-launch kernel choice.  The result
 // is stored in a text cache keyed by a signature of the histogram, so that later environments
 // with the same histogram (the same site of another sweep, another process) are planned the
@@ -52,6 +52,10 @@ bool set_flags(Env& env, int precision, const std::string& f) {
   return true;
 }
 
+bool same_params(const PlanParams& a, const PlanParams& b) {
+  return a.tile_overhead == b.tile_overhead && a.split_k == b.split_k && a.p2_order == b.p2_order;
+}
+
 struct Entry {
   PlanParams pp;
   std::string flags[3];
@@ -66,7 +70,8 @@ bool cache_find(const std::string& path, uint64_t sig, Entry& e) {
     std::istringstream ls(line);
     unsigned long long s = 0;
     Entry x;
-    if (!(ls >> std::hex >> s >> std::dec >> x.pp.tile_overhead >> x.pp.split_k >> x.flags[0] >> x.flags[1] >> x.flags[2]))
+    if (!(ls >> std::hex >> s >> std::dec >> x.pp.tile_overhead >> x.pp.split_k >> x.pp.p2_order >> x.flags[0] >>
+          x.flags[1] >> x.flags[2]))
       continue;
     if (s == sig) {
       e = x;
@@ -82,8 +87,8 @@ void cache_add(const std::string& path, uint64_t sig, const Entry& e) {
   if (!out) throw Error{LCC_ERR_ARG, "cannot write the tuning cache " + path};
   char head[64];
   std::snprintf(head, sizeof head, "%016llx", (unsigned long long)sig);
-  out << head << " " << e.pp.tile_overhead << " " << e.pp.split_k << " " << e.flags[0] << " " << e.flags[1] << " "
-      << e.flags[2] << "\n";
+  out << head << " " << e.pp.tile_overhead << " " << e.pp.split_k << " " << e.pp.p2_order << " " << e.flags[0] << " "
+      << e.flags[1] << " " << e.flags[2] << "\n";
 }
 
 // Per-launch mean times (ms) of one apply with every launch on the packed (or term-walk) kernel.
@@ -146,7 +151,7 @@ uint64_t histogram_signature(const Env& env) {
 bool apply_tuned(Env& env) {
   Entry e;
   if (!cache_find(env.ctx->tune_cache, histogram_signature(env), e)) return false;
-  if (e.pp.tile_overhead != env.params.tile_overhead || e.pp.split_k != env.params.split_k) plan_env(env, e.pp);
+  if (!same_params(e.pp, env.params)) plan_env(env, e.pp);
   for (int p = 0; p < 3; ++p) set_flags(env, p, e.flags[p]);
   return true;
 }
@@ -175,8 +180,7 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info) {
   Entry cached;
   if (cache_find(env.ctx->tune_cache, sig, cached)) {
     out.ms_before = (float)total_ms(env, precision, x.p, y.p, reps);
-    if (cached.pp.tile_overhead != env.params.tile_overhead || cached.pp.split_k != env.params.split_k)
-      plan_env(env, cached.pp);
+    if (!same_params(cached.pp, env.params)) plan_env(env, cached.pp);
     for (int p = 0; p < 3; ++p) set_flags(env, p, cached.flags[p]);
     out.from_cache = 1;
   } else {
@@ -185,10 +189,12 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info) {
     PlanParams best_pp = env.params;
     double best = 1e300;
     for (double ov : kOverheads)
-      for (int64_t sk : kSplits) {
+      for (int64_t sk : kSplits)
+      for (int order = 0; order < 2; ++order) {
         PlanParams pp;
         pp.tile_overhead = ov;
         pp.split_k = sk;
+        pp.p2_order = order;
         plan_env(env, pp);
         const double t = choose_kernels(env, precision, x.p, y.p, reps);
         ++out.candidates;
@@ -222,6 +228,7 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info) {
   }
   out.tile_overhead = env.params.tile_overhead;
   out.split_k = env.params.split_k;
+  out.p2_order = env.params.p2_order;
   out.ms_after = (float)total_ms(env, precision, x.p, y.p, reps);
   for (GemmLaunch* L : launches_of(env)) {
     ++out.launches;

@@ -86,7 +86,7 @@ class LaunchProfile(C.Structure):
 class TuneInfo(C.Structure):
     _fields_ = [("tile_overhead", C.c_double), ("split_k", C.c_int64), ("candidates", C.c_int32),
                 ("launches", C.c_int32), ("packed_launches", C.c_int32), ("from_cache", C.c_int32),
-                ("ms_before", C.c_float), ("ms_after", C.c_float)]
+                ("p2_order", C.c_int32), ("reserved", C.c_int32), ("ms_before", C.c_float), ("ms_after", C.c_float)]
 
 
 class SweepInfo(C.Structure):
@@ -389,7 +389,8 @@ class Env:
         """Time the planner candidates and both GEMM kernels per launch; keep the fastest."""
         info = TuneInfo()
         _check(library().lcc_env_autotune(self.handle, PRECISIONS[precision], reps, C.byref(info)), self.ctx.handle)
-        return {"tile_overhead": info.tile_overhead, "split_k": info.split_k, "candidates": info.candidates,
+        return {"tile_overhead": info.tile_overhead, "split_k": info.split_k, "p2_order": info.p2_order,
+                "candidates": info.candidates,
                 "launches": info.launches, "packed_launches": info.packed_launches,
                 "from_cache": bool(info.from_cache), "ms_before": info.ms_before, "ms_after": info.ms_after}
 
