@@ -243,7 +243,8 @@ def run_sweep(args):
         for l in range(spec["n_orb"] - 1):
             x = torch.zeros_like(b)
             t0 = time.perf_counter()
-            info = env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-10, max_iter=5000)
+            info = env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-10, max_iter=5000, inner_tol=args.inner_tol,
+                                       max_outer=200)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             t_solve += dt
@@ -253,6 +254,7 @@ def run_sweep(args):
                 split = sw.advance(x, m_max)
                 rec["kept"] = split["kept"]
                 rec["discarded_weight"] = split["discarded_weight"]
+                rec["advance_ms"] = {k: split[k] for k in ("ms_svd", "ms_env", "ms_guess", "ms_total")}
                 env = sw.env()
                 b = torch.empty(env.n, dtype=torch.float64, device=dev)
                 sw.guess(b)
@@ -291,6 +293,8 @@ def main():
     ap.add_argument("--tune-cache", default=SHIPPED_TUNE_CACHE)
     ap.add_argument("--tune-workloads", default="abinitio_k24_m1000,threeband_4x2_m2000,hubbard2d_4x4_m500")
     ap.add_argument("--no-tune", action="store_true", help="plan with the default planner parameters")
+    ap.add_argument("--inner-tol", type=float, default=1e-3,
+                    help="mixed precision: residual reduction between FP64 refreshes")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-intermediate-mib", type=int, default=1024)
     args = ap.parse_args()
@@ -374,7 +378,8 @@ def main():
 
     def solve(prec):
         x.zero_()
-        return env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-10, max_iter=5000)
+        return env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-10, max_iter=5000, inner_tol=args.inner_tol,
+                                   max_outer=200)
 
     for i in range(args.warmup):
         info = solve(args.precision)
@@ -434,7 +439,7 @@ def main():
                    "two_sz": spec["two_sz"], "m_max": C.WORKLOADS[args.workload][1], "site": mps["center"],
                    "vector_elements": env.n, "mpo_bond_dim_mid": env.mpo_bond_dim, "flops_per_apply": F,
                    "parallelism": "single GPU"},
-        "solve": {"precision": args.precision, "ms": ms_step, "iterations": infos[-1]["iterations"],
+        "solve": {"precision": args.precision, "inner_tol": args.inner_tol or 0.1, "ms": ms_step, "iterations": infos[-1]["iterations"],
                   "outer": infos[-1]["outer"], "applies_fp64": infos[-1]["applies_fp64"],
                   "applies_low": infos[-1]["applies_low"], "hylleraas": j_mixed,
                   "rel_residual": infos[-1]["rel_residual"], "e0": e0,

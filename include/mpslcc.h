@@ -280,6 +280,10 @@ typedef struct {
   int32_t reserved;
   double discarded_weight;    /* sum of discarded s^2 / sum of all s^2 */
   double largest_discarded;   /* largest discarded singular value (0 if none) */
+  float ms_svd;               /* wall time: per-sector SVDs */
+  float ms_env;               /* wall time: left-environment step and the next block's plan */
+  float ms_guess;             /* wall time: next guess */
+  float ms_total;             /* wall time of the call */
 } lcc_sweep_info;
 /* MPS as for lcc_build_environments with the block at first_site.  Synchronous. */
 lcc_status lcc_sweep_create(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t first_site,

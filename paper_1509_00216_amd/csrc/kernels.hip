@@ -128,10 +128,10 @@ __device__ __forceinline__ void lds_write_quad(double* p, double a, double b, do
 }
 
 // OP 0: operand A (rows = output rows, scaled by the quad's alpha); OP 1: operand B.
-template <class T, bool KC, int R, int BK, int OP>
+template <class T, bool KC, int R, int BK, int OP, int NT>
 struct Stager {
   static constexpr int QUADS = R * BK / 4;
-  static constexpr int NQ = (QUADS + kThreads - 1) / kThreads;
+  static constexpr int NQ = (QUADS + NT - 1) / NT;
   static constexpr int SPC = BK / 4;
   static constexpr int PAD = 16 / (int)sizeof(T);
   // LDS tile of the FP64/FP32 kernel mirrors the stored layout: [R][BK] if KC, else [BK][R]
@@ -140,7 +140,7 @@ struct Stager {
   T v[NQ][4];
   T scale[NQ];
 
-  static __device__ __forceinline__ bool live(int q) { return QUADS % kThreads == 0 || q < QUADS; }
+  static __device__ __forceinline__ bool live(int q) { return QUADS % NT == 0 || q < QUADS; }
   // quad q -> (first row r, packed k kk): KC quads run along k, the others along r
   static __device__ __forceinline__ void coords(int q, int& r, int& kk) {
     if (KC) {
@@ -157,7 +157,7 @@ struct Stager {
 #pragma unroll
       for (int j = 0; j < 4; ++j) v[i][j] = (T)0;
       scale[i] = (T)1;
-      const int q = threadIdx.x + i * kThreads;
+      const int q = threadIdx.x + i * NT;
       if (!live(q)) continue;
       int r, kk;
       coords(q, r, kk);
@@ -194,7 +194,7 @@ struct Stager {
   __device__ __forceinline__ void store(T (*S)[D1]) const {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-      const int q = threadIdx.x + i * kThreads;
+      const int q = threadIdx.x + i * NT;
       if (!live(q)) continue;
       int r, kk;
       coords(q, r, kk);
@@ -207,7 +207,7 @@ struct Stager {
   __device__ __forceinline__ void store_split(__bf16 (*H)[KP], __bf16 (*L)[KP]) const {
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
-      const int q = threadIdx.x + i * kThreads;
+      const int q = threadIdx.x + i * NT;
       if (!live(q)) continue;
       int r, kk;
       coords(q, r, kk);
@@ -250,7 +250,7 @@ struct Stager {
 // Waves are arranged WM x WN; each wave owns (BM/WM) x (BN/WN) = (16 TM) x (16 TN).
 // ------------------------------------------------------------------------------------------
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(64 * WM * WN)
 gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
                  const GemmTile* __restrict__ tiles, int n_tiles,
                  Bases<typename Mfma<MODE>::T> bases, const Bases<typename Mfma<MODE>::T>* __restrict__ table,
@@ -261,9 +261,9 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
   constexpr int SPC = BK / 4;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  static_assert(WM * WN == kThreads / 64, "four waves");
-  typedef Stager<T, !TA, BM, BK, 0> SA;
-  typedef Stager<T, TB, BN, BK, 1> SB;
+  constexpr int NT = 64 * WM * WN;
+  typedef Stager<T, !TA, BM, BK, 0, NT> SA;
+  typedef Stager<T, TB, BN, BK, 1, NT> SB;
   __shared__ __attribute__((aligned(16))) T As[SA::D0][SA::D1];
   __shared__ __attribute__((aligned(16))) T Bs[SB::D0][SB::D1];
   __shared__ QuadRef<T> refs[SPC];
@@ -383,7 +383,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
 // lane's eight k values are contiguous.
 // ------------------------------------------------------------------------------------------
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(64 * WM * WN)
 gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
                    const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
                    const Bases<float>* __restrict__ table, const int* __restrict__ active) {
@@ -392,8 +392,9 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
   constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  typedef Stager<float, !TA, BM, BK, 0> SA;
-  typedef Stager<float, TB, BN, BK, 1> SB;
+  constexpr int NT = 64 * WM * WN;
+  typedef Stager<float, !TA, BM, BK, 0, NT> SA;
+  typedef Stager<float, TB, BN, BK, 1, NT> SB;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
@@ -498,9 +499,9 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
 // and NB of the next B chunk in registers, so the global loads of chunk i+1 are in flight
 // while the MFMAs of chunk i run.  Element e of a chunk maps to (row, k) so that consecutive
 // threads read consecutive addresses of the stored (row-major) operand.
-template <class T, bool TA, int BM, int BK>
+template <class T, bool TA, int BM, int BK, int NT>
 struct ALoader {
-  static constexpr int N = BM * BK / kThreads;
+  static constexpr int N = BM * BK / NT;
   static __device__ __forceinline__ void coords(int e, int& mm, int& kk) {
     if (!TA) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
   }
@@ -509,15 +510,15 @@ struct ALoader {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       int mm, kk;
-      coords(threadIdx.x + i * kThreads, mm, kk);
+      coords(threadIdx.x + i * NT, mm, kk);
       const int gr = row0 + mm, gk = k0 + kk;
       r[i] = (gr < m && gk < K) ? (TA ? A[(int64_t)gk * lda + gr] : A[(int64_t)gr * lda + gk]) : (T)0;
     }
   }
 };
-template <class T, bool TB, int BN, int BK>
+template <class T, bool TB, int BN, int BK, int NT>
 struct BLoader {
-  static constexpr int N = BN * BK / kThreads;
+  static constexpr int N = BN * BK / NT;
   static __device__ __forceinline__ void coords(int e, int& nn, int& kk) {
     if (!TB) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
   }
@@ -526,7 +527,7 @@ struct BLoader {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       int nn, kk;
-      coords(threadIdx.x + i * kThreads, nn, kk);
+      coords(threadIdx.x + i * NT, nn, kk);
       const int gc = col0 + nn, gk = k0 + kk;
       r[i] = (gc < n && gk < K) ? (TB ? B[(int64_t)gc * ldb + gk] : B[(int64_t)gk * ldb + gc]) : (T)0;
     }
@@ -534,7 +535,7 @@ struct BLoader {
 };
 
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(64 * WM * WN)
 gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
                  const GemmTile* __restrict__ tiles, int n_tiles,
                  Bases<typename Mfma<MODE>::T> bases, const Bases<typename Mfma<MODE>::T>* __restrict__ table,
@@ -545,9 +546,9 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
   constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  static_assert(WM * WN == kThreads / 64, "four waves");
-  typedef ALoader<T, TA, BM, BK> LA;
-  typedef BLoader<T, TB, BN, BK> LB;
+  constexpr int NT = 64 * WM * WN;
+  typedef ALoader<T, TA, BM, BK, NT> LA;
+  typedef BLoader<T, TB, BN, BK, NT> LB;
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
 
@@ -589,13 +590,13 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
 #pragma unroll
     for (int i = 0; i < LA::N; ++i) {
       int mm, kk;
-      LA::coords(tid + i * kThreads, mm, kk);
+      LA::coords(tid + i * NT, mm, kk);
       As[kk][mm] = alpha * ra[i];
     }
 #pragma unroll
     for (int i = 0; i < LB::N; ++i) {
       int nn, kk;
-      LB::coords(tid + i * kThreads, nn, kk);
+      LB::coords(tid + i * NT, nn, kk);
       Bs[kk][nn] = rb[i];
     }
     __syncthreads();
@@ -650,7 +651,7 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
 // lane's eight k values are contiguous.
 // ------------------------------------------------------------------------------------------
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(64 * WM * WN)
 gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
                    const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
                    const Bases<float>* __restrict__ table, const int* __restrict__ active) {
@@ -658,8 +659,9 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
   constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
-  typedef ALoader<float, TA, BM, BK> LA;
-  typedef BLoader<float, TB, BN, BK> LB;
+  constexpr int NT = 64 * WM * WN;
+  typedef ALoader<float, TA, BM, BK, NT> LA;
+  typedef BLoader<float, TB, BN, BK, NT> LB;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
@@ -699,7 +701,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
 #pragma unroll
     for (int i = 0; i < LA::N; ++i) {
       int mm, kk;
-      LA::coords(tid + i * kThreads, mm, kk);
+      LA::coords(tid + i * NT, mm, kk);
       const float v = alpha * ra[i];
       const __bf16 h = (__bf16)v;
       Ah[mm][kk] = h;
@@ -708,7 +710,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
 #pragma unroll
     for (int i = 0; i < LB::N; ++i) {
       int nn, kk;
-      LB::coords(tid + i * kThreads, nn, kk);
+      LB::coords(tid + i * NT, nn, kk);
       const float v = rb[i];
       const __bf16 h = (__bf16)v;
       Bh[nn][kk] = h;
@@ -772,10 +774,10 @@ template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 static void fire_mfma(const GemmDesc& d, const Bases<typename Mfma<MODE>::T>& b, hipStream_t s,
                       const Bases<typename Mfma<MODE>::T>* table, const int* active) {
   if (d.packed)
-    hipLaunchKernelGGL((gemm_packed_kernel<MODE, TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((gemm_packed_kernel<MODE, TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(64 * WM * WN), 0, s,
                        d.slots, d.groups, d.tiles, d.n_tiles, b, table, active);
   else
-    hipLaunchKernelGGL((gemm_terms_kernel<MODE, TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((gemm_terms_kernel<MODE, TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(64 * WM * WN), 0, s,
                        d.terms, d.groups, d.tiles, d.n_tiles, b, table, active);
 }
 template <int MODE, int BM, int BN, int WM, int WN>
@@ -793,10 +795,10 @@ template <bool TA, bool TB, int BM, int BN, int WM, int WN>
 static void fire_bf(const GemmDesc& d, const Bases<float>& b, hipStream_t s, const Bases<float>* table,
                     const int* active) {
   if (d.packed)
-    hipLaunchKernelGGL((gemm_bf16x3_packed_kernel<TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((gemm_bf16x3_packed_kernel<TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(64 * WM * WN), 0, s,
                        d.slots, d.groups, d.tiles, d.n_tiles, b, table, active);
   else
-    hipLaunchKernelGGL((gemm_bf16x3_terms_kernel<TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((gemm_bf16x3_terms_kernel<TA, TB, BM, BN, WM, WN>), dim3(d.n_tiles), dim3(64 * WM * WN), 0, s,
                        d.terms, d.groups, d.tiles, d.n_tiles, b, table, active);
 }
 template <int BM, int BN, int WM, int WN>

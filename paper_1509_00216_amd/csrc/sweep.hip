@@ -7,10 +7,9 @@
 // extended by that site on the device, and S V^T contracted with the right-canonical tensor of
 // site l+2 is the initial guess of the next local problem at (l+1, l+2).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -30,8 +29,142 @@ __global__ void scale_rows_kernel(double* __restrict__ dst, const double* __rest
   }
 }
 
-void check_blas(rocblas_status s, const char* what) {
-  if (s != rocblas_status_success) throw Error{LCC_ERR_HIP, std::string(what) + ": rocBLAS/rocSOLVER status " + std::to_string((int)s)};
+// ---------------------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD, one workgroup per middle-bond sector.
+//
+// The sector block X (row-major nrows x ncols) is copied into a column-major m x n workspace
+// W with n = min(nrows, ncols): W = X if nrows >= ncols, else W = X^T.  Pairs of columns are
+// rotated until every pair is orthogonal to a relative tolerance (cyclic round-robin order:
+// each step rotates n/2 disjoint pairs, 16 lanes per pair); the rotations accumulate in V
+// (n x n), so that W V_0 ... = U diag(s).  Singular values are the final column norms; they
+// are written in descending order together with the matching vectors:
+//   left vectors of X  (row-major nrows x n)  -> L,   right vectors (row-major n x ncols) -> R.
+// One-sided Jacobi computes small singular values to high relative accuracy.
+// ---------------------------------------------------------------------------------------
+struct SvdJob {
+  int64_t x_off;                // the block in the two-site vector
+  int64_t w_off;                // workspace: W (m n), V (n n), norms (n), ranks (n)
+  int64_t s_off, l_off, r_off;  // outputs
+  int32_t nrows, ncols;
+};
+constexpr int kSvdThreads = 1024;
+constexpr int kSvdMaxSweeps = 60;
+constexpr double kSvdTol = 1e-14;  // |w_i . w_j| <= tol ||w_i|| ||w_j|| counts as orthogonal
+
+constexpr int kSvdGroup = 16;  // lanes per column pair
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// sum over the kSvdGroup lanes of a group (groups are aligned within the wave)
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = kSvdGroup / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(kSvdThreads)
+jacobi_svd_kernel(const SvdJob* __restrict__ jobs, const double* __restrict__ x, double* __restrict__ work,
+                  double* __restrict__ S, double* __restrict__ L, double* __restrict__ R, int* __restrict__ failed) {
+  const SvdJob jb = jobs[blockIdx.x];
+  const bool tall = jb.nrows >= jb.ncols;
+  const int m = tall ? jb.nrows : jb.ncols, n = tall ? jb.ncols : jb.nrows;
+  double* W = work + jb.w_off;
+  double* V = W + (int64_t)m * n;
+  double* nrm = V + (int64_t)n * n;
+  double* rank = nrm + n;
+  const double* X = x + jb.x_off;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
+    const int j = (int)(e / m), i = (int)(e % m);
+    W[e] = tall ? X[(int64_t)i * jb.ncols + j] : X[(int64_t)j * jb.ncols + i];
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __shared__ int rotated;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int gl = threadIdx.x % kSvdGroup, grp = threadIdx.x / kSvdGroup, ngrp = blockDim.x / kSvdGroup;
+  const int N = n + (n & 1);  // round-robin players (one dummy when n is odd)
+  bool converged = n < 2;
+  for (int sweep = 0; sweep < kSvdMaxSweeps && !converged; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      for (int k = grp; k < N / 2; k += ngrp) {
+        int i = k == 0 ? N - 1 : (r + k) % (N - 1);
+        int j = k == 0 ? r : (r - k + N - 1) % (N - 1);
+        if (i >= n || j >= n) continue;  // the dummy player
+        if (i > j) {
+          const int t = i;
+          i = j;
+          j = t;
+        }
+        double* wi = W + (int64_t)i * m;
+        double* wj = W + (int64_t)j * m;
+        double a = 0, b = 0, g = 0;
+        for (int t = gl; t < m; t += kSvdGroup) {
+          const double u = wi[t], v = wj[t];
+          a += u * u;
+          b += v * v;
+          g += u * v;
+        }
+        a = group_sum(a);
+        b = group_sum(b);
+        g = group_sum(g);
+        if (!(fabs(g) > kSvdTol * sqrt(a * b))) continue;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int q = gl; q < m; q += kSvdGroup) {
+          const double u = wi[q], v = wj[q];
+          wi[q] = c * u - s * v;
+          wj[q] = s * u + c * v;
+        }
+        double* vi = V + (int64_t)i * n;
+        double* vj = V + (int64_t)j * n;
+        for (int q = gl; q < n; q += kSvdGroup) {
+          const double u = vi[q], v = vj[q];
+          vi[q] = c * u - s * v;
+          vj[q] = s * u + c * v;
+        }
+        if (gl == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    converged = rotated == 0;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) failed[blockIdx.x] = converged ? 0 : 1;
+  if (!converged) return;
+  for (int j = wave; j < n; j += nwaves) {
+    const double* wj = W + (int64_t)j * m;
+    double a = 0;
+    for (int t = lane; t < m; t += 64) a += wj[t] * wj[t];
+    a = wave_sum(a);
+    if (lane == 0) nrm[j] = sqrt(a);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    int rk = 0;
+    for (int k = 0; k < n; ++k) rk += (nrm[k] > nrm[j]) || (nrm[k] == nrm[j] && k < j);
+    rank[j] = rk;
+    S[jb.s_off + rk] = nrm[j];
+  }
+  __syncthreads();
+  // tall: X = (W/s) diag(s) V^T -> L from W, R from V;  wide: X^T = (W/s) diag(s) V^T -> L from V, R from W
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
+    const int j = (int)(e / m), i = (int)(e % m);
+    const double u = nrm[j] > 0.0 ? W[e] / nrm[j] : 0.0;
+    const int rk = (int)rank[j];
+    if (tall) L[jb.l_off + (int64_t)i * n + rk] = u;
+    else R[jb.r_off + (int64_t)rk * jb.ncols + i] = u;
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) {
+    const int j = (int)(e / n), i = (int)(e % n);
+    const int rk = (int)rank[j];
+    if (tall) R[jb.r_off + (int64_t)rk * jb.ncols + i] = V[e];
+    else L[jb.l_off + (int64_t)i * n + rk] = V[e];
+  }
 }
 
 }  // namespace
@@ -48,10 +181,6 @@ struct Sweep {
   DevBuf guess;      // initial guess of the current local problem (n_elements), valid if have_guess
   bool have_guess = false;
   std::vector<double> last_sv;  // singular values of the last split, descending
-  rocblas_handle blas = nullptr;
-  ~Sweep() {
-    if (blas) (void)rocblas_destroy_handle(blas);
-  }
 };
 
 Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int first) {
@@ -75,8 +204,6 @@ Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md
   if (first + 2 < K && wr >= 0) check_identity(S->R[first + 2], wr, S->mps.bonds[first + 2], st, "right");
   S->bl = S->mps.bonds[first];
   S->env.reset(make_env(ctx, mpo, first, S->bl, S->mps.bonds[first + 2], S->L, S->R[first + 2]));
-  check_blas(rocblas_create_handle(&S->blas), "rocblas_create_handle");
-  check_blas(rocblas_set_stream(S->blas, st), "rocblas_set_stream");
   return S.release();
 }
 
@@ -85,52 +212,60 @@ Env* sweep_env(Sweep& s) { return s.env.get(); }
 
 void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
   hipStream_t st = S.ctx->stream;
+  typedef std::chrono::steady_clock clk;
+  const auto ms_since = [](clk::time_point t) {
+    return (float)std::chrono::duration<double, std::milli>(clk::now() - t).count();
+  };
+  const clk::time_point t_start = clk::now();
   const Mpo& mpo = S.ham->mpo;
   const int K = mpo.K;
   if (S.site + 2 >= K) throw Error{LCC_ERR_STATE, "the sweep is already at the last two-site block"};
   if (m_max < 1) throw Error{LCC_ERR_ARG, "m_max must be >= 1"};
   Env& E = *S.env;
   const int nsec = (int)E.sectors.size();
-  // ---- SVD per middle sector: X_q (row-major nrows x ncols) is the column-major matrix X_q^T;
-  // its SVD X_q^T = U' S V'^T gives V'^T (column-major r x nrows) = left vectors of X_q as a
-  // row-major nrows x r matrix, and U' (column-major ncols x r) = right vectors as a
-  // row-major r x ncols matrix.
-  struct Split { int r; int64_t a_off, s_off, u_off, v_off; };
+  // ---- SVD per middle sector (one workgroup each): singular values descending at s_off, left
+  // vectors as a row-major nrows x r matrix at v_off, right vectors as a row-major r x ncols
+  // matrix at u_off (r = min(nrows, ncols)).
+  struct Split { int r; int64_t s_off, u_off, v_off; };
   std::vector<Split> sp(nsec);
-  int64_t a_tot = 0, s_tot = 0, u_tot = 0, v_tot = 0;
+  std::vector<SvdJob> jobs(nsec);
+  int64_t s_tot = 0, u_tot = 0, v_tot = 0, w_tot = 0;
   for (int q = 0; q < nsec; ++q) {
     const MiddleSector& M = E.sectors[q];
     Split& p = sp[q];
     p.r = std::min(M.nrows, M.ncols);
-    p.a_off = a_tot; a_tot += (int64_t)M.nrows * M.ncols;
     p.s_off = s_tot; s_tot += p.r;
     p.u_off = u_tot; u_tot += (int64_t)M.ncols * p.r;
     p.v_off = v_tot; v_tot += (int64_t)p.r * M.nrows;
+    SvdJob& j = jobs[q];
+    j.x_off = M.off;
+    j.w_off = w_tot;
+    w_tot += (int64_t)std::max(M.nrows, M.ncols) * p.r + (int64_t)p.r * p.r + 2 * (int64_t)p.r;
+    j.s_off = p.s_off;
+    j.l_off = p.v_off;
+    j.r_off = p.u_off;
+    j.nrows = M.nrows;
+    j.ncols = M.ncols;
   }
-  DevBuf A, Sv, U, V, Ew, inf;
-  A.alloc(sizeof(double) * std::max<int64_t>(a_tot, 1));
+  DevBuf Sv, U, V, Wk, fail, djobs;
   Sv.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
   U.alloc(sizeof(double) * std::max<int64_t>(u_tot, 1));
   V.alloc(sizeof(double) * std::max<int64_t>(v_tot, 1));
-  Ew.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
-  inf.alloc(sizeof(rocblas_int) * std::max(nsec, 1));
-  check_hip(hipMemcpyAsync(A.p, x, sizeof(double) * E.n_elements, hipMemcpyDeviceToDevice, st), "copy x");
-  for (int q = 0; q < nsec; ++q) {
-    const MiddleSector& M = E.sectors[q];
-    const Split& p = sp[q];
-    check_blas(rocsolver_dgesvd(S.blas, rocblas_svect_singular, rocblas_svect_singular, M.ncols, M.nrows,
-                                A.as<double>() + M.off, M.ncols, Sv.as<double>() + p.s_off, U.as<double>() + p.u_off,
-                                M.ncols, V.as<double>() + p.v_off, p.r, Ew.as<double>() + p.s_off,
-                                rocblas_outofplace, inf.as<rocblas_int>() + q),
-               "rocsolver_dgesvd");
-  }
+  Wk.alloc(sizeof(double) * std::max<int64_t>(w_tot, 1));
+  fail.alloc(sizeof(int) * std::max(nsec, 1));
+  upload(djobs, jobs, st);
+  if (nsec > 0)
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nsec), dim3(kSvdThreads), 0, st, djobs.as<SvdJob>(), x,
+                       Wk.as<double>(), Sv.as<double>(), V.as<double>(), U.as<double>(), fail.as<int>());
+  check_hip(hipGetLastError(), "jacobi svd");
   std::vector<double> hs(s_tot);
-  std::vector<rocblas_int> hinf(nsec);
+  std::vector<int> hfail(nsec);
   check_hip(hipMemcpyAsync(hs.data(), Sv.p, sizeof(double) * s_tot, hipMemcpyDeviceToHost, st), "sv copy");
-  check_hip(hipMemcpyAsync(hinf.data(), inf.p, sizeof(rocblas_int) * nsec, hipMemcpyDeviceToHost, st), "info copy");
+  check_hip(hipMemcpyAsync(hfail.data(), fail.p, sizeof(int) * nsec, hipMemcpyDeviceToHost, st), "svd flag copy");
   check_hip(hipStreamSynchronize(st), "svd");
   for (int q = 0; q < nsec; ++q)
-    if (hinf[q] != 0) throw Error{LCC_ERR_NAN, "SVD did not converge in a sector"};
+    if (hfail[q] != 0) throw Error{LCC_ERR_NAN, "Jacobi SVD did not converge in a sector (non-finite input?)"};
+  const float ms_svd = ms_since(t_start);
   // ---- global truncation: the m_max largest singular values; ties by sector (N, 2Sz), then index
   struct Cand { double v; int q, i; };
   std::vector<Cand> cand;
@@ -196,10 +331,13 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
               "A block copy");
   }
   // ---- extend the left environment by the new site tensor
+  const clk::time_point t_env = clk::now();
   Environment Lnew = left_step(S.L, one, S.site, mpo, st);
   // ---- next block (l+1, l+2)
   const int next = S.site + 1;
   std::unique_ptr<Env> nenv(make_env(S.ctx, mpo, next, nb, S.mps.bonds[next + 2], Lnew, S.R[next + 2]));
+  const float ms_env = ms_since(t_env);
+  const clk::time_point t_guess = clk::now();
   // ---- next guess: rows (q, s2) x cols (s3, c) = sum_b (S V^T)_q[:, (s2, b)] B_{l+2}^{s3}[b -> c]
   DevBuf C;
   std::vector<int64_t> c_off(nsec, -1);
@@ -265,6 +403,10 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     info->n_singular = (int32_t)cand.size();
     info->discarded_weight = total > 0 ? (total - kept_w) / total : 0.0;
     info->largest_discarded = largest_dropped;
+    info->ms_svd = ms_svd;
+    info->ms_env = ms_env;
+    info->ms_guess = ms_since(t_guess);
+    info->ms_total = ms_since(t_start);
   }
   S.L = std::move(Lnew);
   S.bl = nb;

@@ -91,7 +91,8 @@ class TuneInfo(C.Structure):
 
 class SweepInfo(C.Structure):
     _fields_ = [("site", C.c_int32), ("kept", C.c_int32), ("n_singular", C.c_int32), ("reserved", C.c_int32),
-                ("discarded_weight", C.c_double), ("largest_discarded", C.c_double)]
+                ("discarded_weight", C.c_double), ("largest_discarded", C.c_double), ("ms_svd", C.c_float),
+                ("ms_env", C.c_float), ("ms_guess", C.c_float), ("ms_total", C.c_float)]
 
 
 _lib = None
@@ -509,7 +510,8 @@ class Sweep:
         _check(library().lcc_sweep_advance(self.handle, C.c_void_p(x.data_ptr()), int(m_max), C.byref(info)),
                self.ctx.handle)
         return {"site": info.site, "kept": info.kept, "n_singular": info.n_singular,
-                "discarded_weight": info.discarded_weight, "largest_discarded": info.largest_discarded}
+                "discarded_weight": info.discarded_weight, "largest_discarded": info.largest_discarded,
+                "ms_svd": info.ms_svd, "ms_env": info.ms_env, "ms_guess": info.ms_guess, "ms_total": info.ms_total}
 
     def singular_values(self) -> np.ndarray:
         lib = library()
