@@ -310,7 +310,9 @@ lcc_status lcc_sweep_singular_values(lcc_sweep sweep, int32_t* count, double* ou
  * (opts->precision must be LCC_FP32 or LCC_BF16X3).
  * ------------------------------------------------------------------------------------- */
 typedef struct lcc_batch_s* lcc_batch;
-/* The environments must stay alive while the batch exists.  Synchronous. */
+/* The environments must stay alive while the batch exists, and each may appear only once
+ * (an environment's intermediate and split-K buffers serve one problem at a time): a repeated
+ * environment is LCC_ERR_ARG.  Synchronous. */
 lcc_status lcc_batch_create(lcc_context ctx, int32_t n, const lcc_env* envs, lcc_batch* out);
 void lcc_batch_destroy(lcc_batch batch);
 /* Arrays of n device pointers (b[i], x[i] double*, length of problem i; v may be NULL or hold

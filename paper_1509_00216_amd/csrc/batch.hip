@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <set>
 #include <vector>
 
 #include "state.h"
@@ -259,8 +260,11 @@ Batch* batch_create(Context* ctx, const std::vector<Env*>& envs) {
   B->ctx = ctx;
   B->envs = envs;
   B->n = (int)envs.size();
+  std::set<const Env*> seen;
   for (Env* e : envs) {
     if (e->ctx != ctx) throw Error{LCC_ERR_ARG, "all environments of a batch must belong to one context"};
+    // an environment's intermediate and split-K buffers serve one problem at a time
+    if (!seen.insert(e).second) throw Error{LCC_ERR_ARG, "an environment appears twice in a batch"};
     ensure_fp32(*e);
   }
   // arena layout and segment blocks

@@ -145,3 +145,36 @@ def test_bad_descriptors(ctx):
     with pytest.raises(lcc.LccError) as e:
         ctx.build_environments(ham, scaled)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_rhs_gives_zero_solution(chain, precision):
+    """Degenerate right-hand side: Q b = 0 has the solution x = 0 and J = 0, with no iteration."""
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    b = torch.zeros(env.n, dtype=torch.float64, device="cuda:0")
+    x = torch.full_like(b, 0.5)  # a non-zero guess is discarded
+    info = env.solve_local_lcc(b, chain["e0"] - 1.0, x, precision=precision, tol=1e-10)
+    assert info["status"] == "LCC_OK"
+    assert info["iterations"] == 0
+    assert info["hylleraas"] == 0.0 and info["e2"] == 0.0
+    assert float(x.abs().max()) == 0.0
+
+
+def test_batch_with_zero_rhs_member(chain, ctx):
+    """A batch whose second member has b = 0: that member stays at x = 0, the other converges.
+    One environment may not serve two members (its intermediate buffers are per problem)."""
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    with pytest.raises(lcc.LccError):
+        lcc.Batch(ctx, [env, env])
+    env2 = ctx.build_environments(ctx.create_hamiltonian(chain["spec"]), chain["mps"])
+    b = to_dev(torch, chain["b"], torch.float64)
+    v = to_dev(torch, chain["v"], torch.float64)
+    batch = lcc.Batch(ctx, [env, env2])
+    xs = [torch.zeros_like(b), torch.zeros_like(b)]
+    status, infos = batch.solve([b, torch.zeros_like(b)], [chain["e0"], chain["e0"]], xs, vs=[v, v],
+                                precision="fp32", tol=1e-10, max_iter=2000)
+    assert status == "LCC_OK"
+    assert abs(infos[0]["hylleraas"] - chain["jstar"]) <= 1e-8
+    assert infos[1]["iterations"] == 0 and float(xs[1].abs().max()) == 0.0

@@ -26,6 +26,9 @@ def _oracle_sweep(spec, mps, b0, e0, steps, m_max):
     b = b0
     for _ in range(steps):
         x, jstar, _ = OW.local_solve(spec, mps, mpo, b, e0)
+        if mps["center"] + 2 >= mps["n_sites"]:  # the last block: nothing to split
+            out.append({"site": mps["center"], "J": jstar})
+            break
         site_blocks, new_bond, guess, sv = OW.split(x, mps, m_max)
         kept = sum(d for _, _, d in new_bond)
         w = sv ** 2
@@ -94,4 +97,61 @@ def test_sweep_errors():
     assert float(x.norm()) > 0
     with pytest.raises(lcc.LccError):
         sw.advance(x, 64)  # block (6, 7) is the last one
+    sw.close()
+
+
+def test_sweep_across_both_boundaries():
+    """Complete-basis chain (K=8): every block from the left end (0,1) to the right end (6,7),
+    against the oracle, then the advance past the last block is refused."""
+    torch, lcc = need_gpu()
+    spec, mps = C.make("hubbard1d_k8_m64", center=0)
+    e0 = C.lower_bound_shift(spec, 0.5)
+    b0 = M.random_two_site_vector(mps, 41)
+    ref = _oracle_sweep(spec, mps, b0, e0, 7, 64)
+    ctx = lcc.Context(0)
+    sw = lcc.Sweep(ctx, ctx.create_hamiltonian(spec), mps, 0)
+    env = sw.env()
+    b = to_dev(torch, env.pack(b0), torch.float64)
+    for k, r in enumerate(ref):
+        x = torch.zeros_like(b)
+        info = env.solve_local_lcc(b, e0, x, precision="fp64", tol=1e-12, max_iter=4000)
+        assert abs(info["hylleraas"] - r["J"]) <= 1e-9, k
+        if k == 6:
+            with pytest.raises(lcc.LccError):
+                sw.advance(x, 64)
+            break
+        split = sw.advance(x, 64)
+        assert split["kept"] == r["kept"] and split["n_singular"] == len(r["sv"])
+        np.testing.assert_allclose(sw.singular_values(), r["sv"], rtol=0, atol=1e-9 * r["sv"][0])
+        env = sw.env()
+        b = torch.empty(env.n, dtype=torch.float64, device="cuda:0")
+        sw.guess(b)
+        b /= b.norm()
+    sw.close()
+
+
+def test_rank_deficient_split():
+    """A two-site tensor with a single non-zero block: all other singular values are zero and
+    are never kept; the split keeps exactly the rank, like the oracle."""
+    torch, lcc = need_gpu()
+    spec, mps = C.make("hubbard2d_4x4_m500", m_max=40, seed=51, center=6)
+    full = M.random_two_site_vector(mps, 52)
+    key = max(full, key=lambda k: full[k].size)
+    x = {key: full[key]}
+    _, _, _, sv = OW.split(x, mps, 1000)
+    ctx = lcc.Context(0)
+    sw = lcc.Sweep(ctx, ctx.create_hamiltonian(spec), mps, 6)
+    env = sw.env()
+    xd = to_dev(torch, env.pack(x), torch.float64)
+    split = sw.advance(xd, 1000)
+    rank = int(np.linalg.matrix_rank(full[key]))
+    say(f"[sweep] rank-deficient block {key}: rank {rank}, kept {split['kept']} / {split['n_singular']}")
+    assert split["kept"] == rank
+    np.testing.assert_allclose(sw.singular_values(), sv, rtol=0, atol=1e-12 * sv[0])
+    # the guess carries the whole norm of x (nothing was discarded)
+    env = sw.env()
+    g = torch.empty(env.n, dtype=torch.float64, device="cuda:0")
+    sw.guess(g)
+    assert abs(float(g.norm()) - np.linalg.norm(full[key])) <= 1e-12 * np.linalg.norm(full[key])
+    assert split["discarded_weight"] == 0.0
     sw.close()
