@@ -75,6 +75,12 @@ lcc_status lcc_context_synchronize(lcc_context ctx);
  * contractions are executed chunk by chunk over the middle-bond channels (default 16 GiB).
  * Smaller values trade launches for memory (e.g. for many environments in one batch). */
 lcc_status lcc_context_set_intermediate_limit(lcc_context ctx, int64_t bytes);
+/* Concurrency of lcc_apply_heff (and of the solves built on it): the launches of one GEMM
+ * phase (one per tile shape) are independent and run on `side_streams` extra streams of
+ * default priority next to the context stream, joined by events before the next phase
+ * (default 3; 0 issues every launch in order on the context stream).  The results do not
+ * depend on it.  The side streams are created on first use and destroyed with the context. */
+lcc_status lcc_context_set_overlap(lcc_context ctx, int32_t side_streams);
 /* Text file of autotuning results (one line per block-size histogram; created / appended by
  * lcc_env_autotune, read by environment construction).  NULL or "" disables the cache.
  * The path is copied. */

@@ -81,6 +81,12 @@ void lcc_context_destroy(lcc_context ctx) {
     (void)hipSetDevice(ctx->c.device);
     if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
     if (ctx->c.host_scalar) (void)hipHostFree(ctx->c.host_scalar);
+    for (hipStream_t s : ctx->c.side) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : ctx->c.ev_join) (void)hipEventDestroy(e);
+    if (ctx->c.ev_fork) (void)hipEventDestroy(ctx->c.ev_fork);
     if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
   }
   delete ctx;
@@ -105,6 +111,17 @@ lcc_status lcc_context_set_intermediate_limit(lcc_context ctx, int64_t bytes) {
   if (bytes < 8) return fail(ctx, LCC_ERR_ARG, "limit must hold at least one element");
   ctx->c.t_budget_elems = bytes / 8;
   return LCC_OK;
+}
+
+lcc_status lcc_context_set_overlap(lcc_context ctx, int32_t side_streams) {
+  if (!ctx) return fail(nullptr, LCC_ERR_ARG, "ctx is NULL");
+  if (side_streams < 0 || side_streams > 8) return fail(ctx, LCC_ERR_ARG, "side_streams must be in [0, 8]");
+  return guarded(ctx, [&]() -> lcc_status {
+    if (ctx->c.device >= 0) check_hip(hipSetDevice(ctx->c.device), "hipSetDevice");
+    for (hipStream_t s : ctx->c.side) check_hip(hipStreamSynchronize(s), "side stream sync");
+    ctx->c.overlap = side_streams;
+    return LCC_OK;
+  });
 }
 
 lcc_status lcc_context_set_tune_cache(lcc_context ctx, const char* path) {

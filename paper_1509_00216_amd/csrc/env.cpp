@@ -942,19 +942,11 @@ namespace {
 void no_callback(void*, const LaunchRef&) {}
 }  // namespace
 
-void apply_heff(Env& env, int precision, const void* x, void* y) {
-  apply_heff_each(env, precision, x, y, no_callback, nullptr);
-}
+namespace {
 
-// Every launch of one H_eff x in order: for each channel chunk its phase-1 launches (one per
-// tile shape) then its phase-2 launches, and finally the split-K reduction into y.
-void apply_heff_each(Env& env, int precision, const void* x, void* y,
-                     void (*after_each)(void*, const LaunchRef&), void* user) {
-  hipStream_t st = env.ctx->stream;
-  const Plan& P = env.plan;
-  if (precision != LCC_FP64) ensure_fp32(env);
-  Bases<double> b64{};
-  Bases<float> b32{};
+void bases_of(Env& env, int precision, const void* x, void* y, Bases<double>& b64, Bases<float>& b32) {
+  b64 = Bases<double>{};
+  b32 = Bases<float>{};
   if (precision == LCC_FP64) {
     b64.p[BASE_ENV] = env.env64.as<double>();
     b64.p[BASE_MERGED] = env.merged64.as<double>();
@@ -970,25 +962,103 @@ void apply_heff_each(Env& env, int precision, const void* x, void* y,
     b32.p[BASE_Y] = static_cast<float*>(y);
     b32.p[BASE_WORK] = env.work.as<float>();
   }
-  for (const Plan::Chunk& C : P.chunks)
-    for (int ph = 1; ph <= 2; ++ph)
-      for (const GemmLaunch& L : ph == 1 ? C.phase1 : C.phase2) {
-        hipError_t e;
-        if (precision == LCC_FP64)
-          e = launch_gemm_f64(L.desc(LCC_FP64), b64, st);
-        else if (precision == LCC_FP32)
-          e = launch_gemm_f32(L.desc(LCC_FP32), b32, st);
-        else
-          e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), b32, st);
-        check_hip(e, "gemm launch");
-        after_each(user, LaunchRef{ph, 0, &L});
-      }
+}
+
+void launch_one(const GemmLaunch& L, int precision, const Bases<double>& b64, const Bases<float>& b32,
+                hipStream_t st) {
+  hipError_t e;
+  if (precision == LCC_FP64)
+    e = launch_gemm_f64(L.desc(LCC_FP64), b64, st);
+  else if (precision == LCC_FP32)
+    e = launch_gemm_f32(L.desc(LCC_FP32), b32, st);
+  else
+    e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), b32, st);
+  check_hip(e, "gemm launch");
+}
+
+void launch_reduce(const Plan& P, int precision, const Bases<double>& b64, const Bases<float>& b32, hipStream_t st) {
   hipError_t e = precision == LCC_FP64
                      ? launch_reduce_f64(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
                                          P.n_reduce_tiles, b64, st)
                      : launch_reduce_f32(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
                                          P.n_reduce_tiles, b32, st);
   check_hip(e, "reduce launch");
+}
+
+// Side streams of a context (default priority), created on first use.
+void ensure_side_streams(Context& C) {
+  if ((int)C.side.size() >= C.overlap) return;
+  if (!C.ev_fork) check_hip(hipEventCreateWithFlags(&C.ev_fork, hipEventDisableTiming), "event");
+  while ((int)C.side.size() < C.overlap) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    check_hip(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "side stream");
+    C.side.push_back(s);
+    check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+    C.ev_join.push_back(e);
+  }
+}
+
+}  // namespace
+
+// H_eff x.  The launches of one phase (one per tile shape) are independent: with side streams
+// enabled on the context they run concurrently (the longest on the context stream, the others
+// spread over the side streams), so that short launches fill the tail of long ones; the
+// phases, chunks and the reduction stay ordered on the context stream.
+void apply_heff(Env& env, int precision, const void* x, void* y) {
+  Context& C = *env.ctx;
+  if (C.overlap <= 0) {
+    apply_heff_each(env, precision, x, y, no_callback, nullptr);
+    return;
+  }
+  hipStream_t st = C.stream;
+  const Plan& P = env.plan;
+  if (precision != LCC_FP64) ensure_fp32(env);
+  ensure_side_streams(C);
+  Bases<double> b64;
+  Bases<float> b32;
+  bases_of(env, precision, x, y, b64, b32);
+  for (const Plan::Chunk& Ch : P.chunks)
+    for (int ph = 1; ph <= 2; ++ph) {
+      const std::vector<GemmLaunch>& Ls = ph == 1 ? Ch.phase1 : Ch.phase2;
+      if (Ls.size() <= 1) {
+        for (const GemmLaunch& L : Ls) launch_one(L, precision, b64, b32, st);
+        continue;
+      }
+      std::vector<int> order(Ls.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Ls[a].flops > Ls[b].flops; });
+      const int nside = std::min<int>(C.overlap, (int)Ls.size() - 1);
+      check_hip(hipEventRecord(C.ev_fork, st), "fork");
+      for (int k = 0; k < nside; ++k) check_hip(hipStreamWaitEvent(C.side[k], C.ev_fork, 0), "fork wait");
+      for (size_t i = 0; i < order.size(); ++i)
+        launch_one(Ls[order[i]], precision, b64, b32, i == 0 ? st : C.side[(i - 1) % nside]);
+      for (int k = 0; k < nside; ++k) {
+        check_hip(hipEventRecord(C.ev_join[k], C.side[k]), "join");
+        check_hip(hipStreamWaitEvent(st, C.ev_join[k], 0), "join wait");
+      }
+    }
+  launch_reduce(P, precision, b64, b32, st);
+}
+
+// Every launch of one H_eff x in order on the context stream: for each channel chunk its
+// phase-1 launches (one per tile shape) then its phase-2 launches, and finally the split-K
+// reduction into y (the order the per-launch profile and the batched graph use).
+void apply_heff_each(Env& env, int precision, const void* x, void* y,
+                     void (*after_each)(void*, const LaunchRef&), void* user) {
+  hipStream_t st = env.ctx->stream;
+  const Plan& P = env.plan;
+  if (precision != LCC_FP64) ensure_fp32(env);
+  Bases<double> b64;
+  Bases<float> b32;
+  bases_of(env, precision, x, y, b64, b32);
+  for (const Plan::Chunk& C : P.chunks)
+    for (int ph = 1; ph <= 2; ++ph)
+      for (const GemmLaunch& L : ph == 1 ? C.phase1 : C.phase2) {
+        launch_one(L, precision, b64, b32, st);
+        after_each(user, LaunchRef{ph, 0, &L});
+      }
+  launch_reduce(P, precision, b64, b32, st);
   after_each(user, LaunchRef{2, 1, nullptr});
 }
 

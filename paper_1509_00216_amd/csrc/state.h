@@ -69,6 +69,11 @@ struct Context {
   int64_t t_budget_elems = (int64_t)1 << 31;  // intermediate (phase-1 output) elements per environment
   PlanParams plan_params;                      // defaults for new environments
   std::string tune_cache;                      // autotuner cache file ("" = none)
+  // concurrent launches of one GEMM phase: number of side streams (0 = everything in order)
+  int overlap = 3;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
 };
 
 struct Bond {

@@ -28,7 +28,7 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
-           "lcc_env_autotune"]
+           "lcc_env_autotune", "lcc_context_set_overlap"]
 
 
 class LccError(RuntimeError):
@@ -133,6 +133,7 @@ def library() -> C.CDLL:
         "lcc_batch_create": (C.c_int32, [P, C.c_int32, C.POINTER(P), C.POINTER(P)]),
         "lcc_context_set_intermediate_limit": (C.c_int32, [P, C.c_int64]),
         "lcc_context_set_tune_cache": (C.c_int32, [P, C.c_char_p]),
+        "lcc_context_set_overlap": (C.c_int32, [P, C.c_int32]),
         "lcc_env_autotune": (C.c_int32, [P, C.c_int32, C.c_int32, C.POINTER(TuneInfo)]),
         "lcc_sweep_create": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
         "lcc_sweep_destroy": (None, [P]),
@@ -207,6 +208,10 @@ class Context:
 
     def set_intermediate_limit(self, nbytes: int):
         _check(library().lcc_context_set_intermediate_limit(self.handle, int(nbytes)), self.handle)
+
+    def set_overlap(self, side_streams: int):
+        """Side streams for the independent launches of one GEMM phase (0 = in order)."""
+        _check(library().lcc_context_set_overlap(self.handle, int(side_streams)), self.handle)
 
     def set_tune_cache(self, path):
         """Autotuning results file (read when environments are built, appended by autotune)."""

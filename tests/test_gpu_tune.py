@@ -69,3 +69,25 @@ def test_autotune_rejects_bad_arguments():
     env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
     with pytest.raises(lcc.LccError):
         env.autotune("fp32", reps=0)
+
+
+def test_concurrent_phase_launches_are_bitwise_identical():
+    """Launches of one phase write disjoint outputs, so running them on side streams changes
+    nothing: y is bitwise the same for every overlap setting and precision."""
+    torch, lcc = need_gpu()
+    spec, mps = C.make_member("threeband_4x2_m2000", 150, 33)
+    ctx = lcc.Context(0)
+    env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
+    x64 = to_dev(torch, env.pack(M.random_two_site_vector(mps, 34)), torch.float64)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        xx = x64 if prec == "fp64" else x64.float()
+        outs = []
+        for ov in (0, 3, 1):
+            ctx.set_overlap(ov)
+            yy = torch.empty_like(xx)
+            env.apply_heff(xx, yy, prec)
+            torch.cuda.synchronize()
+            outs.append(yy)
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2]), prec
+    with pytest.raises(lcc.LccError):
+        ctx.set_overlap(-1)
