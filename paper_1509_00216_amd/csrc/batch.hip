@@ -184,7 +184,18 @@ struct Batch {
   DevBuf count;
   int* host_count = nullptr;
   hipStream_t stream = nullptr;
+  // concurrent launches of one GEMM phase (the context's overlap setting): side streams of
+  // default priority joined by events, also inside the captured iteration graph
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t ev_fork = nullptr;
   ~Batch() {
+    for (hipStream_t t : side) {
+      (void)hipStreamSynchronize(t);
+      (void)hipStreamDestroy(t);
+    }
+    for (hipEvent_t e : ev_join) (void)hipEventDestroy(e);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (stream) (void)hipStreamDestroy(stream);
     if (host_count) (void)hipHostFree(host_count);
   }
@@ -352,6 +363,17 @@ Batch* batch_create(Context* ctx, const std::vector<Env*>& envs) {
   B->count.alloc(sizeof(int) * 4);
   check_hip(hipHostMalloc(reinterpret_cast<void**>(&B->host_count), sizeof(int) * 4, hipHostMallocDefault), "hipHostMalloc");
   check_hip(hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking), "batch stream");
+  if (ctx->overlap > 0) {
+    check_hip(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming), "batch event");
+    for (int k = 0; k < ctx->overlap; ++k) {
+      hipStream_t t = nullptr;
+      hipEvent_t e = nullptr;
+      check_hip(hipStreamCreateWithFlags(&t, hipStreamNonBlocking), "batch side stream");
+      B->side.push_back(t);
+      check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "batch event");
+      B->ev_join.push_back(e);
+    }
+  }
   check_hip(hipStreamSynchronize(st), "batch create");
   return B.release();
 }
@@ -384,16 +406,30 @@ struct Runner {
     Bases<double> d64{};
     Bases<float> d32{};
     for (size_t c = 0; c < B.phase1.size(); ++c)
-      for (int ph = 1; ph <= 2; ++ph)
-        for (const MergedLaunch& L : ph == 1 ? B.phase1[c] : B.phase2[c]) {
-        hipError_t e;
-        if (fp64)
-          e = launch_gemm_f64(L.desc(LCC_FP64), d64, s, B.table64.as<Bases<double>>(), mask);
-        else if (prec == LCC_FP32)
-          e = launch_gemm_f32(L.desc(LCC_FP32), d32, s, B.table32.as<Bases<float>>(), mask);
-        else
-          e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), d32, s, B.table32.as<Bases<float>>(), mask);
-        check_hip(e, "batched gemm");
+      for (int ph = 1; ph <= 2; ++ph) {
+        const std::vector<MergedLaunch>& Ls = ph == 1 ? B.phase1[c] : B.phase2[c];
+        // the launches of one phase are independent: the first on s, the others on side streams
+        const int nside = std::min<int>((int)B.side.size(), (int)Ls.size() - 1);
+        if (nside > 0) {
+          check_hip(hipEventRecord(B.ev_fork, s), "fork");
+          for (int k = 0; k < nside; ++k) check_hip(hipStreamWaitEvent(B.side[k], B.ev_fork, 0), "fork wait");
+        }
+        for (size_t i = 0; i < Ls.size(); ++i) {
+          const MergedLaunch& L = Ls[i];
+          hipStream_t q = (i == 0 || nside == 0) ? s : B.side[(i - 1) % nside];
+          hipError_t e;
+          if (fp64)
+            e = launch_gemm_f64(L.desc(LCC_FP64), d64, q, B.table64.as<Bases<double>>(), mask);
+          else if (prec == LCC_FP32)
+            e = launch_gemm_f32(L.desc(LCC_FP32), d32, q, B.table32.as<Bases<float>>(), mask);
+          else
+            e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), d32, q, B.table32.as<Bases<float>>(), mask);
+          check_hip(e, "batched gemm");
+        }
+        for (int k = 0; k < nside; ++k) {
+          check_hip(hipEventRecord(B.ev_join[k], B.side[k]), "join");
+          check_hip(hipStreamWaitEvent(s, B.ev_join[k], 0), "join wait");
+        }
       }
     hipError_t e = fp64 ? launch_reduce_f64(B.reduce_groups.as<ReduceGroup>(), B.reduce_tiles.as<ReduceTile>(),
                                             B.n_reduce_tiles, d64, s, B.table64.as<Bases<double>>(), mask)
