@@ -150,8 +150,13 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
       const int gi = (int)groups.size();
       groups.push_back(g);
       for (int t = 0; t < tiles_m * g.tiles_n; ++t) tiles.push_back(GemmTile{gi, t});
+      // MFMA work issued: k rounded up to the 16-wide k groups, per group of quads (packed
+      // kernel) or per term (term walk)
       const int64_t kpad = ((int64_t)(g.slot_end - g.slot_begin) * 4 + 15) / 16 * 16;
-      L.exec_flops += 2.0 * tiles_m * g.tiles_n * (double)bm * bn * kpad;
+      int64_t kterms = 0;
+      for (int t = g0.term_begin; t < g0.term_end; ++t) kterms += (b.terms[t].k + 15) / 16 * 16;
+      L.exec_flops_packed += 2.0 * tiles_m * g.tiles_n * (double)bm * bn * kpad;
+      L.exec_flops_terms += 2.0 * tiles_m * g.tiles_n * (double)bm * bn * kterms;
       L.elems_written += (double)g.m * g.n;
     }
     if (tiles.empty()) continue;

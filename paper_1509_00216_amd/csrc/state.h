@@ -112,7 +112,7 @@ struct GemmLaunch {
   int n_tiles = 0;
   int64_t n_slots = 0;
   double flops = 0;          // 2 m n k over the launch's block products
-  double exec_flops = 0;     // MFMA work including tile and k-group padding
+  double exec_flops_terms = 0, exec_flops_packed = 0;  // MFMA work incl. tile and k-group padding, per kernel
   double elems_read = 0;     // distinct operand blocks, each counted once
   double elems_written = 0;  // output blocks
   DevBuf terms, slots, groups, tiles;
