@@ -85,6 +85,10 @@ lcc_status lcc_context_set_overlap(lcc_context ctx, int32_t side_streams);
  * lcc_env_autotune, read by environment construction).  NULL or "" disables the cache.
  * The path is copied. */
 lcc_status lcc_context_set_tune_cache(lcc_context ctx, const char* path);
+/* Planner parameters for environments built afterwards on this context when no tuning-cache
+ * entry applies (meanings as in lcc_tune_info; defaults 2048, 2048, 0, 0). */
+lcc_status lcc_context_set_plan(lcc_context ctx, double tile_overhead, int64_t split_k, int32_t p2_order,
+                                int32_t t_colmajor);
 
 /* ---------------------------------------------------------------------------------------
  * Hamiltonian (Theory section, partitioned-Hamiltonian equation, read with the usual 1/2):
@@ -205,7 +209,9 @@ lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const 
  * elements, of the tile-shape choice; split_k in {1024, 2048, 4096}: accumulation length of
  * a phase-2 split-K part; p2_order in {0, 1}: phase-2 output blocks one after the other, or
  * their parts interleaved by channel so that parts reading the same intermediate columns are
- * neighbours) and, per GEMM launch, both kernels (term walk / packed k), with
+ * neighbours; t_colmajor in {0, 1}: the phase-1 intermediate stored row- or column-major,
+ * the latter computed as X^T Lt^T so that phase 2 reads long contiguous columns) and, per GEMM
+ * launch, both kernels (term walk / packed k), with
  * `reps` timed applications of `precision` per measurement; keeps the fastest plan and
  * chooses the kernels of all three precisions on it.  With a tuning cache set on the
  * context (lcc_context_set_tune_cache) the choice is appended to it, and an entry already
@@ -221,7 +227,7 @@ typedef struct {
   int32_t packed_launches;    /* ... of which use the packed-k kernel for `precision` */
   int32_t from_cache;         /* 1 if the entry came from the cache */
   int32_t p2_order;           /* phase-2 group order: 0 output-major, 1 channel-major */
-  int32_t reserved;
+  int32_t t_colmajor;         /* intermediate T blocks: 0 row-major, 1 column-major */
   float ms_before, ms_after;  /* one H_eff x of `precision`, summed launch times */
 } lcc_tune_info;
 lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, lcc_tune_info* info);

@@ -612,7 +612,12 @@ void plan_env(Env& E, const PlanParams& pp) {
       const MiddleSector& Sp = env->sectors[sec_index[S.q + dq_mid[w1]]];
       for (size_t i = 0; i < Sp.rows.size(); ++i) {
         const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
-        B1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
+        // row-major T: the block of rows (a',s1') is Lt X;  column-major T: its transpose,
+        // X^T Lt^T, is a row-major (ncols x dim a') block with leading dimension nrows(q')
+        if (pp.t_colmajor)
+          B1.group(BASE_T, to + Sp.row_off[i], Sp.nrows, S.ncols, bl.dim[ap], false);
+        else
+          B1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
         auto it = lt.find(std::make_tuple(w1, ap, sp));
         if (it == lt.end()) continue;
         for (const auto& src : it->second) {
@@ -620,7 +625,11 @@ void plan_env(Env& E, const PlanParams& pp) {
           if (ra.first != m) continue;
           const OperandRef& ref = std::get<2>(src);
           const int ka = bl.dim[std::get<0>(src)];
-          B1.term(ref.base, ref.off, ka, BASE_X, S.off + (int64_t)S.row_off[ra.second] * S.ncols, S.ncols, ka, ref.alpha);
+          const int64_t x_off = S.off + (int64_t)S.row_off[ra.second] * S.ncols;
+          if (pp.t_colmajor)
+            B1.term(BASE_X, x_off, S.ncols, ref.base, ref.off, ka, ka, ref.alpha);
+          else
+            B1.term(ref.base, ref.off, ka, BASE_X, x_off, S.ncols, ka, ref.alpha);
         }
       }
     }
@@ -664,8 +673,13 @@ void plan_env(Env& E, const PlanParams& pp) {
           const int kb = br.dim[std::get<1>(src)];
           GemmTerm t{};
           t.a_base = BASE_T;
-          t.a_off = to + S.col_off[ca.second];
-          t.lda = S.ncols;
+          if (pp.t_colmajor) {  // columns (s2,b) of a column-major block: stored k x m
+            t.a_off = to + (int64_t)S.col_off[ca.second] * gm;
+            t.lda = gm;
+          } else {
+            t.a_off = to + S.col_off[ca.second];
+            t.lda = S.ncols;
+          }
           t.b_base = ref.base;
           t.b_off = ref.off;
           t.ldb = kb;
@@ -761,8 +775,8 @@ void plan_env(Env& E, const PlanParams& pp) {
   env->plan.flops2 = flops2;
   env->plan.chunks.resize(nchunks);
   for (int c = 0; c < nchunks; ++c) {
-    env->plan.chunks[c].phase1 = finalize(p1[c], false, false, st, pp.tile_overhead);
-    env->plan.chunks[c].phase2 = finalize(p2[c], false, true, st, pp.tile_overhead, pp.p2_order == 0);
+    env->plan.chunks[c].phase1 = finalize(p1[c], pp.t_colmajor != 0, pp.t_colmajor != 0, st, pp.tile_overhead);
+    env->plan.chunks[c].phase2 = finalize(p2[c], pp.t_colmajor != 0, true, st, pp.tile_overhead, pp.p2_order == 0);
   }
   {
     std::vector<ReduceTile> rtl;

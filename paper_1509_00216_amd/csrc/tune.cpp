@@ -3,7 +3,7 @@
 // The block-size histogram of a two-site problem (bond sectors and their dimensions, the MPO
 // bond dimension) fixes the shapes of all block products.  For a histogram the tuner times,
 // on the device, every candidate of the planner parameters (the per-tile cost that picks tile
-// shapes, the split-K length and the group order of phase 2) and, for every launch of a plan, both GEMM kernels
+// shapes, the split-K length and the group order of phase 2, the layout of the intermediate) and, for every launch of a plan, both GEMM kernels
 // (term walk, packed k), then keeps the fastest plan and per-launch kernel choice.  The result
 // is stored in a text cache keyed by a signature of the histogram, so that later environments
 // with the same histogram (the same site of another sweep, another process) are planned the
@@ -53,7 +53,8 @@ bool set_flags(Env& env, int precision, const std::string& f) {
 }
 
 bool same_params(const PlanParams& a, const PlanParams& b) {
-  return a.tile_overhead == b.tile_overhead && a.split_k == b.split_k && a.p2_order == b.p2_order;
+  return a.tile_overhead == b.tile_overhead && a.split_k == b.split_k && a.p2_order == b.p2_order &&
+         a.t_colmajor == b.t_colmajor;
 }
 
 struct Entry {
@@ -70,8 +71,8 @@ bool cache_find(const std::string& path, uint64_t sig, Entry& e) {
     std::istringstream ls(line);
     unsigned long long s = 0;
     Entry x;
-    if (!(ls >> std::hex >> s >> std::dec >> x.pp.tile_overhead >> x.pp.split_k >> x.pp.p2_order >> x.flags[0] >>
-          x.flags[1] >> x.flags[2]))
+    if (!(ls >> std::hex >> s >> std::dec >> x.pp.tile_overhead >> x.pp.split_k >> x.pp.p2_order >> x.pp.t_colmajor >>
+          x.flags[0] >> x.flags[1] >> x.flags[2]))
       continue;
     if (s == sig) {
       e = x;
@@ -87,8 +88,8 @@ void cache_add(const std::string& path, uint64_t sig, const Entry& e) {
   if (!out) throw Error{LCC_ERR_ARG, "cannot write the tuning cache " + path};
   char head[64];
   std::snprintf(head, sizeof head, "%016llx", (unsigned long long)sig);
-  out << head << " " << e.pp.tile_overhead << " " << e.pp.split_k << " " << e.pp.p2_order << " " << e.flags[0] << " "
-      << e.flags[1] << " " << e.flags[2] << "\n";
+  out << head << " " << e.pp.tile_overhead << " " << e.pp.split_k << " " << e.pp.p2_order << " " << e.pp.t_colmajor
+      << " " << e.flags[0] << " " << e.flags[1] << " " << e.flags[2] << "\n";
 }
 
 // Per-launch mean times (ms) of one apply with every launch on the packed (or term-walk) kernel.
@@ -190,11 +191,13 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info) {
     double best = 1e300;
     for (double ov : kOverheads)
       for (int64_t sk : kSplits)
-      for (int order = 0; order < 2; ++order) {
+      for (int order = 0; order < 2; ++order)
+      for (int cm = 0; cm < 2; ++cm) {
         PlanParams pp;
         pp.tile_overhead = ov;
         pp.split_k = sk;
         pp.p2_order = order;
+        pp.t_colmajor = cm;
         plan_env(env, pp);
         const double t = choose_kernels(env, precision, x.p, y.p, reps);
         ++out.candidates;
@@ -229,6 +232,7 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info) {
   out.tile_overhead = env.params.tile_overhead;
   out.split_k = env.params.split_k;
   out.p2_order = env.params.p2_order;
+  out.t_colmajor = env.params.t_colmajor;
   out.ms_after = (float)total_ms(env, precision, x.p, y.p, reps);
   for (GemmLaunch* L : launches_of(env)) {
     ++out.launches;

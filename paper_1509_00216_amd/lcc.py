@@ -28,7 +28,7 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
-           "lcc_env_autotune", "lcc_context_set_overlap"]
+           "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan"]
 
 
 class LccError(RuntimeError):
@@ -86,7 +86,7 @@ class LaunchProfile(C.Structure):
 class TuneInfo(C.Structure):
     _fields_ = [("tile_overhead", C.c_double), ("split_k", C.c_int64), ("candidates", C.c_int32),
                 ("launches", C.c_int32), ("packed_launches", C.c_int32), ("from_cache", C.c_int32),
-                ("p2_order", C.c_int32), ("reserved", C.c_int32), ("ms_before", C.c_float), ("ms_after", C.c_float)]
+                ("p2_order", C.c_int32), ("t_colmajor", C.c_int32), ("ms_before", C.c_float), ("ms_after", C.c_float)]
 
 
 class SweepInfo(C.Structure):
@@ -134,6 +134,7 @@ def library() -> C.CDLL:
         "lcc_context_set_intermediate_limit": (C.c_int32, [P, C.c_int64]),
         "lcc_context_set_tune_cache": (C.c_int32, [P, C.c_char_p]),
         "lcc_context_set_overlap": (C.c_int32, [P, C.c_int32]),
+        "lcc_context_set_plan": (C.c_int32, [P, C.c_double, C.c_int64, C.c_int32, C.c_int32]),
         "lcc_env_autotune": (C.c_int32, [P, C.c_int32, C.c_int32, C.POINTER(TuneInfo)]),
         "lcc_sweep_create": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
         "lcc_sweep_destroy": (None, [P]),
@@ -212,6 +213,11 @@ class Context:
     def set_overlap(self, side_streams: int):
         """Side streams for the independent launches of one GEMM phase (0 = in order)."""
         _check(library().lcc_context_set_overlap(self.handle, int(side_streams)), self.handle)
+
+    def set_plan(self, tile_overhead: float = 2048.0, split_k: int = 2048, p2_order: int = 0, t_colmajor: int = 0):
+        """Planner parameters of environments built afterwards (when no tuning-cache entry applies)."""
+        _check(library().lcc_context_set_plan(self.handle, float(tile_overhead), int(split_k), int(p2_order),
+                                              int(t_colmajor)), self.handle)
 
     def set_tune_cache(self, path):
         """Autotuning results file (read when environments are built, appended by autotune)."""
@@ -396,6 +402,7 @@ class Env:
         info = TuneInfo()
         _check(library().lcc_env_autotune(self.handle, PRECISIONS[precision], reps, C.byref(info)), self.ctx.handle)
         return {"tile_overhead": info.tile_overhead, "split_k": info.split_k, "p2_order": info.p2_order,
+                "t_colmajor": info.t_colmajor,
                 "candidates": info.candidates,
                 "launches": info.launches, "packed_launches": info.packed_launches,
                 "from_cache": bool(info.from_cache), "ms_before": info.ms_before, "ms_after": info.ms_after}

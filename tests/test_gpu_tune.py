@@ -35,7 +35,7 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert rel(y.cpu().numpy(), ref) <= 1e-12
     info = env.autotune("fp32", reps=2)
     say(f"[tune] {info}")
-    assert info["candidates"] == 18 and not info["from_cache"]
+    assert info["candidates"] == 36 and not info["from_cache"]
     assert 0 <= info["packed_launches"] <= info["launches"]
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-4)):
         xx = xd if prec == "fp64" else xd.float()
@@ -53,7 +53,8 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     env2 = ctx2.build_environments(ctx2.create_hamiltonian(spec), mps)
     info2 = env2.autotune("fp32", reps=1)
     assert info2["from_cache"] and info2["candidates"] == 0
-    assert (info2["tile_overhead"], info2["split_k"], info2["p2_order"]) == (info["tile_overhead"], info["split_k"], info["p2_order"])
+    keys = ("tile_overhead", "split_k", "p2_order", "t_colmajor")
+    assert [info2[k] for k in keys] == [info[k] for k in keys]
     assert info2["packed_launches"] == info["packed_launches"]
     y2 = torch.empty_like(xd)
     env2.apply_heff(xd, y2, "fp64")
@@ -91,3 +92,26 @@ def test_concurrent_phase_launches_are_bitwise_identical():
         assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2]), prec
     with pytest.raises(lcc.LccError):
         ctx.set_overlap(-1)
+
+
+@pytest.mark.parametrize("p2_order,t_colmajor,split_k", [(0, 1, 2048), (1, 1, 512), (1, 0, 1024)])
+def test_every_plan_option_matches_oracle(p2_order, t_colmajor, split_k):
+    """Planner options (phase-2 order, intermediate layout, split-K length) reorder and
+    re-lay-out the same block products: every combination reproduces the oracle."""
+    torch, lcc = need_gpu()
+    for name, m, seed in (("hubbard2d_4x4_m500", 70, 41), ("threeband_4x2_m2000", 110, 42)):
+        spec, mps = C.make_member(name, m, seed)
+        x = M.random_two_site_vector(mps, seed + 1)
+        ctx = lcc.Context(0)
+        ctx.set_plan(2048.0, split_k, p2_order, t_colmajor)
+        env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
+        ref = env.pack(_oracle_apply(spec, mps, x))
+        xd = to_dev(torch, env.pack(x), torch.float64)
+        for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-4)):
+            xx = xd if prec == "fp64" else xd.float()
+            yy = torch.empty_like(xx)
+            env.apply_heff(xx, yy, prec)
+            torch.cuda.synchronize()
+            assert rel(yy.double().cpu().numpy(), ref) <= tol, (name, prec)
+    with pytest.raises(lcc.LccError):
+        lcc.Context(0).set_plan(2048.0, 0, 0, 0)
