@@ -150,13 +150,23 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
       const int gi = (int)groups.size();
       groups.push_back(g);
       for (int t = 0; t < tiles_m * g.tiles_n; ++t) tiles.push_back(GemmTile{gi, t});
-      // MFMA work issued: k rounded up to the 16-wide k groups, per group of quads (packed
-      // kernel) or per term (term walk)
-      const int64_t kpad = ((int64_t)(g.slot_end - g.slot_begin) * 4 + 15) / 16 * 16;
-      int64_t kterms = 0;
-      for (int t = g0.term_begin; t < g0.term_end; ++t) kterms += (b.terms[t].k + 15) / 16 * 16;
-      L.exec_flops_packed += 2.0 * tiles_m * g.tiles_n * (double)bm * bn * kpad;
-      L.exec_flops_terms += 2.0 * tiles_m * g.tiles_n * (double)bm * bn * kterms;
+      // MFMA work issued.  FP64 / FP32 kernels skip the 16 x 16 sub-tiles outside the block
+      // (m, n padded to 16) and pad k to 4 per term (term walk) or to 16 per group of quads
+      // (packed); the BF16x3 kernels run whole tiles and pad k to 32 per term or per group.
+      const int64_t nk = (int64_t)(g.slot_end - g.slot_begin) * 4;
+      int64_t k4 = 0, k32 = 0;
+      for (int t = g0.term_begin; t < g0.term_end; ++t) {
+        k4 += (b.terms[t].k + 3) / 4 * 4;
+        k32 += (b.terms[t].k + 31) / 32 * 32;
+      }
+      const double live = 2.0 * ((g.m + 15) / 16 * 16) * (double)((g.n + 15) / 16 * 16);
+      const double whole = 2.0 * tiles_m * g.tiles_n * (double)bm * bn;
+      for (int p = LCC_FP64; p <= LCC_FP32; ++p) {
+        L.exec_flops[p][0] += live * k4;
+        L.exec_flops[p][1] += live * ((nk + 15) / 16 * 16);
+      }
+      L.exec_flops[LCC_BF16X3][0] += whole * k32;
+      L.exec_flops[LCC_BF16X3][1] += whole * ((nk + 31) / 32 * 32);
       L.elems_written += (double)g.m * g.n;
     }
     if (tiles.empty()) continue;

@@ -34,6 +34,15 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return ((local / kTileRun) * 8 + xcd) * kTileRun + (local % kTileRun);
 }
 
+// Number of a wave's 16-row (or 16-column) sub-tiles, starting at `first`, that intersect a
+// block of `extent` rows (columns); at most T16.  Wave-uniform: the sub-tiles of an edge tile
+// that lie wholly outside the block issue no MFMA and read no LDS.
+template <int T16>
+__device__ __forceinline__ int live_subtiles(int first, int extent) {
+  const int n = (extent - first + 15) >> 4;
+  return __builtin_amdgcn_readfirstlane(n < 0 ? 0 : (n > T16 ? T16 : n));
+}
+
 template <int MODE>
 struct Mfma;
 template <>
@@ -249,6 +258,54 @@ struct Stager {
 // from an r-contiguous tile it reads them one by one.
 // Waves are arranged WM x WN; each wave owns (BM/WM) x (BN/WN) = (16 TM) x (16 TN).
 // ------------------------------------------------------------------------------------------
+// MFMAs of one staged chunk of the packed-k kernel.  The wave's sub-tiles i >= ni or j >= nj
+// lie outside the block and are skipped (their LDS reads stay: unconditional reads pair up).
+// arow / bcol: the lane's row (column) in the LDS tile for sub-tile 0.
+template <int MODE, bool TA, bool TB, int BK, int TM, int TN, class TA_, class TB_>
+__device__ __forceinline__ void packed_chunk(const TA_& As, const TB_& Bs, int arow, int bcol, int kmax, int ni,
+                                             int nj, typename Mfma<MODE>::Acc (&acc)[TM][TN]) {
+  typedef typename Mfma<MODE>::T T;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int kg = 0; kg < BK; kg += 16) {
+    if (kg < kmax) {
+      const int kq = kg + 4 * (lane >> 4);
+      T a[TM][4], b[TN][4];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = arow + i * 16;
+        if (!TA) {
+          const auto q = lds_read_quad(&As[r][kq]);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[i][s] = q[s];
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[i][s] = As[kq + s][r];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int cc = bcol + j * 16;
+        if (TB) {
+          const auto q = lds_read_quad(&Bs[cc][kq]);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[j][s] = q[s];
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[j][s] = Bs[kq + s][cc];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (i < ni && j < nj) acc[i][j] = Mfma<MODE>::step(a[i][s], b[j][s], acc[i][j]);
+    }
+  }
+}
+
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
@@ -281,6 +338,9 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
   }
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
+  const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
+  const int ni = live_subtiles<TM>(row0 + wm * (BM / WM), g.m);
+  const int nj = live_subtiles<TN>(col0 + wn * (BN / WN), g.n);
 
   Acc acc[TM][TN];
 #pragma unroll
@@ -319,43 +379,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
       sb.load(refs, col0, g.n);
       if (tid < SPC && (c + 2) * SPC + tid < nslots) pending = gs[(c + 2) * SPC + tid];
     }
-#pragma unroll
-    for (int kg = 0; kg < BK; kg += 16) {
-      if (kg < kmax) {
-        const int kq = kg + 4 * (lane >> 4);
-        T a[TM][4], b[TN][4];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const int r = wm * (BM / WM) + i * 16 + (lane & 15);
-          if (!TA) {
-            const auto q = lds_read_quad(&As[r][kq]);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) a[i][s] = q[s];
-          } else {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) a[i][s] = As[kq + s][r];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int cc = wn * (BN / WN) + j * 16 + (lane & 15);
-          if (TB) {
-            const auto q = lds_read_quad(&Bs[cc][kq]);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) b[j][s] = q[s];
-          } else {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) b[j][s] = Bs[kq + s][cc];
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<MODE>::step(a[i][s], b[j][s], acc[i][j]);
-      }
-    }
+    packed_chunk<MODE, TA, TB, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
   }
 
   T* __restrict__ C = bases.p[g.c_base] + g.c_off;
@@ -382,6 +406,34 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
 // at row 4(l/16) + r, column l%16.  LDS holds A as [m][k] and B as [n][k] so that each
 // lane's eight k values are contiguous.
 // ------------------------------------------------------------------------------------------
+// Split-product MFMAs of one staged 32-k chunk (LDS hi / lo tiles [r][k]); arow, bcol as for
+// packed_chunk.  Every sub-tile runs: skipping those outside the block (as the FP64 / FP32
+// kernels do) raises the register count of these kernels past an occupancy step.
+template <int TM, int TN, class TA_, class TB_>
+__device__ __forceinline__ void bf16x3_chunk(const TA_& Ah, const TA_& Al, const TB_& Bh, const TB_& Bl, int arow,
+                                             int bcol, f4 (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  bf8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    ah[i] = *reinterpret_cast<const bf8*>(&Ah[arow + i * 16][8 * (lane >> 4)]);
+    al[i] = *reinterpret_cast<const bf8*>(&Al[arow + i * 16][8 * (lane >> 4)]);
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    bh[j] = *reinterpret_cast<const bf8*>(&Bh[bcol + j * 16][8 * (lane >> 4)]);
+    bl[j] = *reinterpret_cast<const bf8*>(&Bl[bcol + j * 16][8 * (lane >> 4)]);
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+}
+
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
@@ -414,6 +466,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
   }
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
+  const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
 
   f4 acc[TM][TN];
 #pragma unroll
@@ -451,27 +504,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
       if (tid < SPC && (c + 2) * SPC + tid < nslots) pending = gs[(c + 2) * SPC + tid];
     }
     (void)kmax;
-    bf8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int r = wm * (BM / WM) + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const bf8*>(&Ah[r][8 * (lane >> 4)]);
-      al[i] = *reinterpret_cast<const bf8*>(&Al[r][8 * (lane >> 4)]);
-    }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int cc = wn * (BN / WN) + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const bf8*>(&Bh[cc][8 * (lane >> 4)]);
-      bl[j] = *reinterpret_cast<const bf8*>(&Bl[cc][8 * (lane >> 4)]);
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-      }
+    bf16x3_chunk<TM, TN>(Ah, Al, Bh, Bl, arow, bcol, acc);
   }
 
   float* __restrict__ C = bases.p[g.c_base] + g.c_off;
@@ -534,6 +567,41 @@ struct BLoader {
   }
 };
 
+// LDS tiles [k][r] of the term-walk kernel: row pitch r + 2 words (FP32) or r + 1 doubles.
+// A wider pitch (16 mod 64 words) makes the operand reads conflict-free but puts the 32 k of
+// a staging store on 4 banks, and an XOR swizzle that fixes both costs address registers and
+// a wave of occupancy; both measured slower.
+template <class T>
+struct KPitch {
+  static constexpr int of(int r) { return r + (sizeof(T) == 8 ? 1 : 2); }
+};
+
+// MFMAs of one staged chunk of the term-walk kernel (LDS tiles [k][m], [k][n]); ni, nj, arow,
+// bcol as for packed_chunk.
+template <int MODE, int BK, int TM, int TN, class TA_, class TB_>
+__device__ __forceinline__ void terms_chunk(const TA_& As, const TB_& Bs, int arow, int bcol, int kmax, int ni,
+                                            int nj, typename Mfma<MODE>::Acc (&acc)[TM][TN]) {
+  typedef typename Mfma<MODE>::T T;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int kk = 0; kk < BK; kk += 4) {
+    if (kk < kmax) {
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = As[kk + (lane >> 4)][arow + i * 16];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = Bs[kk + (lane >> 4)][bcol + j * 16];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if (i < ni && j < nj) acc[i][j] = Mfma<MODE>::step(a[i], b[j], acc[i][j]);
+    }
+  }
+}
+
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
@@ -543,14 +611,13 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
   typedef typename Mfma<MODE>::T T;
   typedef typename Mfma<MODE>::Acc Acc;
   constexpr int BK = 128 / (int)sizeof(T);  // one 128-byte line of a row per chunk
-  constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
   constexpr int TM = BM / WM / 16;
   constexpr int TN = BN / WN / 16;
   constexpr int NT = 64 * WM * WN;
   typedef ALoader<T, TA, BM, BK, NT> LA;
   typedef BLoader<T, TB, BN, BK, NT> LB;
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  __shared__ T As[BK][KPitch<T>::of(BM)];
+  __shared__ T Bs[BK][KPitch<T>::of(BN)];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -565,6 +632,9 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
   }
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
+  const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
+  const int ni = live_subtiles<TM>(row0 + wm * (BM / WM), g.m);
+  const int nj = live_subtiles<TN>(col0 + wn * (BN / WN), g.n);
 
   Acc acc[TM][TN];
 #pragma unroll
@@ -610,20 +680,7 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
       LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, k0, term.k);
       LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, k0, term.k);
     }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      if (kk < kmax) {
-        T a[TM], b[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) a[i] = As[kk + (lane >> 4)][wm * (BM / WM) + i * 16 + (lane & 15)];
-#pragma unroll
-        for (int j = 0; j < TN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * (BN / WN) + j * 16 + (lane & 15)];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) acc[i][j] = Mfma<MODE>::step(a[i], b[j], acc[i][j]);
-      }
-    }
+    terms_chunk<MODE, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
   }
 
   T* __restrict__ C = bases.p[g.c_base] + g.c_off;
@@ -680,6 +737,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
   }
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
+  const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
 
   f4 acc[TM][TN];
 #pragma unroll
@@ -727,27 +785,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
       LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, k0, term.k);
       LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, k0, term.k);
     }
-    bf8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int r = wm * (BM / WM) + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const bf8*>(&Ah[r][8 * (lane >> 4)]);
-      al[i] = *reinterpret_cast<const bf8*>(&Al[r][8 * (lane >> 4)]);
-    }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int c = wn * (BN / WN) + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const bf8*>(&Bh[c][8 * (lane >> 4)]);
-      bl[j] = *reinterpret_cast<const bf8*>(&Bl[c][8 * (lane >> 4)]);
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-      }
+    bf16x3_chunk<TM, TN>(Ah, Al, Bh, Bl, arow, bcol, acc);
   }
 
   float* __restrict__ C = bases.p[g.c_base] + g.c_off;

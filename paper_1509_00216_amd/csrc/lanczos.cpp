@@ -168,7 +168,7 @@ std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const 
       p.n_tiles = L.n_tiles;
       p.packed = L.packed[precision] ? 1 : 0;
       p.flops = L.flops;
-      p.exec_flops = L.packed[precision] ? L.exec_flops_packed : L.exec_flops_terms;
+      p.exec_flops = L.exec_flops[precision][L.packed[precision] ? 1 : 0];
       p.bytes = (L.elems_read + L.elems_written) * esz;
     } else {
       p.n_tiles = env.plan.n_reduce_tiles;

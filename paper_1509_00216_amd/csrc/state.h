@@ -113,7 +113,9 @@ struct GemmLaunch {
   int n_tiles = 0;
   int64_t n_slots = 0;
   double flops = 0;          // 2 m n k over the launch's block products
-  double exec_flops_terms = 0, exec_flops_packed = 0;  // MFMA work incl. tile and k-group padding, per kernel
+  // MFMA work issued, incl. padding of m, n to the kernel's sub-tiles and of k to its k groups;
+  // [precision][packed kernel]; a BF16x3 product counts once, not per split product
+  double exec_flops[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   double elems_read = 0;     // distinct operand blocks, each counted once
   double elems_written = 0;  // output blocks
   DevBuf terms, slots, groups, tiles;
