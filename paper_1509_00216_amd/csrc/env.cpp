@@ -125,6 +125,12 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
       g.term_begin = (int32_t)terms.size();
       for (int t = g0.term_begin; t < g0.term_end; ++t) {
         const GemmTerm& tm = b.terms[t];
+        if (tm.k <= 0) continue;
+        // the kernels address an operand block with 32-bit byte offsets from its first element
+        const int64_t ea = ta ? (int64_t)(tm.k - 1) * tm.lda + g.m : (int64_t)(g.m - 1) * tm.lda + tm.k;
+        const int64_t eb = tb ? (int64_t)(g.n - 1) * tm.ldb + tm.k : (int64_t)(tm.k - 1) * tm.ldb + g.n;
+        if (std::max(ea, eb) > (int64_t)INT32_MAX / (int64_t)sizeof(double))
+          throw Error{LCC_ERR_ARG, "an operand block exceeds the 2 GiB reach of 32-bit offsets"};
         terms.push_back(tm);
         for (int k0 = 0; k0 < tm.k; k0 += 4) {
           SlotRec r{};

@@ -18,6 +18,19 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// Operand and output pointers live in a by-value struct (Bases); read through them as is, they
+// are generic (flat) pointers, whose loads also count against the LDS wait counter and so hold
+// up the LDS reads that follow a prefetch.  The kernels address device memory through these
+// global-address-space views instead.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+template <class T>
+using gmut = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> global_view(const T* p) { return (gptr<T>)p; }
+template <class T>
+__device__ __forceinline__ gmut<T> global_mut(T* p) { return (gmut<T>)p; }
+
 constexpr int kThreads = 256;
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Tiles are handed out in runs of
@@ -87,19 +100,42 @@ struct QuadRef {
   T alpha;
 };
 
+// A pointer that is the same in every lane, moved to scalar registers.
 template <class T>
-__device__ __forceinline__ T* pick_base(const Bases<T>& bs, int i) {
-  T* p = bs.p[0];
-#pragma unroll
-  for (int j = 1; j < NUM_BASES; ++j) p = (i == j) ? bs.p[j] : p;
-  return p;
+__device__ __forceinline__ T* uniform(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
 }
 
+// The launch's operand base pointers (or, in a batched launch, the problem's row of the
+// table), staged in LDS: a term's base is then one LDS read with its base index, where
+// indexing the by-value argument struct would copy it to private memory.
 template <class T>
-__device__ __forceinline__ void resolve_quad(QuadRef<T>& Q, const SlotRec& s, bool valid, const Bases<T>& bs) {
+struct BaseTable {
+  T* p[NUM_BASES];
+  // threads < NUM_BASES write; the caller synchronises before use
+  __device__ __forceinline__ void stage(const Bases<T>& bs, const Bases<T>* row) {
+    const int tid = threadIdx.x;
+    if (tid < NUM_BASES) {
+      T* v = bs.p[0];
+#pragma unroll
+      for (int j = 1; j < NUM_BASES; ++j)
+        if (tid == j) v = bs.p[j];
+      if (row) v = row->p[tid];
+      p[tid] = v;
+    }
+  }
+  // base i, for an index that is the same in every lane
+  __device__ __forceinline__ T* get(int i) const { return uniform(p[i]); }
+};
+
+template <class T>
+__device__ __forceinline__ void resolve_quad(QuadRef<T>& Q, const SlotRec& s, bool valid, const BaseTable<T>& bt) {
   if (valid) {
-    Q.a = pick_base(bs, s.a_base) + s.a_off;
-    Q.b = pick_base(bs, s.b_base) + s.b_off;
+    Q.a = bt.p[s.a_base] + s.a_off;
+    Q.b = bt.p[s.b_base] + s.b_off;
     Q.lda = s.lda;
     Q.ldb = s.ldb;
     Q.kv = s.kv;
@@ -112,13 +148,13 @@ __device__ __forceinline__ void resolve_quad(QuadRef<T>& Q, const SlotRec& s, bo
   }
 }
 
-__device__ __forceinline__ void load_quad(float* v, const float* p) {
-  const f4u w = *reinterpret_cast<const f4u*>(p);
+__device__ __forceinline__ void load_quad(float* v, gptr<float> p) {
+  const f4u w = *(const __attribute__((address_space(1))) f4u*)p;
   v[0] = w[0]; v[1] = w[1]; v[2] = w[2]; v[3] = w[3];
 }
-__device__ __forceinline__ void load_quad(double* v, const double* p) {
-  const d2u w0 = *reinterpret_cast<const d2u*>(p);
-  const d2u w1 = *reinterpret_cast<const d2u*>(p + 2);
+__device__ __forceinline__ void load_quad(double* v, gptr<double> p) {
+  const d2u w0 = *(const __attribute__((address_space(1))) d2u*)p;
+  const d2u w1 = *(const __attribute__((address_space(1))) d2u*)(p + 2);
   v[0] = w0[0]; v[1] = w0[1]; v[2] = w1[0]; v[3] = w1[1];
 }
 // 16-byte-aligned LDS quads (two 16-byte accesses for double).
@@ -177,7 +213,7 @@ struct Stager {
       const int gr = r0 + r;
       if (KC) {
         if (gr >= rmax || Q.kv == 0) continue;
-        const T* p = P + (int64_t)gr * ld;
+        const gptr<T> p = global_view(P) + (int64_t)gr * ld;
         if (Q.kv == 4) {
           load_quad(v[i], p);
         } else {
@@ -188,7 +224,7 @@ struct Stager {
       } else {
         const int jj = kk & 3;
         if (jj >= Q.kv) continue;
-        const T* p = P + (int64_t)jj * ld + gr;
+        const gptr<T> p = global_view(P) + (int64_t)jj * ld + gr;
         if (gr + 3 < rmax) {
           load_quad(v[i], p);
         } else {
@@ -325,6 +361,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
   __shared__ __attribute__((aligned(16))) T Bs[SB::D0][SB::D1];
   __shared__ QuadRef<T> refs[SPC];
 
+  __shared__ BaseTable<T> bt;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -332,10 +369,13 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
+  const Bases<T>* row = nullptr;
   if (table) {  // batched launch: per-problem operands, converged problems skipped
     if (active && !active[g.problem]) return;
-    bases = table[g.problem];
+    row = table + g.problem;
   }
+  bt.stage(bases, row);
+  __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
@@ -360,7 +400,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
     if (tid < SPC) {
       const bool ok = tid < nslots;
       if (ok) pending = gs[tid];
-      resolve_quad(refs[tid], pending, ok, bases);
+      resolve_quad(refs[tid], pending, ok, bt);
     }
     __syncthreads();
     sa.load(refs, row0, g.m);
@@ -372,7 +412,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
     __syncthreads();
     sa.store(As);
     sb.store(Bs);
-    if (tid < SPC) resolve_quad(refs[tid], pending, (c + 1) * SPC + tid < nslots, bases);
+    if (tid < SPC) resolve_quad(refs[tid], pending, (c + 1) * SPC + tid < nslots, bt);
     __syncthreads();
     if (c + 1 < nch) {
       sa.load(refs, row0, g.m);
@@ -382,7 +422,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
     packed_chunk<MODE, TA, TB, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
   }
 
-  T* __restrict__ C = bases.p[g.c_base] + g.c_off;
+  const gmut<T> C = global_mut(bt.get(g.c_base) + g.c_off);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -392,7 +432,7 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
         const int gr = row0 + wm * (BM / WM) + i * 16 + Mfma<MODE>::row(lane, r);
         const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
         if (gr < g.m && gc < g.n) {
-          T* p = C + (int64_t)gr * g.ldc + gc;
+          const gmut<T> p = C + (int64_t)gr * g.ldc + gc;
           *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
         }
       }
@@ -453,6 +493,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
   __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][KP];
   __shared__ QuadRef<float> refs[SPC];
 
+  __shared__ BaseTable<float> bt;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -460,10 +501,13 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
+  const Bases<float>* row = nullptr;
   if (table) {  // batched launch: per-problem operands, converged problems skipped
     if (active && !active[g.problem]) return;
-    bases = table[g.problem];
+    row = table + g.problem;
   }
+  bt.stage(bases, row);
+  __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
@@ -484,7 +528,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
     if (tid < SPC) {
       const bool ok = tid < nslots;
       if (ok) pending = gs[tid];
-      resolve_quad(refs[tid], pending, ok, bases);
+      resolve_quad(refs[tid], pending, ok, bt);
     }
     __syncthreads();
     sa.load(refs, row0, g.m);
@@ -496,7 +540,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
     __syncthreads();
     sa.template store_split<KP>(Ah, Al);
     sb.template store_split<KP>(Bh, Bl);
-    if (tid < SPC) resolve_quad(refs[tid], pending, (c + 1) * SPC + tid < nslots, bases);
+    if (tid < SPC) resolve_quad(refs[tid], pending, (c + 1) * SPC + tid < nslots, bt);
     __syncthreads();
     if (c + 1 < nch) {
       sa.load(refs, row0, g.m);
@@ -507,7 +551,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
     bf16x3_chunk<TM, TN>(Ah, Al, Bh, Bl, arow, bcol, acc);
   }
 
-  float* __restrict__ C = bases.p[g.c_base] + g.c_off;
+  const gmut<float> C = global_mut(bt.get(g.c_base) + g.c_off);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -517,7 +561,7 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
         const int gr = row0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + r;
         const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
         if (gr < g.m && gc < g.n) {
-          float* p = C + (int64_t)gr * g.ldc + gc;
+          const gmut<float> p = C + (int64_t)gr * g.ldc + gc;
           *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
         }
       }
@@ -528,42 +572,73 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
 // chunks of BK k (a term's last chunk is partial).  Lane layouts of the MFMAs as below; the LDS
 // tiles are [k][m] and [k][n] and every MFMA operand is one LDS read.
 // ------------------------------------------------------------------------------------------
-// Operand staging shared by the kernels: each thread holds NA elements of the next A chunk
-// and NB of the next B chunk in registers, so the global loads of chunk i+1 are in flight
-// while the MFMAs of chunk i run.  Element e of a chunk maps to (row, k) so that consecutive
-// threads read consecutive addresses of the stored (row-major) operand.
-template <class T, bool TA, int BM, int BK, int NT>
-struct ALoader {
-  static constexpr int N = BM * BK / NT;
-  static __device__ __forceinline__ void coords(int e, int& mm, int& kk) {
-    if (!TA) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-  }
-  static __device__ __forceinline__ void load(T (&r)[N], const T* __restrict__ A, int lda, int row0, int m,
-                                              int k0, int K) {
+// Operand staging of the term-walk kernels: each thread holds N elements of the next A chunk
+// and N of the next B chunk in registers, so the global loads of chunk i+1 are in flight while
+// the MFMAs of chunk i run.
+//
+// A block is read through a buffer resource whose base is the block's first element: element
+// (slow, fast), with `fast` the contiguous coordinate, is at byte (slow * ld + fast) *
+// sizeof(T).  Byte offsets within a block fit 31 bits (checked by the planner); an element
+// outside the block gets the offset 2^31, which the buffer's range check turns into a zero
+// load.  Thread t holds fast = t % FAST and slow = t / FAST + i * STEP (i = 0..N-1), so
+// consecutive threads read consecutive addresses and the offsets of a thread's elements differ
+// by a uniform stride.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, 0x7fffffff, 0x00020000);
+}
+constexpr unsigned kOutside = 0x80000000u;
+__device__ __forceinline__ void buffer_load(float& v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buffer_load(double& v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+template <class T, int FAST, int SLOW, int NT>
+struct Strip {
+  static constexpr int STEP = NT / FAST;
+  static constexpr int N = SLOW / STEP;
+  static_assert(NT % FAST == 0 && SLOW % STEP == 0, "strip does not tile the chunk");
+  static __device__ __forceinline__ int fast() { return threadIdx.x % FAST; }
+  static __device__ __forceinline__ int slow(int i) { return (int)threadIdx.x / FAST + i * STEP; }
+  // elements [slow0, slow_lim) x [fast0, fast_lim) of the block at P are in range
+  static __device__ __forceinline__ void load(T (&r)[N], const T* P, int ld, int slow0, int slow_lim, int fast0,
+                                              int fast_lim) {
+    const __amdgpu_buffer_rsrc_t rs = block_rsrc(P);
+    const int f = fast(), s = slow(0);
+    const bool fok = fast0 + f < fast_lim;
+    const int left = slow_lim - slow0 - s;  // element i is in range while i * STEP < left
+    const unsigned base = ((unsigned)(slow0 + s) * (unsigned)ld + (unsigned)(fast0 + f)) * (unsigned)sizeof(T);
+    const unsigned step = (unsigned)STEP * (unsigned)ld * (unsigned)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      int mm, kk;
-      coords(threadIdx.x + i * NT, mm, kk);
-      const int gr = row0 + mm, gk = k0 + kk;
-      r[i] = (gr < m && gk < K) ? (TA ? A[(int64_t)gk * lda + gr] : A[(int64_t)gr * lda + gk]) : (T)0;
-    }
+    for (int i = 0; i < N; ++i) buffer_load(r[i], rs, (fok && i * STEP < left) ? base + i * step : kOutside);
   }
 };
+
+// A chunk: BM rows x BK k of A (TA: stored k-major, element (k, r) at k * lda + r).
+template <class T, bool TA, int BM, int BK, int NT>
+struct ALoader {
+  typedef Strip<T, TA ? BM : BK, TA ? BK : BM, NT> S;
+  static constexpr int N = S::N;
+  static __device__ __forceinline__ void coords(int i, int& mm, int& kk) {
+    if (TA) { mm = S::fast(); kk = S::slow(i); } else { kk = S::fast(); mm = S::slow(i); }
+  }
+  static __device__ __forceinline__ void load(T (&r)[N], const T* A, int lda, int row0, int m, int k0, int K) {
+    if (TA) S::load(r, A, lda, k0, K, row0, m);
+    else S::load(r, A, lda, row0, m, k0, K);
+  }
+};
+// B chunk: BK k x BN columns of B (TB: stored n-major, element (k, c) at c * ldb + k).
 template <class T, bool TB, int BN, int BK, int NT>
 struct BLoader {
-  static constexpr int N = BN * BK / NT;
-  static __device__ __forceinline__ void coords(int e, int& nn, int& kk) {
-    if (!TB) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
+  typedef Strip<T, TB ? BK : BN, TB ? BN : BK, NT> S;
+  static constexpr int N = S::N;
+  static __device__ __forceinline__ void coords(int i, int& nn, int& kk) {
+    if (TB) { kk = S::fast(); nn = S::slow(i); } else { nn = S::fast(); kk = S::slow(i); }
   }
-  static __device__ __forceinline__ void load(T (&r)[N], const T* __restrict__ B, int ldb, int col0, int n,
-                                              int k0, int K) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      int nn, kk;
-      coords(threadIdx.x + i * NT, nn, kk);
-      const int gc = col0 + nn, gk = k0 + kk;
-      r[i] = (gc < n && gk < K) ? (TB ? B[(int64_t)gc * ldb + gk] : B[(int64_t)gk * ldb + gc]) : (T)0;
-    }
+  static __device__ __forceinline__ void load(T (&r)[N], const T* B, int ldb, int col0, int n, int k0, int K) {
+    if (TB) S::load(r, B, ldb, col0, n, k0, K);
+    else S::load(r, B, ldb, k0, K, col0, n);
   }
 };
 
@@ -619,6 +694,7 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
   __shared__ T As[BK][KPitch<T>::of(BM)];
   __shared__ T Bs[BK][KPitch<T>::of(BN)];
 
+  __shared__ BaseTable<T> bt;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -626,10 +702,13 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
+  const Bases<T>* row = nullptr;
   if (table) {  // batched launch: per-problem operands, converged problems skipped
     if (active && !active[g.problem]) return;
-    bases = table[g.problem];
+    row = table + g.problem;
   }
+  bt.stage(bases, row);
+  __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
@@ -650,8 +729,8 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
   GemmTerm term;
   if (t < g.term_end) {
     term = terms[t];
-    LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, 0, term.k);
-    LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, 0, term.k);
+    LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, 0, term.k);
+    LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, 0, term.k);
   }
   while (t < g.term_end) {
     const T alpha = (T)term.alpha;
@@ -660,13 +739,13 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
 #pragma unroll
     for (int i = 0; i < LA::N; ++i) {
       int mm, kk;
-      LA::coords(tid + i * NT, mm, kk);
+      LA::coords(i, mm, kk);
       As[kk][mm] = alpha * ra[i];
     }
 #pragma unroll
     for (int i = 0; i < LB::N; ++i) {
       int nn, kk;
-      LB::coords(tid + i * NT, nn, kk);
+      LB::coords(i, nn, kk);
       Bs[kk][nn] = rb[i];
     }
     __syncthreads();
@@ -677,13 +756,13 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
       if (t < g.term_end) term = terms[t];
     }
     if (t < g.term_end) {
-      LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, k0, term.k);
-      LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, k0, term.k);
+      LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, k0, term.k);
+      LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, k0, term.k);
     }
     terms_chunk<MODE, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
   }
 
-  T* __restrict__ C = bases.p[g.c_base] + g.c_off;
+  const gmut<T> C = global_mut(bt.get(g.c_base) + g.c_off);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -693,7 +772,7 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
         const int gr = row0 + wm * (BM / WM) + i * 16 + Mfma<MODE>::row(lane, r);
         const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
         if (gr < g.m && gc < g.n) {
-          T* p = C + (int64_t)gr * g.ldc + gc;
+          const gmut<T> p = C + (int64_t)gr * g.ldc + gc;
           *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
         }
       }
@@ -724,6 +803,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
   __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][KP];
 
+  __shared__ BaseTable<float> bt;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -731,10 +811,13 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
+  const Bases<float>* row = nullptr;
   if (table) {  // batched launch: per-problem operands, converged problems skipped
     if (active && !active[g.problem]) return;
-    bases = table[g.problem];
+    row = table + g.problem;
   }
+  bt.stage(bases, row);
+  __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
@@ -750,8 +833,8 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
   GemmTerm term;
   if (t < g.term_end) {
     term = terms[t];
-    LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, 0, term.k);
-    LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, 0, term.k);
+    LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, 0, term.k);
+    LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, 0, term.k);
   }
   while (t < g.term_end) {
     const float alpha = (float)term.alpha;
@@ -759,7 +842,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
 #pragma unroll
     for (int i = 0; i < LA::N; ++i) {
       int mm, kk;
-      LA::coords(tid + i * NT, mm, kk);
+      LA::coords(i, mm, kk);
       const float v = alpha * ra[i];
       const __bf16 h = (__bf16)v;
       Ah[mm][kk] = h;
@@ -768,7 +851,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
 #pragma unroll
     for (int i = 0; i < LB::N; ++i) {
       int nn, kk;
-      LB::coords(tid + i * NT, nn, kk);
+      LB::coords(i, nn, kk);
       const float v = rb[i];
       const __bf16 h = (__bf16)v;
       Bh[nn][kk] = h;
@@ -782,13 +865,13 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
       if (t < g.term_end) term = terms[t];
     }
     if (t < g.term_end) {
-      LA::load(ra, bases.p[term.a_base] + term.a_off, term.lda, row0, g.m, k0, term.k);
-      LB::load(rb, bases.p[term.b_base] + term.b_off, term.ldb, col0, g.n, k0, term.k);
+      LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, k0, term.k);
+      LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, k0, term.k);
     }
     bf16x3_chunk<TM, TN>(Ah, Al, Bh, Bl, arow, bcol, acc);
   }
 
-  float* __restrict__ C = bases.p[g.c_base] + g.c_off;
+  const gmut<float> C = global_mut(bt.get(g.c_base) + g.c_off);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -798,7 +881,7 @@ gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __
         const int gr = row0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + r;
         const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
         if (gr < g.m && gc < g.n) {
-          float* p = C + (int64_t)gr * g.ldc + gc;
+          const gmut<float> p = C + (int64_t)gr * g.ldc + gc;
           *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
         }
       }
