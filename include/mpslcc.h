@@ -205,8 +205,8 @@ lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const 
 
 /* Autotuning of the H_eff x plan for the block-size histogram of this environment (bond
  * sectors and dimensions, MPO bond dimension).  Times on the device every candidate of the
- * planner parameters (tile_overhead in {512, 2048, 8192}: per-tile cost, in output
- * elements, of the tile-shape choice; split_k in {1024, 2048, 4096}: accumulation length of
+ * planner parameters (tile_overhead in {2048, 8192, 32768}: per-tile cost, in output
+ * elements, of the tile-shape choice; split_k in {512, 1024, 2048}: accumulation length of
  * a phase-2 split-K part; p2_order in {0, 1}: phase-2 output blocks one after the other, or
  * their parts interleaved by channel so that parts reading the same intermediate columns are
  * neighbours; t_colmajor in {0, 1}: the phase-1 intermediate stored row- or column-major,

@@ -19,8 +19,8 @@ namespace lcc {
 
 namespace {
 
-constexpr double kOverheads[] = {512.0, 2048.0, 8192.0};
-constexpr int64_t kSplits[] = {1024, 2048, 4096};
+constexpr double kOverheads[] = {2048.0, 8192.0, 32768.0};
+constexpr int64_t kSplits[] = {512, 1024, 2048};
 
 void fnv(uint64_t& h, int64_t v) {
   for (int i = 0; i < 8; ++i) {
