@@ -52,20 +52,21 @@ def source_digest() -> str:
 def kernel_name(precision: str, launch: dict) -> str:
     if launch["kind"] == "reduce":
         return "reduce_kernel<%s>" % ("double" if precision == "fp64" else "float")
-    tb = "true" if launch["phase"] == 2 else "false"
+    ta = "true" if launch["a_kmajor"] else "false"
+    tb = "true" if launch["b_colmajor"] else "false"
     bm, bn = launch["tile"]
     waves = {(64, 64): (2, 2), (16, 64): (1, 4), (64, 16): (4, 1), (32, 32): (2, 2), (128, 64): (2, 2),
              (64, 128): (2, 2), (32, 64): (2, 2), (64, 32): (2, 2)}[(bm, bn)]
     kind = "packed" if launch.get("packed") else "terms"
     if precision == "bf16x3":
-        return f"gemm_bf16x3_{kind}_kernel<false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
+        return f"gemm_bf16x3_{kind}_kernel<{ta}, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
     mode = 0 if precision == "fp64" else 1
-    return f"gemm_{kind}_kernel<{mode}, false, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
+    return f"gemm_{kind}_kernel<{mode}, {ta}, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
 
 
-def measured_traffic(kname: str, workload: str):
-    """HBM bytes per launch of `kname` from the committed PMC summary, if the kernel sources
-    have not changed since the counters were taken (else None)."""
+def measured_traffic(kname: str, tiles: int, workload: str):
+    """HBM bytes per launch of `kname` with `tiles` workgroups from the committed PMC summary, if
+    the kernel sources have not changed since the counters were taken (else None)."""
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -75,7 +76,7 @@ def measured_traffic(kname: str, workload: str):
         return None
     if rec.get("source_sha1") != source_digest():
         return None
-    ent = rec.get("kernels", {}).get(kname)
+    ent = rec.get("kernels", {}).get(f"{kname} x{tiles}")
     return None if ent is None else ent.get("traffic_bytes")
 
 
@@ -425,8 +426,9 @@ def main():
     achieved = mult * dom["flops"] / (dom["ms"] * 1e-3) / 1e12
     kname = kernel_name(args.precision, dom)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(kname, args.workload), "kernel": kname,
+                "traffic": measured_traffic(kname, dom["n_tiles"], args.workload), "kernel": kname,
                 "launch_ms": dom["ms"], "launch_flops": dom["flops"], "launch_algorithmic_bytes": dom["bytes"],
+                "launch_tiles": dom["n_tiles"],
                 "launches_per_apply": len(launches),
                 "note": ("bf16x3 counts the three bf16 MFMA products per algorithmic flop" if mult == 3.0 else
                          "achieved = the launch's algorithmic flops / its mean HIP-event duration")}

@@ -196,9 +196,10 @@ typedef struct {
   int32_t packed;   /* GEMM kernel: 0 = term walk, 1 = packed k */
   double flops;     /* algorithmic flops of the launch (2 m n k over its block products) */
   double bytes;     /* algorithmic bytes: operands read once + outputs written once */
-  double exec_flops; /* MFMA work issued, including tile padding and the 16-wide k groups */
+  double exec_flops; /* MFMA work issued, including padding to the kernel's sub-tiles and k groups */
   float ms;         /* mean duration */
-  float pad;
+  int32_t layout;   /* GEMM operand storage: bit 0 A k-major (element (k, r) at k lda + r), bit 1 B
+                       column-major (element (k, c) at c ldb + k); 0 for the reduction */
 } lcc_launch_profile;
 lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev,
                                     int32_t reps, int32_t* count, lcc_launch_profile* out);

@@ -167,6 +167,7 @@ std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const 
       p.tile_n = kTileShapes[L.shape][1];
       p.n_tiles = L.n_tiles;
       p.packed = L.packed[precision] ? 1 : 0;
+      p.layout = (L.ta ? 1 : 0) | (L.tb ? 2 : 0);
       p.flops = L.flops;
       p.exec_flops = L.exec_flops[precision][L.packed[precision] ? 1 : 0];
       p.bytes = (L.elems_read + L.elems_written) * esz;

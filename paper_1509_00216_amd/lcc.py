@@ -80,7 +80,7 @@ class SolveInfo(C.Structure):
 class LaunchProfile(C.Structure):
     _fields_ = [("phase", C.c_int32), ("kind", C.c_int32), ("tile_m", C.c_int32), ("tile_n", C.c_int32),
                 ("n_tiles", C.c_int32), ("packed", C.c_int32), ("flops", C.c_double), ("bytes", C.c_double),
-                ("exec_flops", C.c_double), ("ms", C.c_float), ("pad", C.c_float)]
+                ("exec_flops", C.c_double), ("ms", C.c_float), ("layout", C.c_int32)]
 
 
 class TuneInfo(C.Structure):
@@ -394,7 +394,7 @@ class Env:
                                             _tensor_ptr(y, dt, self.n), reps, C.byref(cnt), arr), self.ctx.handle)
         return [{"phase": a.phase, "kind": "gemm" if a.kind == 0 else "reduce", "tile": (a.tile_m, a.tile_n),
                  "n_tiles": a.n_tiles, "packed": bool(a.packed), "flops": a.flops, "bytes": a.bytes,
-                 "exec_flops": a.exec_flops, "ms": a.ms}
+                 "exec_flops": a.exec_flops, "ms": a.ms, "a_kmajor": bool(a.layout & 1), "b_colmajor": bool(a.layout & 2)}
                 for a in arr[: cnt.value]]
 
     def autotune(self, precision: str = "fp32", reps: int = 3) -> dict:
