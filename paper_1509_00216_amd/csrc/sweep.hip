@@ -30,28 +30,45 @@ __global__ void scale_rows_kernel(double* __restrict__ dst, const double* __rest
 }
 
 // ---------------------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi SVD, one workgroup per middle-bond sector.
+// One-sided (Hestenes) Jacobi SVD of every middle-bond sector, blocked over workgroups.
 //
 // The sector block X (row-major nrows x ncols) is copied into a column-major m x n workspace
-// W with n = min(nrows, ncols): W = X if nrows >= ncols, else W = X^T.  Pairs of columns are
-// rotated until every pair is orthogonal to a relative tolerance (cyclic round-robin order:
-// each step rotates n/2 disjoint pairs, 16 lanes per pair); the rotations accumulate in V
-// (n x n), so that W V_0 ... = U diag(s).  Singular values are the final column norms; they
-// are written in descending order together with the matching vectors:
+// W with n = min(nrows, ncols): W = X if nrows >= ncols, else W = X^T; V (n x n, column j
+// contiguous) starts as the identity.  Pairs of columns are rotated until every pair is
+// orthogonal to a relative tolerance; the rotations accumulate in V, so that W V_0 ... =
+// U diag(s).  Singular values are the final column norms, written in descending order
+// together with the matching vectors:
 //   left vectors of X  (row-major nrows x n)  -> L,   right vectors (row-major n x ncols) -> R.
-// One-sided Jacobi computes small singular values to high relative accuracy.
+//
+// Blocking: the n columns are cut into nb blocks of w columns.  One outer sweep is a
+// round-robin over the blocks (nb - 1 rounds, one more with a dummy when nb is odd); in a
+// round, every pair of blocks goes to one workgroup, which copies the pair's columns into LDS,
+// runs one-sided Jacobi sweeps among them (rotation angles from the columns' own dot
+// products, as in the unblocked method, so small singular values keep their relative
+// accuracy), accumulates the rotations in a small matrix Q, writes the columns back and
+// applies Q to the same columns of V.  A sector has converged when a whole outer sweep finds
+// no pair to rotate.  One launch per round, all sectors together; sectors with fewer rounds or
+// already converged leave their workgroups idle.
 // ---------------------------------------------------------------------------------------
 struct SvdJob {
   int64_t x_off;                // the block in the two-site vector
   int64_t w_off;                // workspace: W (m n), V (n n), norms (n), ranks (n)
   int64_t s_off, l_off, r_off;  // outputs
   int32_t nrows, ncols;
+  int32_t w, nb;                // columns per block, blocks
+};
+struct SvdSlot {  // one workgroup of a round: job and pair index in the round-robin
+  int32_t job, k;
 };
 constexpr int kSvdThreads = 1024;
 constexpr int kSvdMaxSweeps = 60;
 constexpr double kSvdTol = 1e-14;  // |w_i . w_j| <= tol ||w_i|| ||w_j|| counts as orthogonal
+constexpr int kSvdMaxW = 8;        // columns per block (a pair of blocks: at most 16 columns)
+constexpr int kSvdLdsCols = 120 * 1024 / (int)sizeof(double);  // LDS budget for a pair's columns, elements
+constexpr int kSvdInner = 1;       // Jacobi sweeps per visit of a block pair (more when it is the whole matrix)
+constexpr int kSvdRoundThreads = 64 * kSvdMaxW;  // one wave per column pair of a block pair
 
-constexpr int kSvdGroup = 16;  // lanes per column pair
+constexpr int kSvdGroup = 64;  // lanes (one wave) per column pair inside a block pair
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -65,9 +82,138 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+// players i, j of pair k in round r of a round-robin over N (even) players
+__device__ __forceinline__ void round_robin(int N, int r, int k, int& i, int& j) {
+  i = k == 0 ? N - 1 : (r + k) % (N - 1);
+  j = k == 0 ? r : (r - k + N - 1) % (N - 1);
+}
+
 __global__ void __launch_bounds__(kSvdThreads)
-jacobi_svd_kernel(const SvdJob* __restrict__ jobs, const double* __restrict__ x, double* __restrict__ work,
-                  double* __restrict__ S, double* __restrict__ L, double* __restrict__ R, int* __restrict__ failed) {
+svd_setup_kernel(const SvdJob* __restrict__ jobs, const double* __restrict__ x, double* __restrict__ work) {
+  const SvdJob jb = jobs[blockIdx.x];
+  const bool tall = jb.nrows >= jb.ncols;
+  const int m = tall ? jb.nrows : jb.ncols, n = tall ? jb.ncols : jb.nrows;
+  double* W = work + jb.w_off;
+  double* V = W + (int64_t)m * n;
+  const double* X = x + jb.x_off;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
+    const int j = (int)(e / m), i = (int)(e % m);
+    W[e] = tall ? X[(int64_t)i * jb.ncols + j] : X[(int64_t)j * jb.ncols + i];
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+// One round of the blocked sweep.  rot[job] is set when a pair of the job needed a rotation;
+// done[job] marks converged jobs.
+__global__ void __launch_bounds__(kSvdRoundThreads)
+svd_round_kernel(const SvdJob* __restrict__ jobs, const SvdSlot* __restrict__ slots, int round,
+                 double* __restrict__ work, int* __restrict__ rot, const int* __restrict__ done) {
+  extern __shared__ double cols[];  // the pair's columns, column-major m x cnt
+  __shared__ double Q[2 * kSvdMaxW][2 * kSvdMaxW];
+  __shared__ int col_of[2 * kSvdMaxW];
+  __shared__ int rotated, any;
+  const SvdSlot sl = slots[blockIdx.x];
+  if (done[sl.job]) return;
+  const SvdJob jb = jobs[sl.job];
+  const int N = jb.nb + (jb.nb & 1);
+  if (round >= N - 1 && !(jb.nb == 1 && round == 0)) return;  // this job has fewer rounds
+  int bp = 0, bq = 1;
+  if (jb.nb > 1) round_robin(N, round, sl.k, bp, bq);
+  const bool tall = jb.nrows >= jb.ncols;
+  const int m = tall ? jb.nrows : jb.ncols, n = tall ? jb.ncols : jb.nrows;
+  double* W = work + jb.w_off;
+  double* V = W + (int64_t)m * n;
+  // columns of the pair: block bp, then block bq (a dummy block, index >= nb, has none)
+  const int np = bp < jb.nb ? min(n, (bp + 1) * jb.w) - bp * jb.w : 0;
+  const int nq = bq < jb.nb ? min(n, (bq + 1) * jb.w) - bq * jb.w : 0;
+  const int cnt = np + nq;
+  if (cnt < 2) return;  // a lone column: nothing to rotate
+  if (threadIdx.x < cnt) col_of[threadIdx.x] = threadIdx.x < np ? bp * jb.w + threadIdx.x : bq * jb.w + threadIdx.x - np;
+  if (threadIdx.x == 0) {
+    rotated = 0;
+    any = 0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * cnt; e += blockDim.x) cols[e] = W[(int64_t)col_of[e / m] * m + e % m];
+  for (int e = threadIdx.x; e < 4 * kSvdMaxW * kSvdMaxW; e += blockDim.x) {
+    const int a = e / (2 * kSvdMaxW), b = e % (2 * kSvdMaxW);
+    Q[a][b] = a == b ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int gl = threadIdx.x % kSvdGroup, grp = threadIdx.x / kSvdGroup;
+  const int N2 = cnt + (cnt & 1);
+  const int inner = jb.nb == 1 ? kSvdMaxSweeps : kSvdInner;
+  for (int sweep = 0; sweep < inner; ++sweep) {
+    for (int r = 0; r < N2 - 1; ++r) {
+      if (grp < N2 / 2) {
+        int i, j;
+        round_robin(N2, r, grp, i, j);
+        if (i < cnt && j < cnt) {
+          if (i > j) {
+            const int t = i;
+            i = j;
+            j = t;
+          }
+          double* wi = cols + i * m;
+          double* wj = cols + j * m;
+          double a = 0, b = 0, g = 0;
+          for (int t = gl; t < m; t += kSvdGroup) {
+            const double u = wi[t], v = wj[t];
+            a += u * u;
+            b += v * v;
+            g += u * v;
+          }
+          a = group_sum(a);
+          b = group_sum(b);
+          g = group_sum(g);
+          if (fabs(g) > kSvdTol * sqrt(a * b)) {
+            const double zeta = (b - a) / (2.0 * g);
+            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+            for (int q = gl; q < m; q += kSvdGroup) {
+              const double u = wi[q], v = wj[q];
+              wi[q] = c * u - s * v;
+              wj[q] = s * u + c * v;
+            }
+            for (int q = gl; q < cnt; q += kSvdGroup) {
+              const double u = Q[q][i], v = Q[q][j];
+              Q[q][i] = c * u - s * v;
+              Q[q][j] = s * u + c * v;
+            }
+            if (gl == 0) rotated = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int rs = rotated;
+    __syncthreads();
+    if (rs == 0) break;
+    if (threadIdx.x == 0) {
+      any = 1;
+      rotated = 0;
+    }
+    __syncthreads();
+  }
+  if (any == 0) return;  // the pair was orthogonal: W and V unchanged
+  if (threadIdx.x == 0) rot[sl.job] = 1;
+  for (int e = threadIdx.x; e < m * cnt; e += blockDim.x) W[(int64_t)col_of[e / m] * m + e % m] = cols[e];
+  __syncthreads();
+  // V(:, C) <- V(:, C) Q, through LDS (n <= m, so the pair's V columns fit where W's were)
+  for (int e = threadIdx.x; e < n * cnt; e += blockDim.x) cols[e] = V[(int64_t)col_of[e / n] * n + e % n];
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * cnt; e += blockDim.x) {
+    const int c = e / n, t = e % n;
+    double v = 0;
+    for (int k = 0; k < cnt; ++k) v += cols[k * n + t] * Q[k][c];
+    V[(int64_t)col_of[c] * n + t] = v;
+  }
+}
+
+// Singular values (column norms, descending) and vectors of every converged job.
+__global__ void __launch_bounds__(kSvdThreads)
+svd_finalize_kernel(const SvdJob* __restrict__ jobs, double* __restrict__ work, double* __restrict__ S,
+                    double* __restrict__ L, double* __restrict__ R) {
   const SvdJob jb = jobs[blockIdx.x];
   const bool tall = jb.nrows >= jb.ncols;
   const int m = tall ? jb.nrows : jb.ncols, n = tall ? jb.ncols : jb.nrows;
@@ -75,67 +221,7 @@ jacobi_svd_kernel(const SvdJob* __restrict__ jobs, const double* __restrict__ x,
   double* V = W + (int64_t)m * n;
   double* nrm = V + (int64_t)n * n;
   double* rank = nrm + n;
-  const double* X = x + jb.x_off;
-  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
-    const int j = (int)(e / m), i = (int)(e % m);
-    W[e] = tall ? X[(int64_t)i * jb.ncols + j] : X[(int64_t)j * jb.ncols + i];
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __shared__ int rotated;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int gl = threadIdx.x % kSvdGroup, grp = threadIdx.x / kSvdGroup, ngrp = blockDim.x / kSvdGroup;
-  const int N = n + (n & 1);  // round-robin players (one dummy when n is odd)
-  bool converged = n < 2;
-  for (int sweep = 0; sweep < kSvdMaxSweeps && !converged; ++sweep) {
-    if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
-    for (int r = 0; r < N - 1; ++r) {
-      for (int k = grp; k < N / 2; k += ngrp) {
-        int i = k == 0 ? N - 1 : (r + k) % (N - 1);
-        int j = k == 0 ? r : (r - k + N - 1) % (N - 1);
-        if (i >= n || j >= n) continue;  // the dummy player
-        if (i > j) {
-          const int t = i;
-          i = j;
-          j = t;
-        }
-        double* wi = W + (int64_t)i * m;
-        double* wj = W + (int64_t)j * m;
-        double a = 0, b = 0, g = 0;
-        for (int t = gl; t < m; t += kSvdGroup) {
-          const double u = wi[t], v = wj[t];
-          a += u * u;
-          b += v * v;
-          g += u * v;
-        }
-        a = group_sum(a);
-        b = group_sum(b);
-        g = group_sum(g);
-        if (!(fabs(g) > kSvdTol * sqrt(a * b))) continue;
-        const double zeta = (b - a) / (2.0 * g);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int q = gl; q < m; q += kSvdGroup) {
-          const double u = wi[q], v = wj[q];
-          wi[q] = c * u - s * v;
-          wj[q] = s * u + c * v;
-        }
-        double* vi = V + (int64_t)i * n;
-        double* vj = V + (int64_t)j * n;
-        for (int q = gl; q < n; q += kSvdGroup) {
-          const double u = vi[q], v = vj[q];
-          vi[q] = c * u - s * v;
-          vj[q] = s * u + c * v;
-        }
-        if (gl == 0) rotated = 1;
-      }
-      __syncthreads();
-    }
-    converged = rotated == 0;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) failed[blockIdx.x] = converged ? 0 : 1;
-  if (!converged) return;
   for (int j = wave; j < n; j += nwaves) {
     const double* wj = W + (int64_t)j * m;
     double a = 0;
@@ -240,31 +326,70 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     SvdJob& j = jobs[q];
     j.x_off = M.off;
     j.w_off = w_tot;
-    w_tot += (int64_t)std::max(M.nrows, M.ncols) * p.r + (int64_t)p.r * p.r + 2 * (int64_t)p.r;
+    const int mm = std::max(M.nrows, M.ncols);
+    w_tot += (int64_t)mm * p.r + (int64_t)p.r * p.r + 2 * (int64_t)p.r;
     j.s_off = p.s_off;
     j.l_off = p.v_off;
     j.r_off = p.u_off;
     j.nrows = M.nrows;
     j.ncols = M.ncols;
+    // a pair of blocks (2w columns of mm rows) must fit the LDS budget of the round kernel
+    if (2 * mm > kSvdLdsCols) throw Error{LCC_ERR_ARG, "a middle-bond sector is too tall for the blocked SVD"};
+    j.w = std::max(1, std::min(kSvdMaxW, kSvdLdsCols / (2 * mm)));
+    j.nb = std::max(1, (p.r + j.w - 1) / j.w);
   }
-  DevBuf Sv, U, V, Wk, fail, djobs;
+  // workgroups of a round: the pairs of each job's round-robin over its blocks
+  std::vector<SvdSlot> slots;
+  int rounds = 1;
+  int64_t lds_cols = 1;  // LDS of the round kernel: the largest pair of blocks
+  for (int q = 0; q < nsec; ++q) {
+    lds_cols = std::max<int64_t>(lds_cols, 2 * (int64_t)jobs[q].w * std::max(jobs[q].nrows, jobs[q].ncols));
+    const int N = jobs[q].nb + (jobs[q].nb & 1);
+    rounds = std::max(rounds, N - 1);
+    for (int k = 0; k < std::max(1, N / 2); ++k) slots.push_back(SvdSlot{q, k});
+  }
+  DevBuf Sv, U, V, Wk, rot, done, djobs, dslots;
   Sv.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
   U.alloc(sizeof(double) * std::max<int64_t>(u_tot, 1));
   V.alloc(sizeof(double) * std::max<int64_t>(v_tot, 1));
   Wk.alloc(sizeof(double) * std::max<int64_t>(w_tot, 1));
-  fail.alloc(sizeof(int) * std::max(nsec, 1));
+  rot.alloc(sizeof(int) * std::max(nsec, 1));
+  done.alloc(sizeof(int) * std::max(nsec, 1));
   upload(djobs, jobs, st);
-  if (nsec > 0)
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nsec), dim3(kSvdThreads), 0, st, djobs.as<SvdJob>(), x,
-                       Wk.as<double>(), Sv.as<double>(), V.as<double>(), U.as<double>(), fail.as<int>());
-  check_hip(hipGetLastError(), "jacobi svd");
+  upload(dslots, slots, st);
   std::vector<double> hs(s_tot);
-  std::vector<int> hfail(nsec);
+  if (nsec > 0) {
+    const size_t lds = sizeof(double) * lds_cols;
+    check_hip(hipFuncSetAttribute((const void*)svd_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+              "svd lds");
+    hipLaunchKernelGGL(svd_setup_kernel, dim3(nsec), dim3(kSvdThreads), 0, st, djobs.as<SvdJob>(), x, Wk.as<double>());
+    check_hip(hipMemsetAsync(done.p, 0, sizeof(int) * nsec, st), "svd flags");
+    std::vector<int> hrot(nsec), hdone(nsec, 0);
+    bool converged = false;
+    for (int sweep = 0; sweep < kSvdMaxSweeps && !converged; ++sweep) {
+      check_hip(hipMemsetAsync(rot.p, 0, sizeof(int) * nsec, st), "svd flags");
+      for (int r = 0; r < rounds; ++r)
+        hipLaunchKernelGGL(svd_round_kernel, dim3((unsigned)slots.size()), dim3(kSvdRoundThreads), lds, st,
+                           djobs.as<SvdJob>(), dslots.as<SvdSlot>(), r, Wk.as<double>(), rot.as<int>(),
+                           (const int*)done.as<int>());
+      check_hip(hipGetLastError(), "jacobi svd round");
+      check_hip(hipMemcpyAsync(hrot.data(), rot.p, sizeof(int) * nsec, hipMemcpyDeviceToHost, st), "svd flag copy");
+      check_hip(hipStreamSynchronize(st), "svd sweep");
+      converged = true;
+      for (int q = 0; q < nsec; ++q) {
+        if (hrot[q] == 0) hdone[q] = 1;
+        converged = converged && hdone[q];
+      }
+      if (!converged)
+        check_hip(hipMemcpyAsync(done.p, hdone.data(), sizeof(int) * nsec, hipMemcpyHostToDevice, st), "svd flags");
+    }
+    if (!converged) throw Error{LCC_ERR_NAN, "Jacobi SVD did not converge in a sector (non-finite input?)"};
+    hipLaunchKernelGGL(svd_finalize_kernel, dim3(nsec), dim3(kSvdThreads), 0, st, djobs.as<SvdJob>(), Wk.as<double>(),
+                       Sv.as<double>(), V.as<double>(), U.as<double>());
+    check_hip(hipGetLastError(), "jacobi svd finalize");
+  }
   check_hip(hipMemcpyAsync(hs.data(), Sv.p, sizeof(double) * s_tot, hipMemcpyDeviceToHost, st), "sv copy");
-  check_hip(hipMemcpyAsync(hfail.data(), fail.p, sizeof(int) * nsec, hipMemcpyDeviceToHost, st), "svd flag copy");
   check_hip(hipStreamSynchronize(st), "svd");
-  for (int q = 0; q < nsec; ++q)
-    if (hfail[q] != 0) throw Error{LCC_ERR_NAN, "Jacobi SVD did not converge in a sector (non-finite input?)"};
   const float ms_svd = ms_since(t_start);
   // ---- global truncation: the m_max largest singular values; ties by sector (N, 2Sz), then index
   struct Cand { double v; int q, i; };
