@@ -157,3 +157,18 @@ def test_abinitio_full_size_hermitian_and_bounded(ctx):
     # determinism: a second FP64 application is bitwise identical
     ax2 = _apply(torch, env, x, "fp64")
     assert np.array_equal(ax, ax2)
+    # the plan the benchmark times (the shipped tuning cache: column-major intermediate,
+    # channel-major phase 2, tuned tile costs and split-K, per-launch kernel choice) gives the
+    # same product: FP64 to rounding, FP32 within the FP32 tolerance
+    import os
+    from paper_1509_00216_amd import lcc as L
+    tctx = L.Context(0)
+    tctx.set_tune_cache(os.path.join(os.path.dirname(L.LIB_PATH), "tune_cache.txt"))
+    tenv = tctx.build_environments(tctx.create_hamiltonian(spec), mps)
+    prof = tenv.profile_launches(to_dev(torch, x, torch.float32), to_dev(torch, x, torch.float32), "fp32", reps=1)
+    say(f"  tuned plan: {len(prof)} launches, A k-major in {sum(p['a_kmajor'] for p in prof if p['kind'] == 'gemm')}")
+    tx = _apply(torch, tenv, x, "fp64")
+    tx32 = _apply(torch, tenv, x, "fp32")
+    say(f"  tuned vs default plan: fp64 {rel(tx, ax):.3e}  fp32 {rel(tx32, ax):.3e}")
+    assert rel(tx, ax) <= 1e-12
+    assert rel(tx32, ax) <= 1e-5
