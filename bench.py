@@ -181,14 +181,16 @@ def run_batch(args):
     t_setup = time.perf_counter() - t0
     xs = [torch.zeros_like(b) for b in bs]
     batch = lcc.Batch(ctx, envs)
-    status, infos = batch.solve(bs, e0s, xs, precision=args.precision, tol=1e-10, max_iter=5000)  # warm-up
+    status, infos = batch.solve(bs, e0s, xs, precision=args.precision, tol=1e-10, max_iter=5000,
+                                inner_tol=args.inner_tol)  # warm-up
     torch.cuda.synchronize()
     reps = max(1, args.steps)
     t0 = time.perf_counter()
     for _ in range(reps):
         for x in xs:
             x.zero_()
-        status, infos = batch.solve(bs, e0s, xs, precision=args.precision, tol=1e-10, max_iter=5000)
+        status, infos = batch.solve(bs, e0s, xs, precision=args.precision, tol=1e-10, max_iter=5000,
+                                    inner_tol=args.inner_tol)
     torch.cuda.synchronize()
     ms_batch = (time.perf_counter() - t0) * 1e3 / reps
     # sequential FP64 baseline on the same problems
