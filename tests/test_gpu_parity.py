@@ -80,6 +80,26 @@ def test_small_systems_vs_fock(ctx, label, make, m, seed):
     assert err["bf16x3"] <= 1e-3
 
 
+@pytest.mark.parametrize("plan", ["default", "benchmarked"])
+def test_every_block_position_vs_fock(plan):
+    """The two-site block at every position of the chain, both ends included (one environment
+    is the trivial one there), against the Fock-space effective Hamiltonian; with the default
+    planner parameters and with those of the benchmarked plan (column-major intermediate,
+    channel-major phase 2, large tiles, short split-K parts)."""
+    torch, lcc = need_gpu()
+    spec = H.random_ab_initio(6, 6, seed=71)
+    pctx = lcc.Context(0)
+    if plan == "benchmarked":
+        pctx.set_plan(8192.0, 1024, 1, 1)
+    for center in range(spec["n_orb"] - 1):
+        mps = M.random_mps(6, 6, 0, 14, seed=72 + center, center=center)
+        err, env = _case_o1(pctx, spec, mps, f"abinitio_k6 block ({center},{center + 1}) {plan}")
+        say(f"  n={env.n} errors {err}")
+        assert err["fp64"] <= 1e-12, center
+        assert err["fp32"] <= 1e-5, center
+        assert err["bf16x3"] <= 1e-3, center
+
+
 def _case_o2(ctx, spec, mps, label, precisions=("fp64", "fp32", "bf16x3")):
     torch, lcc = need_gpu()
     say(f"[parity-o2] {label}: build")
