@@ -203,20 +203,24 @@ struct Batch {
 
 namespace {
 
+// One merged launch per tile shape and operand layout: members planned with different
+// layouts (e.g. one with the column-major intermediate) keep separate launches.
 void merge_phase(const std::vector<Env*>& envs, int chunk, int phase, hipStream_t st, std::vector<MergedLaunch>& out) {
-  for (int shape = 0; shape < kNumTileShapes; ++shape) {
+  for (int key = 0; key < 4 * kNumTileShapes; ++key) {
+    const int shape = key / 4;
+    const bool ta = (key & 1) != 0, tb = (key & 2) != 0;
     std::vector<GemmTerm> terms;
     std::vector<SlotRec> slots;
     std::vector<GemmGroup> groups;
     std::vector<GemmTile> tiles;
-    bool ta = false, tb = phase == 2, first = true;
+    bool first = true;
     bool packed[3] = {false, false, false};
     for (size_t p = 0; p < envs.size(); ++p) {
       if (chunk >= (int)envs[p]->plan.chunks.size()) continue;
       const Plan::Chunk& C = envs[p]->plan.chunks[chunk];
       const std::vector<GemmLaunch>& Ls = phase == 1 ? C.phase1 : C.phase2;
       for (const GemmLaunch& L : Ls) {
-        if (L.shape != shape) continue;
+        if (L.shape != shape || L.ta != ta || L.tb != tb) continue;
         const size_t ng = L.groups.bytes / sizeof(GemmGroup);
         auto hs = download<SlotRec>(L.slots, (size_t)L.n_slots, st);
         auto hg = download<GemmGroup>(L.groups, ng, st);
@@ -243,8 +247,6 @@ void merge_phase(const std::vector<Env*>& envs, int chunk, int phase, hipStream_
           for (int q = 0; q < 3; ++q) packed[q] = L.packed[q];
         first = false;
         for (const GemmTile& t : hl) tiles.push_back(GemmTile{t.group + gb0, t.tile});
-        ta = L.ta;
-        tb = L.tb;
       }
     }
     if (tiles.empty()) continue;

@@ -115,3 +115,33 @@ def test_chunked_intermediate_matches(problems):
     say(f"[batch] chunked vs unchunked: {rel(y2.cpu().numpy(), y1.cpu().numpy()):.2e}")
     assert rel(y2.cpu().numpy(), y1.cpu().numpy()) <= 1e-13
     assert env_c.flops_per_apply == env_u.flops_per_apply
+
+
+def test_batch_members_with_different_plans(problems):
+    """Members planned with different operand layouts (row- and column-major intermediate, as
+    tuning-cache entries of different histograms can choose) are merged per layout, so every
+    member keeps its own transposition."""
+    torch, lcc = need_gpu()
+    _, _, refs = problems
+    pctx = lcc.Context(0)
+    members = []
+    for i, idx in enumerate((1, 2, 4, 1)):
+        label, spec, mps, e0, v = refs[idx]
+        if i % 2:
+            pctx.set_plan(8192.0, 1024, 1, 1)
+        else:
+            pctx.set_plan(2048.0, 2048, 0, 0)
+        members.append((f"{label} plan {i % 2}", spec, mps, e0, pctx.build_environments(pctx.create_hamiltonian(spec), mps)))
+    batch = lcc.Batch(pctx, [m[4] for m in members])
+    bs, xs, e0s, exp = [], [], [], []
+    for i, (label, spec, mps, e0, env) in enumerate(members):
+        b, jstar, _, _, _ = _oracle_problem(spec, mps, e0, 300 + i)
+        bs.append(to_dev(torch, env.pack(b), torch.float64))
+        xs.append(torch.zeros_like(bs[-1]))
+        e0s.append(e0)
+        exp.append((label, jstar))
+    status, infos = batch.solve(bs, e0s, xs, precision="fp32", tol=1e-10, max_iter=4000, inner_tol=1e-4)
+    assert status == "LCC_OK", (status, infos)
+    for (label, jstar), info in zip(exp, infos):
+        say(f"  {label}: J {info['hylleraas']:.12f} vs {jstar:.12f}")
+        assert abs(info["hylleraas"] - jstar) <= 1e-8, label
