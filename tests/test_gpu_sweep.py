@@ -40,11 +40,12 @@ def _oracle_sweep(spec, mps, b0, e0, steps, m_max):
     return out
 
 
-@pytest.mark.parametrize("name,m,first,steps,m_max,seed", [
-    ("hubbard2d_4x4_m500", 48, 5, 4, 30, 21),       # truncating sweep across the middle
-    ("threeband_4x2_m2000", 40, 2, 3, 1000, 22),    # m_max above every bond: nothing discarded
+@pytest.mark.parametrize("name,m,first,steps,m_max,seed,plan", [
+    ("hubbard2d_4x4_m500", 48, 5, 4, 30, 21, 0),       # truncating sweep across the middle
+    ("threeband_4x2_m2000", 40, 2, 3, 1000, 22, 0),    # m_max above every bond: nothing discarded
+    ("hubbard2d_4x4_m500", 48, 5, 4, 30, 23, 1),       # environments planned as the benchmark plans them
 ])
-def test_sweep_matches_oracle(name, m, first, steps, m_max, seed):
+def test_sweep_matches_oracle(name, m, first, steps, m_max, seed, plan):
     torch, lcc = need_gpu()
     spec, mps = C.make(name, m_max=m, seed=seed, center=first)
     e0 = C.lower_bound_shift(spec, 0.5)
@@ -52,6 +53,8 @@ def test_sweep_matches_oracle(name, m, first, steps, m_max, seed):
     say(f"[sweep] {name} M={m} first={first} steps={steps} m_max={m_max}: oracle")
     ref = _oracle_sweep(spec, mps, b0, e0, steps, m_max)
     ctx = lcc.Context(0)
+    if plan:  # column-major intermediate, channel-major phase 2, large tiles, short split-K parts
+        ctx.set_plan(8192.0, 1024, 1, 1)
     ham = ctx.create_hamiltonian(spec)
     sw = lcc.Sweep(ctx, ham, mps, first)
     env = sw.env()
