@@ -240,6 +240,21 @@ lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, 
  * it).  Synchronous; uses steps+2 device vectors of workspace. */
 lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual);
 
+/* Lowest eigenpair of H_eff, the local problem of a DMRG sweep (Implementation section: the
+ * DMRG energy functional, stationary at an eigenvector of the effective Hamiltonian; the
+ * eigensolver of the sweep that produces the zeroth-order state).  Lanczos cycles of `steps`
+ * Krylov vectors with full re-orthogonalisation in FP64, each cycle restarted from the Ritz
+ * vector of the previous one, until ||H_eff u - theta u|| <= tol * max(1, |theta|) or
+ * `max_restarts` cycles have run.
+ * x_dev: double*, length of the layout.  On entry the start vector (all zeros: a start
+ * vector drawn by a counter-based generator from `seed`); on return the unit Ritz vector u.
+ * theta = u^T H_eff u, residual = ||H_eff u - theta u||.  Returns LCC_NOT_CONVERGED (x_dev
+ * still holds the last Ritz vector) when the tolerance was not met, LCC_ERR_ARG for steps < 1,
+ * max_restarts < 1 or tol < 0, LCC_ERR_NAN for a non-finite start vector.  Synchronous; uses
+ * steps + 2 device vectors of workspace. */
+lcc_status lcc_lowest_eigenpair(lcc_env env, int32_t steps, int32_t max_restarts, double tol, uint64_t seed,
+                                double* x_dev, double* theta, double* residual);
+
 /* ---------------------------------------------------------------------------------------
  * Local LCC solve:  Q (H_eff - e0) Q x = Q b,  Q = 1 - v v^T (v unit norm) or Q = 1.
  * Conjugate gradients (Implementation section).  precision selects the operator of the
@@ -279,7 +294,7 @@ lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const do
  * Sweep (Implementation section: one local problem at a time, sweeping over the sites).
  * A left-to-right sweep of two-site blocks starting at `first_site`: right environments of
  * every bond are built once; after each local solve the two-site tensor is split by an SVD per
- * middle-bond sector (rocSOLVER), the m_max largest singular values over all sectors are kept
+ * middle-bond sector (a blocked one-sided Jacobi SVD on the device), the m_max largest singular values over all sectors are kept
  * (ties: sector (N, 2Sz) ascending, then index), the left factor becomes the new
  * left-canonical site tensor, the left environment is extended by it on the device, and
  * S V^T times the next site's right-canonical tensor becomes the initial guess of the next

@@ -107,34 +107,166 @@ class Environments:
         self.R = right_environments(mps, mpo, self.l + 2)
         self.W12 = two_site_w(mpo, self.l)
 
-    def apply(self, x: dict) -> dict:
-        """y = H_eff x with x, y as {(ia, s1, s2, ib): block}; loops in the canonical L, W, R order."""
+    def apply(self, x: dict, counter: dict | None = None) -> dict:
+        """y = H_eff x with x, y as {(ia, s1, s2, ib): block}, in the canonical order:
+        K1 T_w = L^w X, K2 Z_w2 = sum W12^{w,w2} T_w, K3 y += Z_w2 R^{w2 T}.
+
+        Only work that reaches an allowed y block is done: the Z blocks are the ones some R
+        block carries into y, and a T block is formed the first time a nonzero W12 entry asks
+        for it.  `counter`, if given, receives the multiply-add work as counter['k1'],
+        counter['k2'], counter['k3'] (2 per multiply-add)."""
+        cnt = counter if counter is not None else {}
+        for k in ("k1", "k2", "k3"):
+            cnt.setdefault(k, 0)
         y = {k: np.zeros_like(v) for k, v in x.items()}
+        # L^w by row sector: for a fixed channel the source sector follows from the row
+        lrow = {w: {iap: (ia, blk) for (iap, ia), blk in Lw.items()} for w, Lw in self.L.items()}
+        # y blocks by right sector, and the Z blocks each R^{w2} needs
+        y_by_right = {}
+        for (ia, s1, s2, ib) in y:
+            y_by_right.setdefault(ib, []).append((ia, s1, s2))
+        z_need = {}
+        for w2, Rw in self.R.items():
+            need = set()
+            for (ibp, ib) in Rw:
+                for (iap, s1p, s2p) in y_by_right.get(ibp, []):
+                    need.add((iap, s1p, s2p, ib))
+            z_need[w2] = sorted(need)
+        T = {}
+
+        def get_t(w, iap, s1, s2, ib):
+            key = (w, iap, s1, s2, ib)
+            if key not in T:
+                hit = lrow.get(w, {}).get(iap)
+                xb = None if hit is None else x.get((hit[0], s1, s2, ib))
+                if xb is None:
+                    T[key] = None
+                else:
+                    T[key] = hit[1] @ xb
+                    cnt["k1"] += 2 * hit[1].shape[0] * hit[1].shape[1] * xb.shape[1]
+            return T[key]
+
+        Z = {}
         for (w, w2), W12 in self.W12.items():
-            Lw = self.L.get(w)
-            Rw = self.R.get(w2)
-            if not Lw or not Rw:
+            if w not in self.L or w2 not in self.R:
                 continue
-            Lby = {}
-            for (iap, ia), blk in Lw.items():
-                Lby.setdefault(ia, []).append((iap, blk))
-            Rby = {}
-            for (ibp, ib), blk in Rw.items():
-                Rby.setdefault(ib, []).append((ibp, blk))
-            for (ia, s1, s2, ib), xb in x.items():
-                col = 4 * s1 + s2
-                rows = np.nonzero(W12[:, col])[0]
-                if rows.size == 0:
-                    continue
-                for iap, Lb in Lby.get(ia, []):
-                    LX = Lb @ xb
-                    for ibp, Rb in Rby.get(ib, []):
-                        T = LX @ Rb.T
-                        for r in rows:
-                            key = (iap, r // 4, r % 4, ibp)
-                            if key in y:
-                                y[key] += W12[r, col] * T
+            for (iap, s1p, s2p, ib) in z_need[w2]:
+                row = 4 * s1p + s2p
+                for col in np.nonzero(W12[row, :])[0]:
+                    t = get_t(w, iap, col // 4, col % 4, ib)
+                    if t is None:
+                        continue
+                    zk = (w2, iap, s1p, s2p, ib)
+                    if zk in Z:
+                        Z[zk] = Z[zk] + W12[row, col] * t
+                    else:
+                        Z[zk] = W12[row, col] * t
+                    cnt["k2"] += 2 * t.size
+        for (w2, iap, s1p, s2p, ib), z in Z.items():
+            for (ibp, ib2), Rb in self.R[w2].items():
+                key = (iap, s1p, s2p, ibp)
+                if ib2 == ib and key in y:
+                    y[key] += z @ Rb.T
+                    cnt["k3"] += 2 * z.shape[0] * z.shape[1] * Rb.shape[0]
         return y
+
+
+class MiddleBondEnvironments:
+    """H_eff x factorised over the middle MPO bond (transition-element figure, cut between the
+    two sites): H_eff = sum_{w1} Lt^{w1} (x) Rt^{w1} with
+        Lt^{w1}[(a',s1'),(a,s1)] = sum_w  W_l^{w,w1}[s1',s1] L^w[a',a]
+        Rt^{w1}[(s2',b'),(s2,b)] = sum_w2 W_{l+1}^{w1,w2}[s2',s2] R^{w2}[b',b].
+    The two-site vector is one matrix X_q per middle-bond sector q (rows (a, s1), columns
+    (s2, b)), so that y is Y_{q'} = sum_{w1} Lt^{w1} X_q Rt^{w1 T} with q' = q + dq(w1)."""
+
+    def __init__(self, spec: dict, mps: dict, mpo: dict):
+        from .flops import middle_sectors
+        self.mps = mps
+        l = self.l = mps["center"]
+        self.bl, self.br = mps["bonds"][l], mps["bonds"][l + 2]
+        self.dq = mpo["dq"][l + 1]
+        L = left_environments(mps, mpo, l)
+        R = right_environments(mps, mpo, l + 2)
+        self.secs = middle_sectors(mps)
+        self.row_at, self.col_at = {}, {}
+        for i, S in enumerate(self.secs):
+            off = 0
+            for (a, s1) in S["rows"]:
+                self.row_at[(a, s1)] = (i, off)
+                off += self.bl[a][2]
+            off = 0
+            for (s2, b) in S["cols"]:
+                self.col_at[(s2, b)] = (i, off)
+                off += self.br[b][2]
+        self.lt, self.rt = {}, {}
+        for (w, w1), m in mpo["W"][l].items():
+            for (ap, a), blk in L.get(w, {}).items():
+                for sp in range(4):
+                    for s in range(4):
+                        if m[sp, s] != 0.0 and (ap, sp) in self.row_at and (a, s) in self.row_at:
+                            key = ((ap, sp), (a, s))
+                            d = self.lt.setdefault(w1, {})
+                            d[key] = d.get(key, 0.0) + m[sp, s] * blk
+        for (w1, w2), m in mpo["W"][l + 1].items():
+            for (bp, b), blk in R.get(w2, {}).items():
+                for sp in range(4):
+                    for s in range(4):
+                        if m[sp, s] != 0.0 and (sp, bp) in self.col_at and (s, b) in self.col_at:
+                            key = ((sp, bp), (s, b))
+                            d = self.rt.setdefault(w1, {})
+                            d[key] = d.get(key, 0.0) + m[sp, s] * blk
+
+    def to_sectors(self, x: dict) -> list:
+        out = [np.zeros((S["nrows"], S["ncols"])) for S in self.secs]
+        for (a, s1, s2, b), blk in x.items():
+            i, r0 = self.row_at[(a, s1)]
+            j, c0 = self.col_at[(s2, b)]
+            assert i == j
+            out[i][r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]] = blk
+        return out
+
+    def from_sectors(self, ys: list, template: dict) -> dict:
+        out = {}
+        for (a, s1, s2, b), blk in template.items():
+            i, r0 = self.row_at[(a, s1)]
+            _, c0 = self.col_at[(s2, b)]
+            out[(a, s1, s2, b)] = ys[i][r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]].copy()
+        return out
+
+    def apply(self, x: dict, counter: dict | None = None) -> dict:
+        """y = H_eff x.  T_{w1,q} = Lt^{w1} X_q is formed only where Lt^{w1} and Rt^{w1} both
+        read sector q and q + dq(w1) is a sector; `counter` receives the multiply-add work as
+        counter['phase1'] and counter['phase2']."""
+        cnt = counter if counter is not None else {}
+        cnt.setdefault("phase1", 0)
+        cnt.setdefault("phase2", 0)
+        X = self.to_sectors(x)
+        Y = [np.zeros_like(m) for m in X]
+        index = {S["q"]: i for i, S in enumerate(self.secs)}
+        for w1 in sorted(set(self.lt) & set(self.rt)):
+            src_l = {self.row_at[src][0] for (_, src) in self.lt[w1]}
+            src_r = {self.col_at[src][0] for (_, src) in self.rt[w1]}
+            for m in sorted(src_l & src_r):
+                q = self.secs[m]["q"]
+                mp = index.get((q[0] + self.dq[w1][0], q[1] + self.dq[w1][1]))
+                if mp is None:
+                    continue
+                T = np.zeros((self.secs[mp]["nrows"], self.secs[m]["ncols"]))
+                for (tgt, src), blk in self.lt[w1].items():
+                    i, r0 = self.row_at[src]
+                    if i != m:
+                        continue
+                    _, t0 = self.row_at[tgt]
+                    T[t0:t0 + blk.shape[0], :] += blk @ X[m][r0:r0 + blk.shape[1], :]
+                    cnt["phase1"] += 2 * blk.shape[0] * blk.shape[1] * X[m].shape[1]
+                for (tgt, src), blk in self.rt[w1].items():
+                    j, c0 = self.col_at[src]
+                    if j != m:
+                        continue
+                    _, d0 = self.col_at[tgt]
+                    Y[mp][:, d0:d0 + blk.shape[0]] += T[:, c0:c0 + blk.shape[1]] @ blk.T
+                    cnt["phase2"] += 2 * T.shape[0] * blk.shape[1] * blk.shape[0]
+        return self.from_sectors(Y, x)
 
 
 def check_left_canonical(mps: dict, tol: float = 1e-12) -> float:
@@ -185,6 +317,6 @@ def two_site_template(mps: dict, blocks: list) -> dict:
     return {k: np.zeros((bl[k[0]][2], br[k[3]][2])) for k in blocks}
 
 
-__all__ = ["Environments", "left_environments", "right_environments", "two_site_w",
+__all__ = ["Environments", "MiddleBondEnvironments", "left_environments", "right_environments", "two_site_w",
            "check_left_canonical", "check_right_canonical", "flatten", "unflatten", "dot",
            "two_site_template", "LOCAL_QN"]

@@ -115,3 +115,24 @@ def local_solve(spec: dict, mps: dict, mpo: dict, b: dict, e0: float, tol: float
     bf = BS.flatten(bfull, blocks)
     x, it, rel, _ = OS.cg(A, bf, tol=tol, max_iter=5000)
     return BS.unflatten(x, tmpl, blocks), OS.hylleraas(A, x, bf), it
+
+
+def local_ground_state(spec: dict, mps: dict, mpo: dict):
+    """Lowest eigenpair (theta, u as a block dict) of H_eff at the block mps['center'].
+
+    The DMRG energy functional of the Implementation section is stationary where H_eff u =
+    theta u; the local step of a ground-state sweep takes the lowest such pair.  H_eff is formed
+    densely here, column by column from oracle.blocksparse, and diagonalised with numpy (small
+    blocks only)."""
+    env = BS.Environments(spec, mps, mpo)
+    from workloads import mps as M  # block enumeration of the generator (inputs only)
+    blocks = M.two_site_blocks(mps)
+    tmpl = BS.two_site_template(mps, blocks)
+    n = sum(v.size for v in tmpl.values())
+    heff = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        heff[:, c] = BS.flatten(env.apply(BS.unflatten(e, tmpl, blocks)), blocks)
+    w, U = np.linalg.eigh(0.5 * (heff + heff.T))
+    return float(w[0]), BS.unflatten(U[:, 0], tmpl, blocks), float(w[1] - w[0]) if n > 1 else np.inf

@@ -329,6 +329,17 @@ lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, doub
   });
 }
 
+lcc_status lcc_lowest_eigenpair(lcc_env env, int32_t steps, int32_t max_restarts, double tol, uint64_t seed,
+                                double* x, double* theta, double* residual) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!theta || !residual || !x) throw Error{LCC_ERR_ARG, "NULL argument"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    return lowest_eigenpair(*env->e, steps, max_restarts, tol, seed, x, theta, residual) ? LCC_OK : LCC_NOT_CONVERGED;
+  });
+}
+
 lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const double* b, double e0, const double* v,
                                double* x, lcc_solve_info* info) {
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");

@@ -160,7 +160,7 @@ hipError_t launch_dot_f64(const double* x, const double* y, int64_t n, double* p
                           double* out, hipStream_t stream);
 hipError_t launch_dot_f32(const float* x, const float* y, int64_t n, double* partial,
                           double* out, hipStream_t stream);
-// y = a*x + b*y with FP64 scalars (a, b given by value)
+// y = a*x + b*y with FP64 scalars (a, b given by value); an operand whose coefficient is 0 is not read
 hipError_t launch_axpby_f64(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
 hipError_t launch_axpby_f32(int64_t n, double a, const float* x, double b, float* y, hipStream_t s);
 // z = x (convert)

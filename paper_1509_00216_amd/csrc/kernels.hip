@@ -1102,10 +1102,15 @@ static inline dim3 grid_for(int64_t n) {
   return dim3((unsigned)b);
 }
 
+// A coefficient that is exactly zero drops its operand unread: a fresh output buffer (whose
+// contents may be anything, NaN included) can be written with b = 0.
 template <class T>
 __global__ void axpby_kernel(int64_t n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double ax = a == 0.0 ? 0.0 : a * (double)x[i];
+    const double by = b == 0.0 ? 0.0 : b * (double)y[i];
+    y[i] = (T)(ax + by);
+  }
 }
 hipError_t launch_axpby_f64(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
   hipLaunchKernelGGL(axpby_kernel<double>, grid_for(n), dim3(kThreads), 0, s, n, a, x, b, y);

@@ -59,61 +59,92 @@ void jacobi_eigen(std::vector<double> a, int k, std::vector<double>& w, std::vec
 
 }  // namespace
 
-void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual) {
+// Lanczos cycles with full re-orthogonalisation, each restarted from the Ritz vector of the
+// previous one.  Returns true when ||H u - theta u|| <= tol max(1, |theta|).
+bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_t seed, double* x_io, double* theta,
+                      double* residual) {
   hipStream_t st = env.ctx->stream;
   const int64_t n = env.n_elements;
   if (steps < 1) throw Error{LCC_ERR_ARG, "steps must be >= 1"};
+  if (max_restarts < 1) throw Error{LCC_ERR_ARG, "max_restarts must be >= 1"};
+  if (!(tol >= 0.0)) throw Error{LCC_ERR_ARG, "tol must be >= 0"};
   steps = (int)std::min<int64_t>(steps, n);
   DevBuf Qbuf, wbuf;
   Qbuf.alloc(sizeof(double) * (size_t)n * (steps + 1));
   wbuf.alloc(sizeof(double) * (size_t)n);
   double* Q = Qbuf.as<double>();
   double* w = wbuf.as<double>();
-  check_hip(launch_random_fill_f64(Q, n, seed, st), "start vector");
-  double nrm = std::sqrt(dot(env, Q, Q));
+  double nrm = 0.0;
+  if (x_io) {
+    check_hip(hipMemcpyAsync(Q, x_io, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "start vector");
+    nrm = std::sqrt(dot(env, Q, Q));
+    if (!std::isfinite(nrm)) throw Error{LCC_ERR_NAN, "non-finite start vector"};
+  }
+  if (nrm == 0.0) {
+    check_hip(launch_random_fill_f64(Q, n, seed, st), "start vector");
+    nrm = std::sqrt(dot(env, Q, Q));
+  }
   check_hip(launch_axpby_f64(n, 0.0, Q, 1.0 / nrm, Q, st), "normalise");
-  std::vector<double> alpha, beta;
-  int k = 0;
-  for (; k < steps; ++k) {
-    double* qk = Q + (size_t)k * n;
-    apply_heff(env, LCC_FP64, qk, w);
-    const double a = dot(env, qk, w);
-    alpha.push_back(a);
-    // full re-orthogonalisation (twice) against every Krylov vector so far
-    for (int pass = 0; pass < 2; ++pass)
-      for (int i = 0; i <= k; ++i) {
-        const double* qi = Q + (size_t)i * n;
-        const double c = dot(env, qi, w);
-        check_hip(launch_axpby_f64(n, -c, qi, 1.0, w, st), "reorth");
+  bool converged = false;
+  for (int cycle = 0; cycle < max_restarts; ++cycle) {
+    std::vector<double> alpha, beta;
+    int k = 0;
+    for (; k < steps; ++k) {
+      double* qk = Q + (size_t)k * n;
+      apply_heff(env, LCC_FP64, qk, w);
+      const double a = dot(env, qk, w);
+      if (!std::isfinite(a)) throw Error{LCC_ERR_NAN, "non-finite Rayleigh quotient"};
+      alpha.push_back(a);
+      // full re-orthogonalisation (twice) against every Krylov vector so far
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i <= k; ++i) {
+          const double* qi = Q + (size_t)i * n;
+          const double c = dot(env, qi, w);
+          check_hip(launch_axpby_f64(n, -c, qi, 1.0, w, st), "reorth");
+        }
+      const double b = std::sqrt(dot(env, w, w));
+      if (k + 1 == steps || b < 1e-12 * std::max(1.0, std::fabs(a))) {
+        ++k;
+        break;
       }
-    const double b = std::sqrt(dot(env, w, w));
-    if (k + 1 == steps || b < 1e-12 * std::max(1.0, std::fabs(a))) {
-      ++k;
-      break;
+      beta.push_back(b);
+      // the next basis vector is written without reading its (uninitialised) slot
+      check_hip(launch_axpby_f64(n, 1.0 / b, w, 0.0, Q + (size_t)(k + 1) * n, st), "next vector");
     }
-    beta.push_back(b);
-    check_hip(launch_axpby_f64(n, 1.0 / b, w, 0.0, Q + (size_t)(k + 1) * n, st), "next vector");
+    const int m = k;
+    std::vector<double> T((size_t)m * m, 0.0), ev, vec;
+    for (int i = 0; i < m; ++i) {
+      T[(size_t)i * m + i] = alpha[i];
+      if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
+    }
+    jacobi_eigen(T, m, ev, vec);
+    int lo = 0;
+    for (int i = 1; i < m; ++i)
+      if (ev[i] < ev[lo]) lo = i;
+    // Ritz vector u = Q s (normalised) and its residual; the basis is free afterwards
+    check_hip(launch_fill_f64(w, n, 0.0, st), "zero");
+    for (int i = 0; i < m; ++i)
+      check_hip(launch_axpby_f64(n, vec[(size_t)i * m + lo], Q + (size_t)i * n, 1.0, w, st), "ritz");
+    const double un = std::sqrt(dot(env, w, w));
+    check_hip(launch_axpby_f64(n, 0.0, w, 1.0 / un, w, st), "normalise ritz");
+    double* hu = Q + (size_t)n;  // slot 1 (steps + 1 >= 2 slots)
+    apply_heff(env, LCC_FP64, w, hu);
+    const double th = dot(env, w, hu);
+    check_hip(launch_axpby_f64(n, -th, w, 1.0, hu, st), "residual");
+    const double res = std::sqrt(dot(env, hu, hu));
+    *theta = th;
+    *residual = res;
+    converged = res <= tol * std::max(1.0, std::fabs(th));
+    check_hip(hipMemcpyAsync(Q, w, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "restart vector");
+    if (converged) break;
   }
-  const int m = k;
-  std::vector<double> T((size_t)m * m, 0.0), ev, vec;
-  for (int i = 0; i < m; ++i) {
-    T[(size_t)i * m + i] = alpha[i];
-    if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
-  }
-  jacobi_eigen(T, m, ev, vec);
-  int lo = 0;
-  for (int i = 1; i < m; ++i)
-    if (ev[i] < ev[lo]) lo = i;
-  // Ritz vector u = Q s and its residual
-  check_hip(launch_fill_f64(w, n, 0.0, st), "zero");
-  for (int i = 0; i < m; ++i) check_hip(launch_axpby_f64(n, vec[(size_t)i * m + lo], Q + (size_t)i * n, 1.0, w, st), "ritz");
-  double* u = w;
-  double* hu = Q;  // the Krylov basis is no longer needed
-  apply_heff(env, LCC_FP64, u, hu);
-  check_hip(launch_axpby_f64(n, -ev[lo], u, 1.0, hu, st), "residual");
-  const double un = std::sqrt(dot(env, u, u));
-  *theta = ev[lo];
-  *residual = std::sqrt(dot(env, hu, hu)) / un;
+  if (x_io) check_hip(hipMemcpyAsync(x_io, w, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "ritz out");
+  check_hip(hipStreamSynchronize(st), "lanczos");
+  return converged;
+}
+
+void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual) {
+  (void)lowest_eigenpair(env, steps, 1, 0.0, seed, nullptr, theta, residual);
 }
 
 namespace {

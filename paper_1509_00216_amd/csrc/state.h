@@ -243,6 +243,8 @@ void apply_heff_each(Env& env, int precision, const void* x, void* y,
                      void (*after_each)(void*, const LaunchRef&), void* user);
 // lanczos.cpp
 void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual);
+bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_t seed, double* x_io, double* theta,
+                      double* residual);
 void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2);
 std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const void* x, void* y, int reps);
 // batch.hip

@@ -28,7 +28,7 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
-           "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan"]
+           "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan", "lcc_lowest_eigenpair"]
 
 
 class LccError(RuntimeError):
@@ -128,6 +128,8 @@ def library() -> C.CDLL:
                                               C.POINTER(C.c_float)]),
         "lcc_lowest_eigenvalue": (C.c_int32, [P, C.c_int32, C.c_uint64, C.POINTER(C.c_double),
                                               C.POINTER(C.c_double)]),
+        "lcc_lowest_eigenpair": (C.c_int32, [P, C.c_int32, C.c_int32, C.c_double, C.c_uint64, P,
+                                             C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lcc_env_profile_launches": (C.c_int32, [P, C.c_int32, P, P, C.c_int32, C.POINTER(C.c_int32),
                                                  C.POINTER(LaunchProfile)]),
         "lcc_batch_create": (C.c_int32, [P, C.c_int32, C.POINTER(P), C.POINTER(P)]),
@@ -413,6 +415,15 @@ class Env:
                self.ctx.handle)
         return th.value, res.value
 
+    def lowest_eigenpair(self, x, steps: int = 40, max_restarts: int = 20, tol: float = 1e-10, seed: int = 1) -> dict:
+        """Lowest eigenpair of H_eff; x (FP64 device tensor) holds the start vector (zeros: random)
+        on entry and the unit Ritz vector on return."""
+        th, res = C.c_double(), C.c_double()
+        code = library().lcc_lowest_eigenpair(self.handle, steps, max_restarts, tol, seed,
+                                              _tensor_ptr(x, "fp64", self.n), C.byref(th), C.byref(res))
+        _check(code, self.ctx.handle, allow=(0, 1))
+        return {"status": STATUS[code], "theta": th.value, "residual": res.value}
+
     def solve_local_lcc(self, b, e0: float, x, v=None, precision: str = "fp64", tol: float = 1e-10,
                         max_iter: int = 1000, inner_tol: float = 0.0, max_outer: int = 20,
                         replace_every: int = 50) -> dict:
@@ -483,6 +494,28 @@ class Batch:
         if code < 0:
             _check(code, self.ctx.handle)
         return STATUS[code], [_info_dict(0, i) for i in infos]
+
+
+def solve_local_lcc_batched(envs: list, bs: list, e0s: list, xs: list, vs: list | None = None,
+                            precision: str = "fp32", tol: float = 1e-10, max_iter: int = 1000,
+                            inner_tol: float = 0.0, max_outer: int = 0):
+    """One-shot batched solve (lcc_solve_local_lcc_batched): creates a batch of `envs`, solves,
+    destroys it.  Returns (most severe status, per-problem info dicts)."""
+    n = len(envs)
+    opts = SolveOpts(PRECISIONS[precision], max_iter, tol, inner_tol, max_outer, 0)
+    P = C.c_void_p
+    earr = (P * n)(*[e.handle for e in envs])
+    barr = (P * n)(*[_tensor_ptr(b, "fp64", e.n) for b, e in zip(bs, envs)])
+    xarr = (P * n)(*[_tensor_ptr(x, "fp64", e.n) for x, e in zip(xs, envs)])
+    varr = None
+    if vs is not None:
+        varr = (P * n)(*[(_tensor_ptr(v, "fp64", e.n) if v is not None else None) for v, e in zip(vs, envs)])
+    e0 = (C.c_double * n)(*[float(v) for v in e0s])
+    infos = (SolveInfo * n)()
+    code = library().lcc_solve_local_lcc_batched(n, earr, C.byref(opts), barr, e0, varr, xarr, infos)
+    if code < 0:
+        _check(code, envs[0].ctx.handle)
+    return STATUS[code], [_info_dict(0, i) for i in infos]
 
 
 class Sweep:

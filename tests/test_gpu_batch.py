@@ -145,3 +145,28 @@ def test_batch_members_with_different_plans(problems):
     for (label, jstar), info in zip(exp, infos):
         say(f"  {label}: J {info['hylleraas']:.12f} vs {jstar:.12f}")
         assert abs(info["hylleraas"] - jstar) <= 1e-8, label
+
+
+def test_one_shot_batched_entry_point(problems):
+    """lcc_solve_local_lcc_batched (create, solve, destroy in one call) on three members,
+    against the oracle's J*."""
+    torch, lcc = need_gpu()
+    ctx, envs, refs = problems
+    sel = (1, 2, 4)
+    bs, xs, e0s, exp = [], [], [], []
+    for k, i in enumerate(sel):
+        label, spec, mps, e0, v = refs[i]
+        b, jstar, _, _, _ = _oracle_problem(spec, mps, e0, 500 + k)
+        bs.append(to_dev(torch, envs[i].pack(b), torch.float64))
+        xs.append(torch.zeros_like(bs[-1]))
+        e0s.append(e0)
+        exp.append((label, jstar))
+    status, infos = lcc.solve_local_lcc_batched([envs[i] for i in sel], bs, e0s, xs, precision="fp32", tol=1e-10,
+                                                max_iter=4000, inner_tol=1e-4)
+    assert status == "LCC_OK", (status, infos)
+    for (label, jstar), info in zip(exp, infos):
+        say(f"  one-shot {label}: J {info['hylleraas']:.12f} vs {jstar:.12f}")
+        assert abs(info["hylleraas"] - jstar) <= 1e-8, label
+    # a repeated environment is refused
+    with pytest.raises(lcc.LccError):
+        lcc.solve_local_lcc_batched([envs[1], envs[1]], bs[:1] * 2, e0s[:1] * 2, [torch.zeros_like(bs[0]) for _ in range(2)])

@@ -1,6 +1,6 @@
 """GPU parity of H_eff x (the HIP path through the C ABI) against the CPU oracle.
 
-Bars: FP64 relative L2 <= 1e-12; raw FP32 <= 1e-5; raw BF16x3 <= 1e-3 (reported).
+Bars: FP64 relative L2 <= 1e-12; raw FP32 <= 1e-5; raw BF16x3 <= 1e-4 (operands split to about 2^-16 relative, FP32 accumulation).
 Cases span several tiles and ragged tails (sector dims 1..300), every Hamiltonian family,
 the complete-basis chain against exact diagonalisation (O1), and the full-size workloads
 either element by element against O2 or, where the oracle cannot hold the environments
@@ -61,7 +61,7 @@ def test_chain8_complete_basis_vs_ed(ctx):
     assert env.n == 4900
     assert err["fp64"] <= 1e-12
     assert err["fp32"] <= 1e-5
-    assert err["bf16x3"] <= 1e-3
+    assert err["bf16x3"] <= 1e-4
 
 
 @pytest.mark.parametrize("label,make,m,seed", [
@@ -77,7 +77,7 @@ def test_small_systems_vs_fock(ctx, label, make, m, seed):
     say(f"  errors {err}")
     assert err["fp64"] <= 1e-12
     assert err["fp32"] <= 1e-5
-    assert err["bf16x3"] <= 1e-3
+    assert err["bf16x3"] <= 1e-4
 
 
 @pytest.mark.parametrize("plan", ["default", "benchmarked"])
@@ -97,7 +97,7 @@ def test_every_block_position_vs_fock(plan):
         say(f"  n={env.n} errors {err}")
         assert err["fp64"] <= 1e-12, center
         assert err["fp32"] <= 1e-5, center
-        assert err["bf16x3"] <= 1e-3, center
+        assert err["bf16x3"] <= 1e-4, center
 
 
 def _case_o2(ctx, spec, mps, label, precisions=("fp64", "fp32", "bf16x3")):
@@ -128,7 +128,7 @@ def test_lattice_workloads_vs_blocksparse(ctx, name, m):
     say(f"  n={env.n} D={env.mpo_bond_dim} errors {err}")
     assert err["fp64"] <= 1e-12
     assert err["fp32"] <= 1e-5
-    assert err["bf16x3"] <= 1e-3
+    assert err["bf16x3"] <= 1e-4
 
 
 def test_abinitio_k10_vs_blocksparse(ctx):
@@ -173,7 +173,7 @@ def test_abinitio_full_size_hermitian_and_bounded(ctx):
     axbf = _apply(torch, env, x, "bf16x3")
     say(f"  fp32 vs fp64 {rel(ax32, ax):.3e}  bf16x3 vs fp64 {rel(axbf, ax):.3e}")
     assert rel(ax32, ax) <= 1e-5
-    assert rel(axbf, ax) <= 1e-3
+    assert rel(axbf, ax) <= 1e-4
     # determinism: a second FP64 application is bitwise identical
     ax2 = _apply(torch, env, x, "fp64")
     assert np.array_equal(ax, ax2)

@@ -193,3 +193,15 @@ def test_cg_detects_indefinite():
     A = OS.make_operator(lambda z: heff @ z, 0.0)
     with pytest.raises(ArithmeticError):
         OS.cg(A, np.array([1.0, 0.0, 0.0]))
+
+
+def test_lanczos_lowest_is_the_lowest_eigenvalue(chain8):
+    # two-sided: the Ritz value equals lambda_min of the dense matrix (not merely >= it), and
+    # the reported residual is the true ||H u - theta u|| of the returned unit vector
+    spec, mps, blocks, heff = chain8
+    w = np.linalg.eigvalsh(heff)
+    th, res, u = OS.lanczos_lowest(lambda z: heff @ z, heff.shape[0], steps=100, seed=2)
+    assert abs(th - w[0]) <= 1e-10
+    assert abs(np.linalg.norm(u) - 1.0) <= 1e-12
+    assert abs(np.linalg.norm(heff @ u - th * u) - res) <= 1e-12
+    assert res <= 1e-8
