@@ -18,6 +18,8 @@ against the Fock-space Hamiltonian in the tests.
 """
 from __future__ import annotations
 
+import bisect
+
 import numpy as np
 
 from . import fock
@@ -148,3 +150,123 @@ def dense_operator(mpo: dict) -> np.ndarray:
                 nxt[b] = nxt.get(b, 0.0) + np.kron(partial[a], m)
         partial = nxt
     return partial[0]
+
+
+def build_mpo_twosided(spec: dict, switch: int | None = None) -> dict:
+    """An exact MPO whose bond dimension stays O(k^2) for two-body terms (MPO equation; the
+    Implementation section bounds it by k^2 with spin adaptation, this one uses spin orbitals).
+
+    Each operator string is sorted by site with the sign of the permutation, as in build_mpo.
+    At bond j it splits into the operators left of j (nL of them) and right of j (nR).  The
+    channel that carries it is labelled by whichever side is shorter:
+        nL = 0: 'I'        nR = 0: 'H'
+        nL < nR: ('L', left operators)    the coefficient has not been applied yet
+        nL > nR: ('R', right operators)   the coefficient has been applied
+        nL = nR = 1: ('R', right operator)
+        nL = nR = 2: ('L', ...) on bonds j < switch, ('R', ...) on bonds j >= switch
+    so no label holds more than two operators.  The coefficient enters on the one transition
+    from an 'I' / 'L' channel into an 'R' / 'H' channel; every other transition is fixed by the
+    labels.  On a site where a string has no operator its channel passes through with the
+    local parity F^(number of its operators on the far side), the Jordan-Wigner string.
+    `switch` defaults to k // 2.  Same output format as build_mpo.
+    """
+    K = spec["n_orb"]
+    sw = K // 2 if switch is None else switch
+
+    def label(ops, j):
+        nl = bisect.bisect_left(ops, (j,))  # operators on sites < j (ops are sorted by site)
+        nr = len(ops) - nl
+        if nl == 0:
+            return "I"
+        if nr == 0:
+            return "H"
+        if nl < nr or (nl == nr == 2 and j < sw):
+            return ("L",) + tuple(ops[:nl])
+        return ("R",) + tuple(ops[nl:])
+
+    def applies_coefficient(a, b):
+        return (a == "I" or a[0] == "L") and (b == "H" or b[0] == "R")
+
+    coef_entries = [dict() for _ in range(K)]
+    fixed = [dict() for _ in range(K)]
+    first, last = {}, {}
+
+    def seen(lab, b0, b1):
+        first[lab] = min(first.get(lab, b0), b0)
+        last[lab] = max(last.get(lab, b1), b1)
+
+    # identical site-sorted strings (e.g. the (ij|kl) and (kl|ij) images) are merged first
+    merged = {}
+    for coef, ops in _site_strings(spec):
+        key = tuple(ops)
+        merged[key] = merged.get(key, 0.0) + coef
+    for ops, coef in merged.items():
+        if coef == 0.0:
+            continue
+        sites = sorted({o[0] for o in ops})
+        local = {}
+        for t in sites:
+            m = ID.copy()
+            for _, spin, dag in (o for o in ops if o[0] == t):
+                m = m @ local_op(spin, dag)
+            local[t] = m
+        if any(not np.any(m) for m in local.values()):
+            continue  # e.g. a+_p a+_p: the zero operator
+        events = sorted(set(sites) | ({sw - 1} if 0 <= sw - 1 < K else set()))
+        # bond ranges of the string's labels: constant between consecutive events
+        b0 = 0
+        for e in events:
+            seen(label(ops, b0), b0, e)
+            b0 = e + 1
+        seen(label(ops, b0), b0, K)
+        for j in events:
+            a, b = label(ops, j), label(ops, j + 1)
+            if j not in local and a == b:
+                continue  # plain pass-through, added per channel below
+            m = local.get(j, ID)
+            if (len(ops) - bisect.bisect_left(ops, (j + 1,))) % 2 == 1:  # operators right of site j
+                m = m @ F
+            if applies_coefficient(a, b):
+                coef_entries[j][(a, b)] = coef_entries[j].get((a, b), 0.0) + coef * m
+            else:
+                old = fixed[j].get((a, b))
+                assert old is None or np.array_equal(old, m), "inconsistent label transition"
+                fixed[j][(a, b)] = m
+    if spec.get("e_const", 0.0) != 0.0:
+        coef_entries[0][("I", "H")] = coef_entries[0].get(("I", "H"), 0.0) + spec["e_const"] * ID
+        seen("I", 0, 0)
+        seen("H", 1, K)
+    # pass-through of every channel inside its range of bonds
+    for lab in first:
+        par = F if (lab not in ("I", "H") and (len(lab) - 1) % 2 == 1) else ID
+        for j in range(first[lab], last[lab]):
+            old = fixed[j].get((lab, lab))
+            assert old is None or np.array_equal(old, par), "inconsistent pass-through"
+            fixed[j][(lab, lab)] = par
+
+    def order(lab):
+        if lab == "I":
+            return (0, ())
+        if lab == "H":
+            return (1, ())
+        return (2 if lab[0] == "L" else 3, (len(lab), lab[1:]))
+
+    chans = [sorted((lab for lab in first if first[lab] <= b <= last[lab]), key=order) for b in range(K + 1)]
+    assert chans[0] == ["I"] and chans[K] == ["H"], "boundary bonds must hold one channel"
+    index = [{lab: i for i, lab in enumerate(c)} for c in chans]
+
+    def shift(lab):
+        if lab in ("I", "H"):
+            return (0, 0)
+        dn, dz = _dq(lab[1:])
+        return (dn, dz) if lab[0] == "L" else (-dn, -dz)
+
+    W = []
+    for j in range(K):
+        d = {}
+        for src in (fixed[j], coef_entries[j]):
+            for (a, b), m in src.items():
+                key = (index[j][a], index[j + 1][b])
+                d[key] = d.get(key, 0.0) + m
+        W.append({k: m for k, m in d.items() if np.any(m)})
+    return {"channels": chans, "dq": [[shift(l) for l in c] for c in chans], "W": W, "n_sites": K}

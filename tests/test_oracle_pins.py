@@ -76,9 +76,13 @@ def test_orbital_rotation_invariance_pins_two_body_convention():
     lambda: H.rotate_orbitals(H.hubbard_chain(4, U=2.0, n_elec=3, two_sz=1), H.random_orthogonal(4, 3)),
     lambda: H.three_band(2, 1, n_holes=3, two_sz=1),
 ])
-def test_oracle_mpo_contracts_to_fock_hamiltonian(make):
+@pytest.mark.parametrize("builder", ["prefix", "twosided", "twosided_switch1", "twosided_switch3"])
+def test_oracle_mpo_contracts_to_fock_hamiltonian(make, builder):
     spec = make()
-    mpo = OM.build_mpo(spec)
+    if builder == "prefix":
+        mpo = OM.build_mpo(spec)
+    else:
+        mpo = OM.build_mpo_twosided(spec, {"twosided": None, "twosided_switch1": 1, "twosided_switch3": 3}[builder])
     D = OM.dense_operator(mpo)
     basis = fock.sector_basis(spec["n_orb"], spec["n_elec"], spec["two_sz"])
     ci = sector_to_config(basis, spec["n_orb"])
@@ -87,6 +91,14 @@ def test_oracle_mpo_contracts_to_fock_hamiltonian(make):
     # the MPO conserves N and Sz: no amplitude leaves the sector
     other = np.setdiff1d(np.arange(D.shape[0]), ci)
     assert np.abs(D[np.ix_(other, ci)]).max() < 1e-14
+    # channel shifts agree with the entries: <s'|W^{w,w'}|s> != 0 only if dq(w') = dq(w) + qn(s') - qn(s)
+    for j, Wj in enumerate(mpo["W"]):
+        for (a, b), m in Wj.items():
+            for sp in range(4):
+                for s in range(4):
+                    if m[sp, s] != 0.0:
+                        assert mpo["dq"][j + 1][b][0] == mpo["dq"][j][a][0] + OM.LOCAL_QN[sp][0] - OM.LOCAL_QN[s][0]
+                        assert mpo["dq"][j + 1][b][1] == mpo["dq"][j][a][1] + OM.LOCAL_QN[sp][1] - OM.LOCAL_QN[s][1]
 
 
 def test_generator_canonical_and_isometry():
