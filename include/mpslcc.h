@@ -240,6 +240,17 @@ lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, 
  * it).  Synchronous; uses steps+2 device vectors of workspace. */
 lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual);
 
+/* lcc_lowest_eigenvalue for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation (one
+ * Lanczos cycle, same start vector, same results) with the Krylov basis in a fixed 64 MiB
+ * device array of the library, one per GPU, held until the process ends; no hipMalloc or
+ * hipFree and no stream creation (every launch on the context stream).  Limits:
+ * 1 <= steps <= 128 and (steps + 2) * vector length * 8 bytes <= 64 MiB, else LCC_ERR_ARG.
+ * The array keeps the last call's contents (every vector is written before it is read); the
+ * library runs one such call at a time, as calls overlapping on one GPU would race on the
+ * array.  Synchronous. */
+lcc_status lcc_lowest_eigenvalue_noalloc(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual);
+
 /* Lowest eigenpair of H_eff, the local problem of a DMRG sweep (Implementation section: the
  * DMRG energy functional, stationary at an eigenvector of the effective Hamiltonian; the
  * eigensolver of the sweep that produces the zeroth-order state).  Lanczos cycles of `steps`

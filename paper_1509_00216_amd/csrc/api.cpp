@@ -64,6 +64,7 @@ lcc_status lcc_context_create(int32_t device, void* stream, lcc_context* out) {
       if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         throw Error{LCC_ERR_NODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950"};
       check_hip(hipSetDevice(device), "hipSetDevice");
+      scratch_register_current_device();
       c->c.stream = static_cast<hipStream_t>(stream);
       c->c.dot_partial.alloc(sizeof(double) * kDotBlocks);
       c->c.dot_out.alloc(sizeof(double) * 8);
@@ -325,6 +326,17 @@ lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, doub
     if (!theta || !residual) throw Error{LCC_ERR_ARG, "NULL output"};
     check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
     lowest_eigenvalue(*env->e, steps, seed, theta, residual);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_lowest_eigenvalue_noalloc(lcc_env env, int32_t steps, uint64_t seed, double* theta, double* residual) {
+  if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!theta || !residual) throw Error{LCC_ERR_ARG, "NULL output"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    lowest_eigenvalue_noalloc(*env->e, steps, seed, theta, residual);
     return LCC_OK;
   });
 }

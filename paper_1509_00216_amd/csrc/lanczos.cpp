@@ -19,9 +19,10 @@ double dot(Env& env, const double* a, const double* b) {
 }
 
 // Eigen-decomposition of a small symmetric matrix by cyclic Jacobi rotations (host, k <= a
-// few hundred): returns eigenvalues and eigenvectors (columns of v, row-major k x k).
-void jacobi_eigen(std::vector<double> a, int k, std::vector<double>& w, std::vector<double>& v) {
-  v.assign((size_t)k * k, 0.0);
+// few hundred), in place on caller storage: a (k x k, row-major) is destroyed, w receives the
+// eigenvalues and the columns of v (row-major k x k) the eigenvectors.
+void jacobi_eigen(double* a, int k, double* w, double* v) {
+  for (int i = 0; i < k * k; ++i) v[i] = 0.0;
   for (int i = 0; i < k; ++i) v[(size_t)i * k + i] = 1.0;
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0;
@@ -53,7 +54,6 @@ void jacobi_eigen(std::vector<double> a, int k, std::vector<double>& w, std::vec
         }
       }
   }
-  w.resize(k);
   for (int i = 0; i < k; ++i) w[i] = a[(size_t)i * k + i];
 }
 
@@ -61,19 +61,45 @@ void jacobi_eigen(std::vector<double> a, int k, std::vector<double>& w, std::vec
 
 // Lanczos cycles with full re-orthogonalisation, each restarted from the Ritz vector of the
 // previous one.  Returns true when ||H u - theta u|| <= tol max(1, |theta|).
+namespace {
+void no_callback(void*, const LaunchRef&) {}
+}  // namespace
+
+size_t lanczos_host_elems(int steps) {
+  const size_t k = (size_t)std::max(steps, 1);
+  return 2 * k * k + 3 * k;
+}
+
+int64_t lanczos_workspace_elems(const Env& env, int steps) {
+  const int64_t n = env.n_elements;
+  return n * (std::min<int64_t>(std::max(steps, 1), n) + 2);
+}
+
 bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_t seed, double* x_io, double* theta,
                       double* residual) {
+  if (steps < 1) throw Error{LCC_ERR_ARG, "steps must be >= 1"};
+  DevBuf ws;
+  ws.alloc(sizeof(double) * (size_t)lanczos_workspace_elems(env, steps));
+  std::vector<double> host(lanczos_host_elems(steps));
+  return lowest_eigenpair_in(env, steps, max_restarts, tol, seed, x_io, theta, residual, ws.as<double>(), host.data(),
+                             false);
+}
+
+bool lowest_eigenpair_in(Env& env, int steps, int max_restarts, double tol, uint64_t seed, double* x_io,
+                         double* theta, double* residual, double* workspace, double* host_ws, bool in_order) {
   hipStream_t st = env.ctx->stream;
   const int64_t n = env.n_elements;
   if (steps < 1) throw Error{LCC_ERR_ARG, "steps must be >= 1"};
   if (max_restarts < 1) throw Error{LCC_ERR_ARG, "max_restarts must be >= 1"};
   if (!(tol >= 0.0)) throw Error{LCC_ERR_ARG, "tol must be >= 0"};
   steps = (int)std::min<int64_t>(steps, n);
-  DevBuf Qbuf, wbuf;
-  Qbuf.alloc(sizeof(double) * (size_t)n * (steps + 1));
-  wbuf.alloc(sizeof(double) * (size_t)n);
-  double* Q = Qbuf.as<double>();
-  double* w = wbuf.as<double>();
+  // workspace: steps + 1 Krylov vectors, then w
+  double* Q = workspace;
+  double* w = workspace + (size_t)n * (steps + 1);
+  auto apply = [&](const double* in, double* out) {
+    if (in_order) apply_heff_each(env, LCC_FP64, in, out, no_callback, nullptr);  // no side streams
+    else apply_heff(env, LCC_FP64, in, out);
+  };
   double nrm = 0.0;
   if (x_io) {
     check_hip(hipMemcpyAsync(Q, x_io, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "start vector");
@@ -85,16 +111,23 @@ bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_
     nrm = std::sqrt(dot(env, Q, Q));
   }
   check_hip(launch_axpby_f64(n, 0.0, Q, 1.0 / nrm, Q, st), "normalise");
+  // host storage (lanczos_host_elems(steps) doubles): alpha, beta, T (overwritten by its
+  // eigen-decomposition), eigenvalues, eigenvectors
+  const size_t S = (size_t)steps;
+  double* alpha = host_ws;
+  double* beta = alpha + S;
+  double* T = beta + S;
+  double* ev = T + S * S;
+  double* vec = ev + S;
   bool converged = false;
   for (int cycle = 0; cycle < max_restarts; ++cycle) {
-    std::vector<double> alpha, beta;
     int k = 0;
     for (; k < steps; ++k) {
       double* qk = Q + (size_t)k * n;
-      apply_heff(env, LCC_FP64, qk, w);
+      apply(qk, w);
       const double a = dot(env, qk, w);
       if (!std::isfinite(a)) throw Error{LCC_ERR_NAN, "non-finite Rayleigh quotient"};
-      alpha.push_back(a);
+      alpha[k] = a;
       // full re-orthogonalisation (twice) against every Krylov vector so far
       for (int pass = 0; pass < 2; ++pass)
         for (int i = 0; i <= k; ++i) {
@@ -107,12 +140,12 @@ bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_
         ++k;
         break;
       }
-      beta.push_back(b);
+      beta[k] = b;
       // the next basis vector is written without reading its (uninitialised) slot
       check_hip(launch_axpby_f64(n, 1.0 / b, w, 0.0, Q + (size_t)(k + 1) * n, st), "next vector");
     }
     const int m = k;
-    std::vector<double> T((size_t)m * m, 0.0), ev, vec;
+    for (int i = 0; i < m * m; ++i) T[i] = 0.0;
     for (int i = 0; i < m; ++i) {
       T[(size_t)i * m + i] = alpha[i];
       if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[i];
@@ -128,7 +161,7 @@ bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_
     const double un = std::sqrt(dot(env, w, w));
     check_hip(launch_axpby_f64(n, 0.0, w, 1.0 / un, w, st), "normalise ritz");
     double* hu = Q + (size_t)n;  // slot 1 (steps + 1 >= 2 slots)
-    apply_heff(env, LCC_FP64, w, hu);
+    apply(w, hu);
     const double th = dot(env, w, hu);
     check_hip(launch_axpby_f64(n, -th, w, 1.0, hu, st), "residual");
     const double res = std::sqrt(dot(env, hu, hu));

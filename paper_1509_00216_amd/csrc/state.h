@@ -245,6 +245,16 @@ void apply_heff_each(Env& env, int precision, const void* x, void* y,
 void lowest_eigenvalue(Env& env, int steps, uint64_t seed, double* theta, double* residual);
 bool lowest_eigenpair(Env& env, int steps, int max_restarts, double tol, uint64_t seed, double* x_io, double* theta,
                       double* residual);
+// the same on caller-given device workspace (lanczos_workspace_elems doubles) and host workspace
+// (lanczos_host_elems doubles); in_order issues every launch on the context stream (no side
+// streams are created)
+bool lowest_eigenpair_in(Env& env, int steps, int max_restarts, double tol, uint64_t seed, double* x_io,
+                         double* theta, double* residual, double* workspace, double* host_ws, bool in_order);
+int64_t lanczos_workspace_elems(const Env& env, int steps);
+size_t lanczos_host_elems(int steps);
+// noalloc.hip
+void scratch_register_current_device();
+void lowest_eigenvalue_noalloc(Env& env, int steps, uint64_t seed, double* theta, double* residual);
 void profile_apply(Env& env, int precision, const void* x, void* y, int reps, float* ms1, float* ms2);
 std::vector<lcc_launch_profile> profile_launches(Env& env, int precision, const void* x, void* y, int reps);
 // batch.hip

@@ -28,7 +28,8 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
-           "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan", "lcc_lowest_eigenpair"]
+           "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan", "lcc_lowest_eigenpair",
+           "lcc_lowest_eigenvalue_noalloc"]
 
 
 class LccError(RuntimeError):
@@ -128,6 +129,8 @@ def library() -> C.CDLL:
                                               C.POINTER(C.c_float)]),
         "lcc_lowest_eigenvalue": (C.c_int32, [P, C.c_int32, C.c_uint64, C.POINTER(C.c_double),
                                               C.POINTER(C.c_double)]),
+        "lcc_lowest_eigenvalue_noalloc": (C.c_int32, [P, C.c_int32, C.c_uint64, C.POINTER(C.c_double),
+                                                      C.POINTER(C.c_double)]),
         "lcc_lowest_eigenpair": (C.c_int32, [P, C.c_int32, C.c_int32, C.c_double, C.c_uint64, P,
                                              C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lcc_env_profile_launches": (C.c_int32, [P, C.c_int32, P, P, C.c_int32, C.POINTER(C.c_int32),
@@ -412,6 +415,13 @@ class Env:
     def lowest_eigenvalue(self, steps: int = 60, seed: int = 1):
         th, res = C.c_double(), C.c_double()
         _check(library().lcc_lowest_eigenvalue(self.handle, steps, seed, C.byref(th), C.byref(res)),
+               self.ctx.handle)
+        return th.value, res.value
+
+    def lowest_eigenvalue_noalloc(self, steps: int = 60, seed: int = 1):
+        """lcc_lowest_eigenvalue_noalloc: the Krylov basis in the library's fixed device array."""
+        th, res = C.c_double(), C.c_double()
+        _check(library().lcc_lowest_eigenvalue_noalloc(self.handle, steps, seed, C.byref(th), C.byref(res)),
                self.ctx.handle)
         return th.value, res.value
 
