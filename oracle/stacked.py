@@ -129,8 +129,9 @@ def right_environment(mps: dict, mpo: dict, fromsite: int) -> dict:
 
 
 def as_blocks(env: dict, dq: list, bond: list) -> dict:
-    """Stacked environment -> oracle.blocksparse's {w: {(row sector, column sector): block}}
-    (blocks that are identically zero because no term reaches them are left out)."""
+    """Stacked environment -> oracle.blocksparse's {w: {(row sector, column sector): block}}.
+    Every channel of a class gets a block on every sector pair of the class; where no term of
+    the channel reaches that pair the block is zero."""
     cls, _ = _classes(dq)
     idx = _sector_index(bond)
     out = {}
@@ -214,8 +215,12 @@ class FullSizeEnvironments:
             out[(a, s1, s2, b)] = ys[i][r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]].copy()
         return out
 
-    def apply_sectors(self, X: list, channels=None) -> list:
-        """Y = H_eff X on per-sector matrices (all middle channels, or the given subset)."""
+    def apply_sectors(self, X: list, channels=None, counter: dict | None = None) -> list:
+        """Y = H_eff X on per-sector matrices (all middle channels, or the given subset);
+        `counter`, if given, receives the multiply-add work done (2 per multiply-add) as
+        counter['flops']."""
+        cnt = counter if counter is not None else {}
+        cnt.setdefault("flops", 0)
         Y = [np.zeros_like(m) for m in X]
         index = {S["q"]: i for i, S in enumerate(self.secs)}
         chans = sorted(set(self.lt) & set(self.rt)) if channels is None else channels
@@ -235,12 +240,14 @@ class FullSizeEnvironments:
                         continue
                     _, t0 = self.row_at[tgt]
                     T[t0:t0 + blk.shape[0], :] += blk @ X[m][r0:r0 + blk.shape[1], :]
+                    cnt["flops"] += 2 * blk.shape[0] * blk.shape[1] * T.shape[1]
                 for (tgt, src), blk in rt.items():
                     j, c0 = self.col_at[src]
                     if j != m:
                         continue
                     _, d0 = self.col_at[tgt]
                     Y[mp][:, d0:d0 + blk.shape[0]] += T[:, c0:c0 + blk.shape[1]] @ blk.T
+                    cnt["flops"] += 2 * T.shape[0] * blk.shape[1] * blk.shape[0]
         return Y
 
     def apply(self, x: dict) -> dict:
