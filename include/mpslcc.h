@@ -151,6 +151,22 @@ lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lc
                                   int32_t site, lcc_env* out);
 void lcc_env_destroy(lcc_env env);
 
+/* Transition operator between two MPS (Implementation section: the transition element <Psi|H|Phi>,
+ * contracted site by site between different bra and ket, with the bra's two-site tensor at
+ * (site, site+1) removed -- its derivative with respect to that tensor).  Applied to the ket's
+ * own two-site tensor x0 (its tensors at site and site+1 contracted over their common bond, in the
+ * gauge of the ket's other tensors) it gives P^T H Phi, where P is the bra's two-site isometry
+ * and Phi the ket state: the right-hand side of the first-order equation (Theory section,
+ * -Q U Phi0 with U the perturbation) projected onto the local space of the first-order MPS, and,
+ * with H = 1 (an lcc_ham_desc with h = 0 and e_const = 1), the overlap vector P^T Phi0 of the
+ * local projector.  The bra must be left-canonical left of the block and right-canonical right of
+ * it (checked to 1e-10, LCC_ERR_ARG otherwise); the ket may be in any gauge and have other bond
+ * dimensions.  lcc_apply_heff maps a ket vector (lcc_env_input_layout) to a bra vector
+ * (lcc_env_layout); the local solve, the eigensolvers, the tuner and batches refuse such an
+ * environment (LCC_ERR_STATE).  Synchronous.  The environment keeps its own copies. */
+lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* bra,
+                                             const lcc_mps_desc* ket, int32_t site, lcc_env* out);
+
 /* Layout of two-site vectors x, y, b (the unknown tensor of the local problem).
  * Blocks are (left sector a of bond site, s1, s2, right sector b of bond site+2) with
  * qn(a) + qn(s1) + qn(s2) = qn(b).  Element (i, j) of a block sits at
@@ -160,12 +176,23 @@ typedef struct {
   int32_t n_blocks;
   int32_t n_sectors;    /* middle-bond sectors (the vector is block diagonal over them) */
   int32_t mpo_bond_dim; /* D of the middle MPO bond: the number of terms L~ (x) R~ */
-  int32_t reserved;
+  int32_t transition;   /* 1 for a transition operator between two MPS (lcc_build_transition_environments) */
   double flops_per_apply;  /* exact algorithmic flops of one H_eff x (see lcc_env_flops) */
 } lcc_layout_info;
 typedef struct { int32_t left, s1, s2, right; int64_t offset; int32_t ld, rows, cols; } lcc_block_entry;
 /* blocks may be NULL; otherwise it receives info->n_blocks entries. */
 lcc_status lcc_env_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* blocks);
+
+/* Layout of the input vectors of an environment: for lcc_build_environments the same as
+ * lcc_env_layout; for a transition operator the ket's two-site tensor (x of lcc_apply_heff),
+ * while lcc_env_layout describes the bra's (y). */
+lcc_status lcc_env_input_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* blocks);
+
+/* The ket's own two-site tensor at the block of a transition operator (its tensors at site and
+ * site+1 contracted over their common bond, on the device when the environment was built), in
+ * the input layout: applied to it, the operator gives P^T H Phi of the ket state Phi.  x_dev:
+ * double*, lcc_env_input_layout length.  LCC_ERR_STATE for an effective Hamiltonian.  Synchronous. */
+lcc_status lcc_env_ket_tensor(lcc_env env, double* x_dev);
 
 /* Flop counts of one H_eff x: 2*m*n*k summed over every block product the plan performs
  * (phase 1: enlarged left operator times x; phase 2: times enlarged right operator).
@@ -173,7 +200,8 @@ lcc_status lcc_env_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* b
 lcc_status lcc_env_flops(lcc_env env, double* phase1, double* phase2);
 
 /* y = H_eff x.  precision LCC_FP64: x, y are double*; LCC_FP32 / LCC_BF16X3: float*.
- * x and y must not overlap.  Asynchronous on the context stream. */
+ * x has the length of lcc_env_input_layout, y of lcc_env_layout (equal unless the environment is
+ * a transition operator).  x and y must not overlap.  Asynchronous on the context stream. */
 lcc_status lcc_apply_heff(lcc_env env, lcc_precision precision, const void* x_dev, void* y_dev);
 
 /* Time the two grouped-GEMM phases of lcc_apply_heff with HIP events on the context stream:

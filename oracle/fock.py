@@ -208,3 +208,34 @@ def ground_energy(spec: dict, k: int = 1) -> np.ndarray:
     import scipy.sparse.linalg as sla
     vals = sla.eigsh(H, k=k, which="SA", tol=1e-12)[0]
     return np.sort(vals)
+
+
+def config_index(basis: np.ndarray, n_sites: int) -> np.ndarray:
+    """Position of each sector state in the site-product ordering of left_basis (site 0 most
+    significant, local index n_up + 2 n_dn)."""
+    idx = np.zeros(basis.size, dtype=np.int64)
+    for j in range(n_sites):
+        idx = idx * 4 + ((basis >> (2 * j)) & 1) + 2 * ((basis >> (2 * j + 1)) & 1)
+    return idx
+
+
+def mps_state(mps: dict, basis: np.ndarray) -> np.ndarray:
+    """The state of an MPS (MPS equation: all site tensors contracted) as a vector over `basis`."""
+    K = mps["n_sites"]
+    full = left_basis(mps, K)[:, 0]
+    return full[config_index(basis, K)]
+
+
+def first_order_vectors(spec: dict, bra: dict, ket: dict, blocks: list):
+    """Local vectors of the first-order equation at the bra's two-site block (Theory section,
+    first-order equation; Implementation section, its local form): with P the bra's two-site
+    isometry and Phi0 the ket state,
+        u = P^T H Phi0,   v = P^T Phi0,   e1 = <Phi0|H|Phi0> / <Phi0|Phi0>,
+    so that P^T Q H Phi0 = u - e1 v for Q = 1 - |Phi0><Phi0| / <Phi0|Phi0>.  Columns of P in
+    `blocks` order, row-major inside a block."""
+    basis = sector_basis(spec["n_orb"], spec["n_elec"], spec["two_sz"])
+    H = hamiltonian_matrix(spec, basis)
+    phi0 = mps_state(ket, basis)
+    P = two_site_isometry(bra, basis, blocks)
+    hphi = H @ phi0
+    return P.T @ hphi, P.T @ phi0, float(phi0 @ hphi) / float(phi0 @ phi0)

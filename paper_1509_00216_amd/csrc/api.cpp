@@ -228,6 +228,20 @@ lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lc
   });
 }
 
+lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* bra,
+                                             const lcc_mps_desc* ket, int32_t site, lcc_env* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    if (!ham || !bra || !ket) throw Error{LCC_ERR_ARG, "NULL argument"};
+    std::unique_ptr<lcc_env_s> e(new lcc_env_s());
+    e->e = build_transition_env(&ctx->c, ham->h, *bra, *ket, site);
+    *out = e.release();
+    return LCC_OK;
+  });
+}
+
 void lcc_env_destroy(lcc_env env) {
   if (!env || !env->owned) return;
   if (env->e && env->e->ctx) {
@@ -244,10 +258,36 @@ lcc_status lcc_env_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* b
   info->n_blocks = (int32_t)e.layout.size();
   info->n_sectors = (int32_t)e.sectors.size();
   info->mpo_bond_dim = e.D_mid;
-  info->reserved = 0;
+  info->transition = e.transition ? 1 : 0;
   info->flops_per_apply = e.plan.flops1 + e.plan.flops2;
   if (blocks) std::memcpy(blocks, e.layout.data(), sizeof(lcc_block_entry) * e.layout.size());
   return LCC_OK;
+}
+
+lcc_status lcc_env_input_layout(lcc_env env, lcc_layout_info* info, lcc_block_entry* blocks) {
+  if (!env || !info) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  const Env& e = *env->e;
+  info->n_elements = e.n_in;
+  info->n_blocks = (int32_t)e.layout_in.size();
+  info->n_sectors = (int32_t)e.sectors_in.size();
+  info->mpo_bond_dim = e.D_mid;
+  info->transition = e.transition ? 1 : 0;
+  info->flops_per_apply = e.plan.flops1 + e.plan.flops2;
+  if (blocks) std::memcpy(blocks, e.layout_in.data(), sizeof(lcc_block_entry) * e.layout_in.size());
+  return LCC_OK;
+}
+
+lcc_status lcc_env_ket_tensor(lcc_env env, double* x) {
+  if (!env || !x) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    if (!env->e->transition) throw Error{LCC_ERR_STATE, "not a transition environment"};
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    hipStream_t st = env->e->ctx->stream;
+    check_hip(hipMemcpyAsync(x, env->e->x0.p, sizeof(double) * env->e->n_in, hipMemcpyDeviceToDevice, st), "copy");
+    check_hip(hipStreamSynchronize(st), "copy sync");
+    return LCC_OK;
+  });
 }
 
 lcc_status lcc_env_flops(lcc_env env, double* phase1, double* phase2) {
@@ -311,6 +351,7 @@ lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, 
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
   lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
   return guarded(ctx, [&]() -> lcc_status {
+    if (env->e->transition) throw Error{LCC_ERR_STATE, "a transition environment only supports apply"};
     if (precision != LCC_FP64 && precision != LCC_FP32 && precision != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
     if (reps < 1 || reps > 1000) throw Error{LCC_ERR_ARG, "reps must be in [1, 1000]"};
     check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
@@ -323,6 +364,7 @@ lcc_status lcc_lowest_eigenvalue(lcc_env env, int32_t steps, uint64_t seed, doub
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
   lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
   return guarded(ctx, [&]() -> lcc_status {
+    if (env->e->transition) throw Error{LCC_ERR_STATE, "a transition environment only supports apply"};
     if (!theta || !residual) throw Error{LCC_ERR_ARG, "NULL output"};
     check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
     lowest_eigenvalue(*env->e, steps, seed, theta, residual);
@@ -334,6 +376,7 @@ lcc_status lcc_lowest_eigenvalue_noalloc(lcc_env env, int32_t steps, uint64_t se
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
   lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
   return guarded(ctx, [&]() -> lcc_status {
+    if (env->e->transition) throw Error{LCC_ERR_STATE, "a transition environment only supports apply"};
     if (!theta || !residual) throw Error{LCC_ERR_ARG, "NULL output"};
     check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
     lowest_eigenvalue_noalloc(*env->e, steps, seed, theta, residual);
@@ -346,6 +389,7 @@ lcc_status lcc_lowest_eigenpair(lcc_env env, int32_t steps, int32_t max_restarts
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
   lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
   return guarded(ctx, [&]() -> lcc_status {
+    if (env->e->transition) throw Error{LCC_ERR_STATE, "a transition environment only supports apply"};
     if (!theta || !residual || !x) throw Error{LCC_ERR_ARG, "NULL argument"};
     check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
     return lowest_eigenpair(*env->e, steps, max_restarts, tol, seed, x, theta, residual) ? LCC_OK : LCC_NOT_CONVERGED;
@@ -357,6 +401,7 @@ lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const do
   if (!env) return fail(nullptr, LCC_ERR_ARG, "env is NULL");
   lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
   return guarded(ctx, [&]() -> lcc_status {
+    if (env->e->transition) throw Error{LCC_ERR_STATE, "a transition environment only supports apply"};
     if (!b || !x) throw Error{LCC_ERR_ARG, "b or x is NULL"};
     check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
     lcc_solve_opts o{};
@@ -374,6 +419,7 @@ lcc_status lcc_batch_create(lcc_context ctx, int32_t n, const lcc_env* envs, lcc
     std::vector<Env*> v;
     for (int i = 0; i < n; ++i) {
       if (!envs[i]) throw Error{LCC_ERR_ARG, "NULL environment"};
+      if (envs[i]->e->transition) throw Error{LCC_ERR_STATE, "a transition environment only supports apply"};
       v.push_back(envs[i]->e);
     }
     std::unique_ptr<lcc_batch_s> b(new lcc_batch_s());

@@ -301,15 +301,26 @@ void load_mps(const lcc_mps_desc& d, int N, int two_sz, hipStream_t s, DeviceMps
 // ---------------------------------------------------------------------------------------
 static inline double wcoef(const MpoEntry& e, int sp, int s) { return e.m[sp * 4 + s]; }
 
-// L_{j+1}^{w'}[a', a] = sum_{w,s',s} W_j^{w,w'}[s',s] (A^{s'T} L_j^w A^s)[a', a]
+// L_{j+1}^{w'}[a', a] = sum_{w,s',s} W_j^{w,w'}[s',s] (A'^{s'T} L_j^w A^s)[a', a], with A' the bra's
+// tensor (rows of L) and A the ket's (columns of L); the same MPS on both sides for H_eff.
 Environment left_step(const Environment& L, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st) {
-  const Bond& bj = mps.bonds[j];
-  const Bond& bn = mps.bonds[j + 1];
-  std::map<std::pair<int, int>, int> A;  // (left sector, s) -> block
-  for (size_t i = 0; i < mps.sites[j].size(); ++i) A[{mps.sites[j][i].l, mps.sites[j][i].s}] = (int)i;
+  return left_step(L, mps, mps, j, mpo, st);
+}
+
+Environment left_step(const Environment& L, const DeviceMps& bra, const DeviceMps& ket, int j, const Mpo& mpo,
+                      hipStream_t st) {
+  const Bond& bn = bra.bonds[j + 1];
+  const Bond& bn0 = ket.bonds[j + 1];
+  std::map<std::pair<int, int>, int> A, Ab;  // (left sector, s) -> block of the ket / the bra
+  for (size_t i = 0; i < ket.sites[j].size(); ++i) A[{ket.sites[j][i].l, ket.sites[j][i].s}] = (int)i;
+  for (size_t i = 0; i < bra.sites[j].size(); ++i) Ab[{bra.sites[j][i].l, bra.sites[j][i].s}] = (int)i;
   auto Ablk = [&](int l, int s) -> const SiteBlock* {
     auto it = A.find({l, s});
-    return it == A.end() ? nullptr : &mps.sites[j][it->second];
+    return it == A.end() ? nullptr : &ket.sites[j][it->second];
+  };
+  auto Abra = [&](int l, int s) -> const SiteBlock* {
+    auto it = Ab.find({l, s});
+    return it == Ab.end() ? nullptr : &bra.sites[j][it->second];
   };
   // enumerate sandwiches S(w, s', s, c) and their destinations
   struct SKey { int w, sp, s, c; bool operator<(const SKey& o) const { return std::tie(w, sp, s, c) < std::tie(o.w, o.sp, o.s, o.c); } };
@@ -328,7 +339,7 @@ Environment left_step(const Environment& L, const DeviceMps& mps, int j, const M
           const double c = wcoef(e, sp, s);
           if (c == 0.0) continue;
           const SiteBlock* as = Ablk(lb.c, s);
-          const SiteBlock* ap = Ablk(lb.r, sp);
+          const SiteBlock* ap = Abra(lb.r, sp);
           if (!as || !ap) continue;
           auto uk = std::make_tuple(lb.w, s, lb.c);
           if (!u_off.count(uk)) { u_off[uk] = u_total; u_total += (int64_t)lb.rows * as->cols; }
@@ -339,16 +350,16 @@ Environment left_step(const Environment& L, const DeviceMps& mps, int j, const M
     }
   }
   Environment out;
-  out.nsec = (int)bn.q.size();
+  out.nsec = (int)bn0.q.size();
   // output blocks in (w', a) order
   for (const auto& kv : dest) {
     EnvBlock b;
     b.w = std::get<0>(kv.first);
     b.c = std::get<1>(kv.first);
     b.r = std::get<2>(kv.first);
-    if (bn.q[b.r] != bn.q[b.c] + mpo.dq[j + 1][b.w]) throw Error{LCC_ERR_QN, "internal: environment charge mismatch"};
+    if (bn.q[b.r] != bn0.q[b.c] + mpo.dq[j + 1][b.w]) throw Error{LCC_ERR_QN, "internal: environment charge mismatch"};
     b.rows = bn.dim[b.r];
-    b.cols = bn.dim[b.c];
+    b.cols = bn0.dim[b.c];
     b.off = out.size;
     out.size += (int64_t)b.rows * b.cols;
     out.lookup[(int64_t)b.w * out.nsec + b.c] = (int)out.blocks.size();
@@ -368,27 +379,29 @@ Environment left_step(const Environment& L, const DeviceMps& mps, int j, const M
     g1.group(BASE_T, kv.second, as->cols, lb.rows, as->cols, false);
     g1.term(BASE_ENV, lb.off, lb.cols, BASE_MPS, as->off, as->cols, lb.cols, 1.0);
   }
-  // step 2: S(w, s', s, c) = A^{s'}[r -> a']^T U(w, s, c)
+  // step 2: S(w, s', s, c) = A'^{s'}[r -> a']^T U(w, s, c)
   GemmBuilder g2;
   for (const auto& kv : s_off) {
     const SKey& k = kv.first;
     const EnvBlock& lb = L.blocks[L.find(k.w, k.c)];
     const SiteBlock* as = Ablk(k.c, k.s);
-    const SiteBlock* ap = Ablk(lb.r, k.sp);
+    const SiteBlock* ap = Abra(lb.r, k.sp);
     g2.group(BASE_Y, kv.second, as->cols, ap->cols, as->cols, false);
     g2.term(BASE_MPS, ap->off, ap->cols, BASE_T, u_off[std::make_tuple(k.w, k.s, k.c)], as->cols, ap->rows, 1.0);
   }
   Bases<double> b{};
   b.p[BASE_ENV] = L.data.as<double>();
-  b.p[BASE_MPS] = mps.data.as<double>();
+  b.p[BASE_MPS] = ket.data.as<double>();
   b.p[BASE_T] = U.as<double>();
   b.p[BASE_Y] = S.as<double>();
   b.p[BASE_X] = out.data.as<double>();
   {
     auto l1 = finalize(g1, false, false, st);
     run_gemm64(l1, b, st);
+    Bases<double> b2 = b;
+    b2.p[BASE_MPS] = bra.data.as<double>();
     auto l2 = finalize(g2, true, false, st);
-    run_gemm64(l2, b, st);
+    run_gemm64(l2, b2, st);
     check_hip(hipStreamSynchronize(st), "left step gemm");
   }
   // step 3: mix
@@ -401,14 +414,26 @@ Environment left_step(const Environment& L, const DeviceMps& mps, int j, const M
   return out;
 }
 
-// R_j^{w}[b', b] = sum_{w',s',s} W_j^{w,w'}[s',s] (B^{s'} R_{j+1}^{w'} B^{s T})[b', b]
+// R_j^{w}[b', b] = sum_{w',s',s} W_j^{w,w'}[s',s] (B'^{s'} R_{j+1}^{w'} B^{s T})[b', b], with B' the
+// bra's tensor (rows of R) and B the ket's (columns of R).
 Environment right_step(const Environment& R, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st) {
-  const Bond& bj = mps.bonds[j];
-  std::map<std::pair<int, int>, int> B;  // (right sector, s) -> block
-  for (size_t i = 0; i < mps.sites[j].size(); ++i) B[{mps.sites[j][i].r, mps.sites[j][i].s}] = (int)i;
+  return right_step(R, mps, mps, j, mpo, st);
+}
+
+Environment right_step(const Environment& R, const DeviceMps& bra, const DeviceMps& ket, int j, const Mpo& mpo,
+                       hipStream_t st) {
+  const Bond& bj = bra.bonds[j];
+  const Bond& bj0 = ket.bonds[j];
+  std::map<std::pair<int, int>, int> B, Bb;  // (right sector, s) -> block of the ket / the bra
+  for (size_t i = 0; i < ket.sites[j].size(); ++i) B[{ket.sites[j][i].r, ket.sites[j][i].s}] = (int)i;
+  for (size_t i = 0; i < bra.sites[j].size(); ++i) Bb[{bra.sites[j][i].r, bra.sites[j][i].s}] = (int)i;
   auto Bblk = [&](int r, int s) -> const SiteBlock* {
     auto it = B.find({r, s});
-    return it == B.end() ? nullptr : &mps.sites[j][it->second];
+    return it == B.end() ? nullptr : &ket.sites[j][it->second];
+  };
+  auto Bbra = [&](int r, int s) -> const SiteBlock* {
+    auto it = Bb.find({r, s});
+    return it == Bb.end() ? nullptr : &bra.sites[j][it->second];
   };
   struct SKey { int w, sp, s, c; bool operator<(const SKey& o) const { return std::tie(w, sp, s, c) < std::tie(o.w, o.sp, o.s, o.c); } };
   std::map<SKey, int64_t> s_off;
@@ -425,7 +450,7 @@ Environment right_step(const Environment& R, const DeviceMps& mps, int j, const 
           const double c = wcoef(e, sp, s);
           if (c == 0.0) continue;
           const SiteBlock* bs = Bblk(rb.c, s);
-          const SiteBlock* bp = Bblk(rb.r, sp);
+          const SiteBlock* bp = Bbra(rb.r, sp);
           if (!bs || !bp) continue;
           auto uk = std::make_tuple(rb.w, s, rb.c);
           if (!u_off.count(uk)) { u_off[uk] = u_total; u_total += (int64_t)rb.rows * bs->rows; }
@@ -436,15 +461,15 @@ Environment right_step(const Environment& R, const DeviceMps& mps, int j, const 
     }
   }
   Environment out;
-  out.nsec = (int)bj.q.size();
+  out.nsec = (int)bj0.q.size();
   for (const auto& kv : dest) {
     EnvBlock b;
     b.w = std::get<0>(kv.first);
     b.c = std::get<1>(kv.first);
     b.r = std::get<2>(kv.first);
-    if (bj.q[b.r] != bj.q[b.c] + mpo.dq[j][b.w]) throw Error{LCC_ERR_QN, "internal: environment charge mismatch"};
+    if (bj.q[b.r] != bj0.q[b.c] + mpo.dq[j][b.w]) throw Error{LCC_ERR_QN, "internal: environment charge mismatch"};
     b.rows = bj.dim[b.r];
-    b.cols = bj.dim[b.c];
+    b.cols = bj0.dim[b.c];
     b.off = out.size;
     out.size += (int64_t)b.rows * b.cols;
     out.lookup[(int64_t)b.w * out.nsec + b.c] = (int)out.blocks.size();
@@ -470,21 +495,23 @@ Environment right_step(const Environment& R, const DeviceMps& mps, int j, const 
     const SKey& k = kv.first;
     const EnvBlock& rb = R.blocks[R.find(k.w, k.c)];
     const SiteBlock* bs = Bblk(k.c, k.s);
-    const SiteBlock* bp = Bblk(rb.r, k.sp);
+    const SiteBlock* bp = Bbra(rb.r, k.sp);
     g2.group(BASE_Y, kv.second, bs->rows, bp->rows, bs->rows, false);
     g2.term(BASE_MPS, bp->off, bp->cols, BASE_T, u_off[std::make_tuple(k.w, k.s, k.c)], bs->rows, bp->cols, 1.0);
   }
   Bases<double> b{};
   b.p[BASE_ENV] = R.data.as<double>();
-  b.p[BASE_MPS] = mps.data.as<double>();
+  b.p[BASE_MPS] = ket.data.as<double>();
   b.p[BASE_T] = U.as<double>();
   b.p[BASE_Y] = S.as<double>();
   b.p[BASE_X] = out.data.as<double>();
   {
     auto l1 = finalize(g1, false, true, st);
     run_gemm64(l1, b, st);
+    Bases<double> b2 = b;
+    b2.p[BASE_MPS] = bra.data.as<double>();
     auto l2 = finalize(g2, false, false, st);
-    run_gemm64(l2, b, st);
+    run_gemm64(l2, b2, st);
     check_hip(hipStreamSynchronize(st), "right step gemm");
   }
   MixBuilder mb;
@@ -555,6 +582,80 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
   return make_env(ctx, mpo, site, mps.bonds[site], mps.bonds[site + 2], L, R);
 }
 
+namespace {
+// The MPO of the identity operator: one channel on every bond, the identity on every site.
+Mpo identity_mpo(int K) {
+  Mpo m;
+  m.K = K;
+  m.dq.assign(K + 1, std::vector<QN>{QN(0, 0)});
+  m.kind.assign(K + 1, std::vector<int8_t>{0});
+  m.W.assign(K, {});
+  for (int j = 0; j < K; ++j) {
+    MpoEntry e;
+    e.win = 0;
+    e.wout = 0;
+    for (int q = 0; q < 16; ++q) e.m[q] = (q % 5 == 0) ? 1.0 : 0.0;
+    m.W[j].push_back(e);
+  }
+  return m;
+}
+}  // namespace
+
+// Transition operator <bra| H |ket> with the bra's two-site block (site, site+1) cut out: left
+// and right environments between the two MPS (transition-element figure), then the same
+// enlarged operators and plan as an effective Hamiltonian, mapping the ket's two-site space onto
+// the bra's.  The bra must be canonical around the block (its two-site space is the one of the
+// local problem); the ket may be in any gauge.
+Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& bra_d, const lcc_mps_desc& ket_d,
+                          int site) {
+  hipStream_t st = ctx->stream;
+  const Mpo& mpo = ham.mpo;
+  const int K = mpo.K;
+  if (bra_d.n_sites != K || ket_d.n_sites != K)
+    throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
+  if (site < 0 || site + 1 >= K) throw Error{LCC_ERR_ARG, "two-site block must satisfy 0 <= site < K-1"};
+  DeviceMps bra, ket;
+  load_mps(bra_d, ham.desc.N, ham.desc.two_sz, st, bra);
+  load_mps(ket_d, ham.desc.N, ham.desc.two_sz, st, ket);
+  {
+    const Mpo id = identity_mpo(K);
+    Environment L = unit_env(st);
+    for (int j = 0; j < site; ++j) L = left_step(L, bra, j, id, st);
+    if (site > 0) check_identity(L, 0, bra.bonds[site], st, "left");
+    Environment R = unit_env(st);
+    for (int j = K - 1; j >= site + 2; --j) R = right_step(R, bra, j, id, st);
+    if (site + 2 < K) check_identity(R, 0, bra.bonds[site + 2], st, "right");
+  }
+  Environment L = unit_env(st);
+  for (int j = 0; j < site; ++j) L = left_step(L, bra, ket, j, mpo, st);
+  Environment R = unit_env(st);
+  for (int j = K - 1; j >= site + 2; --j) R = right_step(R, bra, ket, j, mpo, st);
+  std::unique_ptr<Env> env(make_env(ctx, mpo, site, bra.bonds[site], bra.bonds[site + 2], ket.bonds[site],
+                                    ket.bonds[site + 2], L, R, true));
+  // the ket's own two-site tensor at the block: x0[a,s1,s2,b] = sum_c A_site^{s1}[a,c] A_{site+1}^{s2}[c,b]
+  std::map<std::pair<int, int>, const SiteBlock*> A1, A2;
+  for (const SiteBlock& b : ket.sites[site]) A1[{b.l, b.s}] = &b;
+  for (const SiteBlock& b : ket.sites[site + 1]) A2[{b.l, b.s}] = &b;
+  GemmBuilder g;
+  for (const lcc_block_entry& blk : env->layout_in) {
+    auto i1 = A1.find({blk.left, blk.s1});
+    if (i1 == A1.end()) continue;
+    auto i2 = A2.find({i1->second->r, blk.s2});
+    if (i2 == A2.end() || i2->second->r != blk.right) continue;
+    g.group(BASE_X, blk.offset, blk.ld, blk.rows, blk.cols, false);
+    g.term(BASE_MPS, i1->second->off, i1->second->cols, BASE_MPS, i2->second->off, i2->second->cols,
+           i1->second->cols, 1.0);
+  }
+  env->x0.alloc(sizeof(double) * std::max<int64_t>(env->n_in, 1));
+  check_hip(launch_fill_f64(env->x0.as<double>(), env->n_in, 0.0, st), "zero ket tensor");
+  Bases<double> b{};
+  b.p[BASE_MPS] = ket.data.as<double>();
+  b.p[BASE_X] = env->x0.as<double>();
+  run_gemm64(finalize(g, false, false, st), b, st);
+  check_hip(hipStreamSynchronize(st), "ket tensor");
+  return env.release();
+}
+
 // The contraction plan of an environment for given planner parameters: channel chunks and
 // the intermediate layout, the phase-1 and phase-2 grouped GEMMs, the split-K reduction and
 // the workspaces.  Replaces any previous plan.
@@ -562,11 +663,14 @@ void plan_env(Env& E, const PlanParams& pp) {
   Env* env = &E;
   Context* ctx = E.ctx;
   hipStream_t st = ctx->stream;
-  const Bond& bl = E.bl;
+  const Bond& bl = E.bl;      // output (bra) rows and columns
   const Bond& br = E.br;
-  auto& sec_index = E.in.sec_index;
-  auto& row_at = E.in.row_at;
-  auto& col_at = E.in.col_at;
+  const Bond& bl0 = E.bl_in;  // input (ket) rows and columns
+  const Bond& br0 = E.br_in;
+  auto& sec_index = E.in.sec_index;        // output sectors by (N, 2Sz)
+  auto& sec_index_in = E.in.sec_index_in;  // input sectors
+  auto& row_at_in = E.in.row_at_in;
+  auto& col_at_in = E.in.col_at_in;
   auto& lt = E.in.lt;
   auto& rt = E.in.rt;
   const std::vector<QN>& dq_mid = E.in.dq_mid;
@@ -574,15 +678,15 @@ void plan_env(Env& E, const PlanParams& pp) {
   E.plan = Plan();
   // ---- active (w1, source sector) pairs and the intermediate layout
   const int D = env->D_mid;
-  const int nsec = (int)env->sectors.size();
+  const int nsec = (int)env->sectors_in.size();  // source (input) sectors
   std::vector<char> lact((size_t)D * nsec, 0), ract((size_t)D * nsec, 0);
   for (const auto& kv : lt) {
     const int w1 = std::get<0>(kv.first);
-    for (const auto& src : kv.second) lact[(size_t)w1 * nsec + row_at[{std::get<0>(src), std::get<1>(src)}].first] = 1;
+    for (const auto& src : kv.second) lact[(size_t)w1 * nsec + row_at_in[{std::get<0>(src), std::get<1>(src)}].first] = 1;
   }
   for (const auto& kv : rt) {
     const int w1 = std::get<0>(kv.first);
-    for (const auto& src : kv.second) ract[(size_t)w1 * nsec + col_at[{std::get<0>(src), std::get<1>(src)}].first] = 1;
+    for (const auto& src : kv.second) ract[(size_t)w1 * nsec + col_at_in[{std::get<0>(src), std::get<1>(src)}].first] = 1;
   }
   // Channels are taken in order and cut into chunks whose intermediates fit the workspace
   // budget; each chunk reuses the same intermediate buffer (and, when small, stays in the
@@ -596,9 +700,9 @@ void plan_env(Env& E, const PlanParams& pp) {
     int64_t need = 0;
     for (int m = 0; m < nsec; ++m) {
       if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
-      auto it = sec_index.find(env->sectors[m].q + dq_mid[w1]);
+      auto it = sec_index.find(env->sectors_in[m].q + dq_mid[w1]);
       if (it == sec_index.end()) continue;
-      need += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
+      need += (int64_t)env->sectors[it->second].nrows * env->sectors_in[m].ncols;
     }
     if (used > 0 && used + need > budget) {
       ++nchunks;
@@ -607,10 +711,10 @@ void plan_env(Env& E, const PlanParams& pp) {
     chunk_of[w1] = nchunks - 1;
     for (int m = 0; m < nsec; ++m) {
       if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
-      auto it = sec_index.find(env->sectors[m].q + dq_mid[w1]);
+      auto it = sec_index.find(env->sectors_in[m].q + dq_mid[w1]);
       if (it == sec_index.end()) continue;
       t_off[(size_t)w1 * nsec + m] = used;
-      used += (int64_t)env->sectors[it->second].nrows * env->sectors[m].ncols;
+      used += (int64_t)env->sectors[it->second].nrows * env->sectors_in[m].ncols;
     }
     t_max = std::max(t_max, used);
   }
@@ -624,7 +728,7 @@ void plan_env(Env& E, const PlanParams& pp) {
       const int64_t to = t_off[(size_t)w1 * nsec + m];
       if (to < 0) continue;
       GemmBuilder& B1 = p1[chunk_of[w1]];
-      const MiddleSector& S = env->sectors[m];
+      const MiddleSector& S = env->sectors_in[m];
       const MiddleSector& Sp = env->sectors[sec_index[S.q + dq_mid[w1]]];
       for (size_t i = 0; i < Sp.rows.size(); ++i) {
         const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
@@ -637,10 +741,10 @@ void plan_env(Env& E, const PlanParams& pp) {
         auto it = lt.find(std::make_tuple(w1, ap, sp));
         if (it == lt.end()) continue;
         for (const auto& src : it->second) {
-          const auto ra = row_at[{std::get<0>(src), std::get<1>(src)}];
+          const auto ra = row_at_in[{std::get<0>(src), std::get<1>(src)}];
           if (ra.first != m) continue;
           const OperandRef& ref = std::get<2>(src);
-          const int ka = bl.dim[std::get<0>(src)];
+          const int ka = bl0.dim[std::get<0>(src)];
           const int64_t x_off = S.off + (int64_t)S.row_off[ra.second] * S.ncols;
           if (pp.t_colmajor)
             B1.term(BASE_X, x_off, S.ncols, ref.base, ref.off, ka, ka, ref.alpha);
@@ -664,7 +768,7 @@ void plan_env(Env& E, const PlanParams& pp) {
     int ldc = 0, m = 0, n = 0;
     std::vector<GemmTerm> terms;
   };
-  for (int mp = 0; mp < nsec; ++mp) {
+  for (int mp = 0; mp < (int)env->sectors.size(); ++mp) {
     const MiddleSector& Sp = env->sectors[mp];
     std::vector<Emit> emits;
     for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
@@ -674,19 +778,19 @@ void plan_env(Env& E, const PlanParams& pp) {
       std::vector<std::vector<GemmTerm>> per(nchunks);
       std::vector<std::vector<int>> per_w1(nchunks);
       for (int w1 = 0; w1 < D; ++w1) {
-        auto si = sec_index.find(Sp.q - dq_mid[w1]);
-        if (si == sec_index.end()) continue;
+        auto si = sec_index_in.find(Sp.q - dq_mid[w1]);
+        if (si == sec_index_in.end()) continue;
         const int m = si->second;
         const int64_t to = t_off[(size_t)w1 * nsec + m];
         if (to < 0) continue;
         auto it = rt.find(std::make_tuple(w1, s2p, bp));
         if (it == rt.end()) continue;
-        const MiddleSector& S = env->sectors[m];
+        const MiddleSector& S = env->sectors_in[m];
         for (const auto& src : it->second) {
-          const auto ca = col_at[{std::get<0>(src), std::get<1>(src)}];
+          const auto ca = col_at_in[{std::get<0>(src), std::get<1>(src)}];
           if (ca.first != m) continue;
           const OperandRef& ref = std::get<2>(src);
-          const int kb = br.dim[std::get<1>(src)];
+          const int kb = br0.dim[std::get<1>(src)];
           GemmTerm t{};
           t.a_base = BASE_T;
           if (pp.t_colmajor) {  // columns (s2,b) of a column-major block: stored k x m
@@ -809,22 +913,15 @@ void plan_env(Env& E, const PlanParams& pp) {
   check_hip(hipStreamSynchronize(st), "plan");
 }
 
-Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
-              const Environment& L, const Environment& R) {
-  hipStream_t st = ctx->stream;
-  const int K = mpo.K;
-  std::unique_ptr<Env> env(new Env());
-  env->ctx = ctx;
-  env->site = site;
-  env->K = K;
-  env->bl = bond_l;
-  env->br = bond_r;
-  const Bond& bl = env->bl;
-  const Bond& br = env->br;
-  const int mid = site + 1;  // MPO bond between the two sites
-  env->D_mid = (int)mpo.dq[mid].size();
+namespace {
 
-  // ---- middle-bond sectors and the vector layout
+// Middle-bond sectors of a two-site block (rows (a, s1) over bond bl, columns (s2, b) over bond
+// br), their vector layout and the row / column lookup (a, s1) -> (sector, row index),
+// (s2, b) -> (sector, col index).  Returns the vector length.
+int64_t middle_sectors(const Bond& bl, const Bond& br, std::vector<MiddleSector>& sectors, std::map<QN, int>& sec_index,
+                       std::vector<lcc_block_entry>& layout,
+                       std::map<std::pair<int, int>, std::pair<int, int>>& row_at,
+                       std::map<std::pair<int, int>, std::pair<int, int>>& col_at) {
   std::map<QN, MiddleSector> secs;
   for (size_t a = 0; a < bl.q.size(); ++a)
     for (int s1 = 0; s1 < 4; ++s1) secs[bl.q[a] + local_qn(s1)].rows.push_back({(int)a, s1});
@@ -833,19 +930,19 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
       auto it = secs.find(br.q[b] - local_qn(s2));
       if (it != secs.end()) it->second.cols.push_back({s2, (int)b});
     }
-  std::map<QN, int>& sec_index = env->in.sec_index;
+  int64_t total = 0;
   for (auto& kv : secs) {
     MiddleSector& m = kv.second;
     if (m.rows.empty() || m.cols.empty()) continue;
     m.q = kv.first;
     for (auto& r : m.rows) { m.row_off.push_back(m.nrows); m.nrows += bl.dim[r.first]; }
     for (auto& c : m.cols) { m.col_off.push_back(m.ncols); m.ncols += br.dim[c.second]; }
-    m.off = env->n_elements;
-    env->n_elements += (int64_t)m.nrows * m.ncols;
-    sec_index[m.q] = (int)env->sectors.size();
-    env->sectors.push_back(m);
+    m.off = total;
+    total += (int64_t)m.nrows * m.ncols;
+    sec_index[m.q] = (int)sectors.size();
+    sectors.push_back(m);
   }
-  for (const MiddleSector& m : env->sectors)
+  for (const MiddleSector& m : sectors)
     for (size_t i = 0; i < m.rows.size(); ++i)
       for (size_t jx = 0; jx < m.cols.size(); ++jx) {
         lcc_block_entry e;
@@ -857,15 +954,46 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         e.ld = m.ncols;
         e.rows = bl.dim[e.left];
         e.cols = br.dim[e.right];
-        env->layout.push_back(e);
+        layout.push_back(e);
       }
-  // row / column lookup: (a, s1) -> (sector, row index); (s2, b) -> (sector, col index)
+  for (size_t m = 0; m < sectors.size(); ++m) {
+    for (size_t i = 0; i < sectors[m].rows.size(); ++i) row_at[sectors[m].rows[i]] = {(int)m, (int)i};
+    for (size_t i = 0; i < sectors[m].cols.size(); ++i) col_at[sectors[m].cols[i]] = {(int)m, (int)i};
+  }
+  return total;
+}
+
+}  // namespace
+
+Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
+              const Environment& L, const Environment& R) {
+  return make_env(ctx, mpo, site, bond_l, bond_r, bond_l, bond_r, L, R, false);
+}
+
+Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r, const Bond& ket_l,
+              const Bond& ket_r, const Environment& L, const Environment& R, bool transition) {
+  hipStream_t st = ctx->stream;
+  const int K = mpo.K;
+  std::unique_ptr<Env> env(new Env());
+  env->ctx = ctx;
+  env->site = site;
+  env->K = K;
+  env->bl = bond_l;
+  env->br = bond_r;
+  env->bl_in = ket_l;
+  env->br_in = ket_r;
+  env->transition = transition;
+  const int mid = site + 1;  // MPO bond between the two sites
+  env->D_mid = (int)mpo.dq[mid].size();
+
+  // ---- middle-bond sectors and the vector layouts (output: bra; input: ket)
   auto& row_at = env->in.row_at;
   auto& col_at = env->in.col_at;
-  for (size_t m = 0; m < env->sectors.size(); ++m) {
-    for (size_t i = 0; i < env->sectors[m].rows.size(); ++i) row_at[env->sectors[m].rows[i]] = {(int)m, (int)i};
-    for (size_t i = 0; i < env->sectors[m].cols.size(); ++i) col_at[env->sectors[m].cols[i]] = {(int)m, (int)i};
-  }
+  auto& row_at_in = env->in.row_at_in;
+  auto& col_at_in = env->in.col_at_in;
+  env->n_elements = middle_sectors(env->bl, env->br, env->sectors, env->in.sec_index, env->layout, row_at, col_at);
+  env->n_in = middle_sectors(env->bl_in, env->br_in, env->sectors_in, env->in.sec_index_in, env->layout_in, row_at_in,
+                             col_at_in);
 
   // ---- environment data on the device: [L | R]
   env->env_elems = L.size + R.size;
@@ -887,7 +1015,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         for (int s = 0; s < 4; ++s) {
           const double c = e.m[sp * 4 + s];
           if (c == 0.0) continue;
-          if (!row_at.count({lb.r, sp}) || !row_at.count({lb.c, s})) continue;
+          if (!row_at.count({lb.r, sp}) || !row_at_in.count({lb.c, s})) continue;
           lt_terms[std::make_tuple(e.wout, lb.r, sp, lb.c, s)].push_back({bi, c});
         }
     }
@@ -901,7 +1029,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         for (int s = 0; s < 4; ++s) {
           const double c = e.m[sp * 4 + s];
           if (c == 0.0) continue;
-          if (!col_at.count({sp, rb.r}) || !col_at.count({s, rb.c})) continue;
+          if (!col_at.count({sp, rb.r}) || !col_at_in.count({s, rb.c})) continue;
           rt_terms[std::make_tuple(e.win, sp, rb.r, s, rb.c)].push_back({bi, c});
         }
     }
@@ -952,10 +1080,12 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
 
   env->in.dq_mid = mpo.dq[mid];
   plan_env(*env, ctx->plan_params);
-  // CG workspace (FP64)
-  for (auto& w : env->w64) w.alloc(sizeof(double) * std::max<int64_t>(env->n_elements, 1));
-  env->flag.alloc(sizeof(int) * 4);
-  apply_tuned(*env);
+  if (!transition) {
+    // CG workspace (FP64)
+    for (auto& w : env->w64) w.alloc(sizeof(double) * std::max<int64_t>(env->n_elements, 1));
+    env->flag.alloc(sizeof(int) * 4);
+    apply_tuned(*env);
+  }
   check_hip(hipStreamSynchronize(st), "build_env");
   return env.release();
 }

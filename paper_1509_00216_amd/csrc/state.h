@@ -168,8 +168,10 @@ struct OperandRef {
 };
 // What the planner needs besides the environments themselves (kept for re-planning).
 struct PlanInputs {
-  std::map<QN, int> sec_index;
+  // output (bra) side and input (ket) side; the same for an effective Hamiltonian
+  std::map<QN, int> sec_index, sec_index_in;
   std::map<std::pair<int, int>, std::pair<int, int>> row_at, col_at;  // (a,s1) / (s2,b) -> (sector, index)
+  std::map<std::pair<int, int>, std::pair<int, int>> row_at_in, col_at_in;
   // Lt: (w1, a', s1') -> [(a, s1, ref)];  Rt: (w1, s2', b') -> [(s2, b, ref)]
   std::map<std::tuple<int, int, int>, std::vector<std::tuple<int, int, OperandRef>>> lt, rt;
   std::vector<QN> dq_mid;
@@ -179,10 +181,19 @@ struct Env {
   Context* ctx = nullptr;
   int site = 0, K = 0;
   int D_mid = 0;
-  Bond bl, br;  // MPS bonds site and site+2
+  Bond bl, br;  // MPS bonds site and site+2 (of the bra: rows of the operator, the output vector)
   std::vector<MiddleSector> sectors;
   std::vector<lcc_block_entry> layout;
   int64_t n_elements = 0;
+  // input side (the ket: columns of the operator).  For an effective Hamiltonian bra = ket and
+  // these equal the output side; a transition operator between two MPS maps the ket's two-site
+  // space onto the bra's.
+  bool transition = false;
+  Bond bl_in, br_in;
+  std::vector<MiddleSector> sectors_in;
+  std::vector<lcc_block_entry> layout_in;
+  int64_t n_in = 0;
+  DevBuf x0;  // transition operator: the ket's own two-site tensor (input layout)
   // device data: [L blocks | R blocks] in FP64 (+ FP32 copy), merged blocks (+ FP32 copy)
   DevBuf env64, env32, merged64, merged32, tbuf, work;
   int64_t env_elems = 0, merged_elems = 0, t_elems = 0, work_elems = 0;
@@ -218,6 +229,11 @@ Environment unit_env(hipStream_t st);
 // one site of the left (right) environment recursion, on the device
 Environment left_step(const Environment& L, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st);
 Environment right_step(const Environment& R, const DeviceMps& mps, int j, const Mpo& mpo, hipStream_t st);
+// the same between two MPS: rows of the environment from the bra, columns from the ket
+Environment left_step(const Environment& L, const DeviceMps& bra, const DeviceMps& ket, int j, const Mpo& mpo,
+                      hipStream_t st);
+Environment right_step(const Environment& R, const DeviceMps& bra, const DeviceMps& ket, int j, const Mpo& mpo,
+                       hipStream_t st);
 void check_identity(const Environment& E, int w_id, const Bond& bond, hipStream_t st, const char* which);
 int channel_of_kind(const Mpo& mpo, int bond, int kind);
 // (re)plan an environment's H_eff x for the given planner parameters
@@ -229,6 +245,11 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info);
 // enlarged operators, vector layout and apply plan of the two-site block (site, site+1)
 Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r,
               const Environment& L, const Environment& R);
+// the transition operator between a bra (bonds bra_l, bra_r; rows of L and R) and a ket
+Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bra_l, const Bond& bra_r, const Bond& ket_l,
+              const Bond& ket_r, const Environment& L, const Environment& R, bool transition);
+Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& bra, const lcc_mps_desc& ket,
+                          int site);
 
 // env.cpp
 Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);

@@ -29,7 +29,8 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
            "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan", "lcc_lowest_eigenpair",
-           "lcc_lowest_eigenvalue_noalloc"]
+           "lcc_lowest_eigenvalue_noalloc", "lcc_build_transition_environments", "lcc_env_input_layout",
+           "lcc_env_ket_tensor"]
 
 
 class LccError(RuntimeError):
@@ -59,7 +60,7 @@ class MpsDesc(C.Structure):
 
 class LayoutInfo(C.Structure):
     _fields_ = [("n_elements", C.c_int64), ("n_blocks", C.c_int32), ("n_sectors", C.c_int32),
-                ("mpo_bond_dim", C.c_int32), ("reserved", C.c_int32), ("flops_per_apply", C.c_double)]
+                ("mpo_bond_dim", C.c_int32), ("transition", C.c_int32), ("flops_per_apply", C.c_double)]
 
 
 class BlockEntry(C.Structure):
@@ -122,6 +123,10 @@ def library() -> C.CDLL:
         "lcc_build_environments": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
         "lcc_env_destroy": (None, [P]),
         "lcc_env_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
+        "lcc_env_input_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
+        "lcc_env_ket_tensor": (C.c_int32, [P, P]),
+        "lcc_build_transition_environments": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.POINTER(MpsDesc), C.c_int32,
+                                                          C.POINTER(P)]),
         "lcc_env_flops": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lcc_apply_heff": (C.c_int32, [P, C.c_int32, P, P]),
         "lcc_solve_local_lcc": (C.c_int32, [P, C.POINTER(SolveOpts), P, C.c_double, P, P, C.POINTER(SolveInfo)]),
@@ -333,11 +338,19 @@ class Env:
         self.n_blocks = int(info.n_blocks)
         self.n_sectors = int(info.n_sectors)
         self.mpo_bond_dim = int(info.mpo_bond_dim)
+        self.transition = bool(info.transition)
         self.flops_per_apply = float(info.flops_per_apply)
         arr = (BlockEntry * max(1, self.n_blocks))()
         _check(library().lcc_env_layout(self.handle, C.byref(info), arr))
         self.blocks = {(b.left, b.s1, b.s2, b.right): (b.offset, b.ld, b.rows, b.cols)
                        for b in arr[: self.n_blocks]}
+        # input side (the ket's two-site tensor of a transition operator; else the same layout)
+        _check(library().lcc_env_input_layout(self.handle, C.byref(info), None))
+        self.n_in = int(info.n_elements)
+        arr = (BlockEntry * max(1, int(info.n_blocks)))()
+        _check(library().lcc_env_input_layout(self.handle, C.byref(info), arr))
+        self.blocks_in = {(b.left, b.s1, b.s2, b.right): (b.offset, b.ld, b.rows, b.cols)
+                          for b in arr[: int(info.n_blocks)]}
 
     def close(self):
         if self.handle:
@@ -373,9 +386,24 @@ class Env:
             out[key] = np.asarray(flat)[idx]
         return out
 
+    def pack_in(self, vec: dict) -> np.ndarray:
+        """pack() for the input side (the ket's layout of a transition operator)."""
+        out = np.zeros(self.n_in)
+        for key, (off, ld, rows, cols) in self.blocks_in.items():
+            blk = vec.get(key)
+            if blk is None:
+                continue
+            idx = off + np.arange(rows)[:, None] * ld + np.arange(cols)[None, :]
+            out[idx] = blk
+        return out
+
+    def ket_tensor(self, x):
+        """lcc_env_ket_tensor: the ket's two-site tensor of a transition operator into x (FP64, input layout)."""
+        _check(library().lcc_env_ket_tensor(self.handle, _tensor_ptr(x, "fp64", self.n_in)), self.ctx.handle)
+
     def apply_heff(self, x, y, precision: str = "fp64"):
         dt = "fp64" if precision == "fp64" else "fp32"
-        _check(library().lcc_apply_heff(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n),
+        _check(library().lcc_apply_heff(self.handle, PRECISIONS[precision], _tensor_ptr(x, dt, self.n_in),
                                         _tensor_ptr(y, dt, self.n)), self.ctx.handle)
 
     def profile_apply(self, x, y, precision: str = "fp64", reps: int = 10):
@@ -456,6 +484,19 @@ def build_environments(ctx: Context, ham: Hamiltonian, mps: dict, site: int | No
     out = C.c_void_p()
     _check(library().lcc_build_environments(ctx.handle, ham.handle, C.byref(desc), site, C.byref(out)), ctx.handle)
     del keep
+    return Env(out, ctx)
+
+
+def build_transition_environments(ctx: Context, ham: Hamiltonian, bra: dict, ket: dict, site: int | None = None) -> Env:
+    """lcc_build_transition_environments: <bra| H |ket> with the bra's two-site block cut out."""
+    if site is None:
+        site = bra["center"]
+    bd, keep_b = _mps_desc(bra)
+    kd, keep_k = _mps_desc(ket)
+    out = C.c_void_p()
+    _check(library().lcc_build_transition_environments(ctx.handle, ham.handle, C.byref(bd), C.byref(kd), site,
+                                                       C.byref(out)), ctx.handle)
+    del keep_b, keep_k
     return Env(out, ctx)
 
 
