@@ -30,7 +30,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def shift_for(spec, env, name):
+def shift_for(spec, env, name, starts: int = 2):
     """E0 below the lowest eigenvalue of H_eff, so that Q(H_eff - E0)Q is positive definite.
 
     Lattice models (one-body + non-negative on-site U): E(U=0) - 0.5, a rigorous bound.  Ab initio:
@@ -41,6 +41,8 @@ def shift_for(spec, env, name):
     if spec["eri"] is None:
         return C.lower_bound_shift(spec, 0.5), "E(U=0) - 0.5"
     t1, r1 = env.lowest_eigenvalue(steps=60, seed=7)
+    if starts < 2:
+        return t1 - max(0.5, 2.0 * r1), f"lanczos theta={t1:.12f} res={r1:.3e}, minus max(0.5, 2 res)"
     t2, r2 = env.lowest_eigenvalue(steps=60, seed=8)
     if abs(t1 - t2) > 2.0 * (r1 + r2) + 1e-9:
         raise RuntimeError(f"Lanczos runs disagree: {t1} (res {r1}) vs {t2} (res {r2})")
@@ -99,11 +101,16 @@ def cpu_baseline_worker(workload: str, target_s: float) -> None:
     from oracle import stacked as ST
     from workloads import configs as C
     from workloads import mps as M
+    import threadpoolctl
     t0 = time.perf_counter()
-    spec, mps = C.make(workload)
-    fe = ST.FullSizeEnvironments(spec, mps, OM.build_mpo_twosided(spec))
+    with threadpoolctl.threadpool_limits(limits=max(1, (os.cpu_count() or 2) // 2)):
+        spec, mps = C.make(workload)
+        fe = ST.FullSizeEnvironments(spec, mps, OM.build_mpo_twosided(spec))
     t_setup = time.perf_counter() - t0
     X = fe.to_sectors(M.random_two_site_vector(mps, 17))
+    # the timed products start when the parent has finished its own work and waits
+    print("ready", flush=True)
+    sys.stdin.readline()
     reps, t_apply, flops = 0, 0.0, 0
     while t_apply < target_s and reps < 10:
         cnt = {}
@@ -112,12 +119,7 @@ def cpu_baseline_worker(workload: str, target_s: float) -> None:
         t_apply += time.perf_counter() - t0
         flops += cnt["flops"]
         reps += 1
-    blas = []
-    try:
-        import threadpoolctl
-        blas = [{k: i.get(k) for k in ("internal_api", "num_threads", "version")} for i in threadpoolctl.threadpool_info()]
-    except Exception:
-        pass
+    blas = [{k: i.get(k) for k in ("internal_api", "num_threads", "version")} for i in threadpoolctl.threadpool_info()]
     threads = max([b.get("num_threads") or 1 for b in blas] or [1])
     print(json.dumps({"value": flops / t_apply / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
                       "sample": (f"{reps} whole H_eff x product(s) of {workload} by the oracle (numpy FP64, "
@@ -131,13 +133,14 @@ def start_cpu_baseline(workload: str, target_s: float = 20.0):
     """Start the oracle's timing in a child process so that it runs beside the GPU measurements."""
     import subprocess
     return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", workload,
-                             "--cpu-baseline-seconds", str(target_s)], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
-                            text=True)
+                             "--cpu-baseline-seconds", str(target_s)], stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                            stderr=subprocess.PIPE, text=True)
 
 
 def finish_cpu_baseline(proc, timeout_s: float = 600.0):
+    """Let the child start its timed products (the GPU work is over) and collect its line."""
     try:
-        out, err = proc.communicate(timeout=timeout_s)
+        out, err = proc.communicate(input="go\n", timeout=timeout_s)
     except Exception as e:  # noqa: BLE001
         proc.kill()
         return {"value": None, "unit": "GFLOP/s", "cores": None, "kind": "oracle", "sample": f"oracle run failed: {e}"}
@@ -201,17 +204,27 @@ def measure_batch(args) -> dict:
     envs, bs, e0s, flops = [], [], [], []
     hams = {}
     t0 = time.perf_counter()
+    t_inputs = t_env = t_shift = 0.0
     for i, (parent, m, seed) in enumerate(members):
+        ta = time.perf_counter()
         spec, mps = C.make_member(parent, m, seed)
+        b_host = M.random_two_site_vector(mps, seed + 7)
+        tb = time.perf_counter()
         if parent not in hams:
             hams[parent] = ctx.create_hamiltonian(spec)
         env = ctx.build_environments(hams[parent], mps)
-        e0, _ = shift_for(spec, env, parent)
+        tc = time.perf_counter()
+        e0, _ = shift_for(spec, env, parent, starts=1)
+        td = time.perf_counter()
+        t_inputs += tb - ta
+        t_env += tc - tb
+        t_shift += td - tc
         envs.append(env)
         e0s.append(e0)
         flops.append(env.flops_per_apply)
-        bs.append(torch.tensor(env.pack(M.random_two_site_vector(mps, seed + 7)), dtype=torch.float64, device=dev))
-        log(f"[batch] member {i}: {parent} M={m} n={env.n} F={env.flops_per_apply:.3e} E0={e0:.6f}")
+        bs.append(torch.tensor(env.pack(b_host), dtype=torch.float64, device=dev))
+        log(f"[batch] member {i}: {parent} M={m} n={env.n} F={env.flops_per_apply:.3e} E0={e0:.6f} "
+            f"(inputs {tb - ta:.1f}s, environments {tc - tb:.1f}s, shift {td - tc:.1f}s)")
     t_setup = time.perf_counter() - t0
     xs = [torch.zeros_like(b) for b in bs]
     batch = lcc.Batch(ctx, envs)
@@ -246,7 +259,8 @@ def measure_batch(args) -> dict:
            "mean_applies_per_problem": applies, "flops_per_apply_total": sum(flops),
            "gflops_batched": sum(f * (i["applies_fp64"] + i["applies_low"]) for f, i in zip(flops, infos)) /
            (ms_batch * 1e-3) / 1e9,
-           "setup_s": t_setup, "intermediate_limit_mib": args.batch_intermediate_mib,
+           "setup_s": t_setup, "setup_split_s": {"inputs": t_inputs, "environments": t_env, "shift": t_shift},
+           "intermediate_limit_mib": args.batch_intermediate_mib,
            "members": [{"parent": p, "m": m} for p, m, _ in members]}
     batch.close()
     for env in envs:
