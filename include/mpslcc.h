@@ -194,6 +194,12 @@ lcc_status lcc_env_input_layout(lcc_env env, lcc_layout_info* info, lcc_block_en
  * double*, lcc_env_input_layout length.  LCC_ERR_STATE for an effective Hamiltonian.  Synchronous. */
 lcc_status lcc_env_ket_tensor(lcc_env env, double* x_dev);
 
+/* Diagonal of H_eff in the vector layout: d[(a,s1,i),(s2,b,j)] = sum over the middle MPO channels
+ * that keep the sector of the diagonal entries of the enlarged left and right operators' diagonal
+ * blocks; one gather and one grouped GEMM per call the first time, cached afterwards.  d_dev:
+ * double*, lcc_env_layout length.  LCC_ERR_STATE for a transition operator.  Synchronous. */
+lcc_status lcc_env_diagonal(lcc_env env, double* d_dev);
+
 /* Flop counts of one H_eff x: 2*m*n*k summed over every block product the plan performs
  * (phase 1: enlarged left operator times x; phase 2: times enlarged right operator).
  * Only symmetry-allowed blocks and nonzero MPO entries are counted; no padding. */
@@ -313,6 +319,10 @@ typedef struct {
                             (default 0.1) */
   int32_t max_outer;     /* mixed precision: maximum FP64 refreshes (default 200) */
   int32_t replace_every; /* FP64 CG: recompute r = Q b - A x every this many iterations (default 50) */
+  int32_t preconditioner; /* 0: none; 1: Jacobi, M = diag(H_eff) - e0 (lcc_env_diagonal), applied as
+                             z = Q M^-1 r (Implementation section: the local equations are solved
+                             iteratively; the diagonal is the usual preconditioner of those solvers).
+                             LCC_ERR_NOT_SPD if an entry of M is <= 0.  Batched solves take 0 only. */
 } lcc_solve_opts;
 typedef struct {
   int32_t iterations;    /* CG iterations, all precisions */

@@ -290,6 +290,20 @@ lcc_status lcc_env_ket_tensor(lcc_env env, double* x) {
   });
 }
 
+lcc_status lcc_env_diagonal(lcc_env env, double* d) {
+  if (!env || !d) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(env->e->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(env->e->ctx->device), "hipSetDevice");
+    compute_diagonal(*env->e);
+    hipStream_t st = env->e->ctx->stream;
+    check_hip(hipMemcpyAsync(d, env->e->diag64.p, sizeof(double) * env->e->n_elements, hipMemcpyDeviceToDevice, st),
+              "copy");
+    check_hip(hipStreamSynchronize(st), "copy sync");
+    return LCC_OK;
+  });
+}
+
 lcc_status lcc_env_flops(lcc_env env, double* phase1, double* phase2) {
   if (!env || !phase1 || !phase2) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
   *phase1 = env->e->plan.flops1;
@@ -445,6 +459,7 @@ lcc_status lcc_batch_solve(lcc_batch batch, const lcc_solve_opts* opts, const do
     check_hip(hipSetDevice(batch->ctx->device), "hipSetDevice");
     lcc_solve_opts o{};
     if (opts) o = *opts;
+    if (o.preconditioner != 0) throw Error{LCC_ERR_ARG, "batched solves are not preconditioned"};
     return batch_solve(*batch->b, o, b, e0, v, x, infos);
   });
 }

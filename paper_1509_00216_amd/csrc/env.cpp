@@ -1103,6 +1103,97 @@ void ensure_fp32(Env& env) {
   env.have32 = true;
 }
 
+// diag(H_eff)[(a,s1,i),(s2,b,j)] = sum_{w1} Lt^{w1}[(a,s1,i),(a,s1,i)] Rt^{w1}[(s2,b,j),(s2,b,j)] over the
+// middle channels that keep the sector (dq = 0): per sector q the diagonals of the enlarged
+// operators' diagonal blocks are gathered into DL_q (channels x rows) and DR_q (channels x
+// columns), and D_q = DL_q^T DR_q is one GEMM.
+void compute_diagonal(Env& E) {
+  if (E.have_diag) return;
+  if (E.transition) throw Error{LCC_ERR_STATE, "a transition environment has no diagonal"};
+  hipStream_t st = E.ctx->stream;
+  const int nsec = (int)E.sectors.size();
+  struct Ref { int w1, m, off, dim; OperandRef ref; };
+  std::vector<Ref> lrefs, rrefs;
+  std::set<std::pair<int, int>> lhas, rhas;  // (sector, w1)
+  for (const auto& kv : E.in.lt) {
+    int w1, ap, sp;
+    std::tie(w1, ap, sp) = kv.first;
+    if (E.in.dq_mid[w1] != QN(0, 0)) continue;
+    for (const auto& src : kv.second) {
+      if (std::get<0>(src) != ap || std::get<1>(src) != sp) continue;
+      const auto ra = E.in.row_at.at({ap, sp});
+      lrefs.push_back(Ref{w1, ra.first, E.sectors[ra.first].row_off[ra.second], E.bl.dim[ap], std::get<2>(src)});
+      lhas.insert({ra.first, w1});
+    }
+  }
+  for (const auto& kv : E.in.rt) {
+    int w1, s2p, bp;
+    std::tie(w1, s2p, bp) = kv.first;
+    if (E.in.dq_mid[w1] != QN(0, 0)) continue;
+    for (const auto& src : kv.second) {
+      if (std::get<0>(src) != s2p || std::get<1>(src) != bp) continue;
+      const auto ca = E.in.col_at.at({s2p, bp});
+      rrefs.push_back(Ref{w1, ca.first, E.sectors[ca.first].col_off[ca.second], E.br.dim[bp], std::get<2>(src)});
+      rhas.insert({ca.first, w1});
+    }
+  }
+  std::vector<std::map<int, int>> chan(nsec);  // sector -> w1 -> row of DL / DR
+  std::vector<int64_t> dl_off(nsec, 0), dr_off(nsec, 0);
+  int64_t dl_total = 0, dr_total = 0;
+  for (const auto& mw : lhas)
+    if (rhas.count(mw)) chan[mw.first].emplace(mw.second, (int)chan[mw.first].size());
+  for (int m = 0; m < nsec; ++m) {
+    dl_off[m] = dl_total;
+    dr_off[m] = dr_total;
+    dl_total += (int64_t)chan[m].size() * E.sectors[m].nrows;
+    dr_total += (int64_t)chan[m].size() * E.sectors[m].ncols;
+  }
+  std::vector<DiagItem> items;
+  auto add = [&](const Ref& r, int64_t base_off, int width, double* /*unused*/) {
+    DiagItem it{};
+    it.src_off = r.ref.off;
+    it.dst_off = base_off + (int64_t)chan[r.m].at(r.w1) * width + r.off;
+    it.alpha = r.ref.alpha;
+    it.ld = r.dim;
+    it.count = r.dim;
+    it.src_base = r.ref.base;
+    items.push_back(it);
+  };
+  for (const Ref& r : lrefs)
+    if (chan[r.m].count(r.w1)) add(r, dl_off[r.m], E.sectors[r.m].nrows, nullptr);
+  const size_t n_left = items.size();
+  for (const Ref& r : rrefs)
+    if (chan[r.m].count(r.w1)) add(r, dr_off[r.m], E.sectors[r.m].ncols, nullptr);
+  DevBuf dl, dr, dli, dri;
+  dl.alloc(sizeof(double) * std::max<int64_t>(dl_total, 1));
+  dr.alloc(sizeof(double) * std::max<int64_t>(dr_total, 1));
+  check_hip(launch_fill_f64(dl.as<double>(), std::max<int64_t>(dl_total, 1), 0.0, st), "zero DL");
+  check_hip(launch_fill_f64(dr.as<double>(), std::max<int64_t>(dr_total, 1), 0.0, st), "zero DR");
+  std::vector<DiagItem> li(items.begin(), items.begin() + n_left), ri(items.begin() + n_left, items.end());
+  upload(dli, li, st);
+  upload(dri, ri, st);
+  Bases<double> b{};
+  b.p[BASE_ENV] = E.env64.as<double>();
+  b.p[BASE_MERGED] = E.merged64.as<double>();
+  check_hip(launch_diag_gather(dli.as<DiagItem>(), (int)li.size(), b, dl.as<double>(), st), "diag gather");
+  check_hip(launch_diag_gather(dri.as<DiagItem>(), (int)ri.size(), b, dr.as<double>(), st), "diag gather");
+  // D_q = DL_q^T DR_q: A stored k-major (channel c, row r at c * nrows + r), B row-major
+  GemmBuilder g;
+  for (int m = 0; m < nsec; ++m) {
+    const MiddleSector& S = E.sectors[m];
+    g.group(BASE_Y, S.off, S.ncols, S.nrows, S.ncols, false);
+    if (!chan[m].empty()) g.term(BASE_T, dl_off[m], S.nrows, BASE_WORK, dr_off[m], S.ncols, (int)chan[m].size(), 1.0);
+  }
+  E.diag64.alloc(sizeof(double) * std::max<int64_t>(E.n_elements, 1));
+  Bases<double> gb{};
+  gb.p[BASE_T] = dl.as<double>();
+  gb.p[BASE_WORK] = dr.as<double>();
+  gb.p[BASE_Y] = E.diag64.as<double>();
+  run_gemm64(finalize(g, true, false, st), gb, st);
+  check_hip(hipStreamSynchronize(st), "diagonal");
+  E.have_diag = true;
+}
+
 namespace {
 void no_callback(void*, const LaunchRef&) {}
 }  // namespace

@@ -170,6 +170,22 @@ hipError_t launch_convert_f32_f64(int64_t n, const float* x, double* y, hipStrea
 hipError_t launch_axpy_f32_into_f64(int64_t n, double a, const float* x, double* y, hipStream_t s);
 // out[0] = 1 if any element is not finite
 hipError_t launch_nonfinite_f64(const double* x, int64_t n, int* flag, hipStream_t s);
+// out[dst_off + i] = alpha * src[src_off + i * (ld + 1)], i < count: the diagonal of a square block
+struct DiagItem {
+  int64_t src_off, dst_off;
+  double alpha;
+  int32_t ld, count;
+  int8_t src_base, pad0;
+  int16_t pad1;
+  int32_t pad2;
+};
+hipError_t launch_diag_gather(const DiagItem* items, int n_items, const Bases<double>& b, double* out, hipStream_t s);
+// y = a * x elementwise
+hipError_t launch_mul_f64(int64_t n, const double* a, const double* x, double* y, hipStream_t s);
+hipError_t launch_mul_f32(int64_t n, const float* a, const float* x, float* y, hipStream_t s);
+// m = 1 / (d - e0) in FP64 and FP32; flag[0] = 1 where d - e0 <= 0
+hipError_t launch_jacobi_inverse(int64_t n, const double* d, double e0, double* m64, float* m32, int* flag,
+                                 hipStream_t s);
 // fill
 hipError_t launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);

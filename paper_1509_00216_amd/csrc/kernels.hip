@@ -1168,6 +1168,55 @@ hipError_t launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// Diagonal of the effective Hamiltonian: gathers of block diagonals, elementwise products.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+diag_gather_kernel(const DiagItem* __restrict__ items, Bases<double> bases, double* __restrict__ out) {
+  const DiagItem it = items[blockIdx.x];
+  const double* __restrict__ src = bases.p[it.src_base] + it.src_off;
+  for (int i = threadIdx.x; i < it.count; i += kThreads) out[it.dst_off + i] = it.alpha * src[(int64_t)i * (it.ld + 1)];
+}
+hipError_t launch_diag_gather(const DiagItem* items, int n_items, const Bases<double>& b, double* out, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(diag_gather_kernel, dim3(n_items), dim3(kThreads), 0, s, items, b, out);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void mul_kernel(int64_t n, const T* __restrict__ a, const T* __restrict__ x, T* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a[i] * x[i];
+}
+hipError_t launch_mul_f64(int64_t n, const double* a, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(mul_kernel<double>, grid_for(n), dim3(kThreads), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+hipError_t launch_mul_f32(int64_t n, const float* a, const float* x, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(mul_kernel<float>, grid_for(n), dim3(kThreads), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+// Jacobi preconditioner: m[i] = 1 / (d[i] - e0) (FP64 and FP32 copies); flag[0] = 1 if some
+// d[i] - e0 <= 0 (the shifted operator is then not positive definite)
+__global__ void jacobi_inverse_kernel(int64_t n, const double* __restrict__ d, double e0, double* __restrict__ m64,
+                                      float* __restrict__ m32, int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = d[i] - e0;
+    bad |= !(v > 0.0);
+    const double inv = v > 0.0 ? 1.0 / v : 0.0;
+    m64[i] = inv;
+    m32[i] = (float)inv;
+  }
+  if (bad) flag[0] = 1;  // benign race: every writer stores the same value
+}
+hipError_t launch_jacobi_inverse(int64_t n, const double* d, double e0, double* m64, float* m32, int* flag,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_inverse_kernel, grid_for(n), dim3(kThreads), 0, s, n, d, e0, m64, m32, flag);
+  return hipGetLastError();
+}
+
 }  // namespace lcc
 
 namespace lcc {

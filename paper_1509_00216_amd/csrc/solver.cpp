@@ -76,7 +76,9 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
   const int max_outer = o.max_outer > 0 ? o.max_outer : 200;
   const int replace_every = o.replace_every > 0 ? o.replace_every : 50;
   if (prec != LCC_FP64 && prec != LCC_FP32 && prec != LCC_BF16X3) throw Error{LCC_ERR_ARG, "unknown precision"};
+  if (o.preconditioner != 0 && o.preconditioner != 1) throw Error{LCC_ERR_ARG, "unknown preconditioner"};
   if (!finite(e0)) throw Error{LCC_ERR_NAN, "e0 is not finite"};
+  const bool jacobi = o.preconditioner == 1;
 
   Ops ops{env, st, n, e0, v, nullptr};
   double* bq = env.w64[0].as<double>();
@@ -96,6 +98,28 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
     check_hip(hipStreamSynchronize(st), "flag sync");
     if (h) throw Error{LCC_ERR_NAN, "non-finite value in b, x or v"};
   }
+  // Jacobi preconditioner M^-1 = 1 / (diag(H_eff) - e0); positive whenever H_eff - e0 is positive definite
+  double* z = r;  // preconditioned residual (the residual itself without a preconditioner)
+  if (jacobi) {
+    compute_diagonal(env);
+    env.minv64.alloc(sizeof(double) * std::max<int64_t>(n, 1));
+    env.minv32.alloc(sizeof(float) * std::max<int64_t>(n, 1));
+    int* flag = env.flag.as<int>();
+    check_hip(launch_fill_f32(reinterpret_cast<float*>(flag), 1, 0.0f, st), "flag clear");
+    check_hip(launch_jacobi_inverse(n, env.diag64.as<double>(), e0, env.minv64.as<double>(), env.minv32.as<float>(),
+                                    flag, st), "jacobi");
+    int h = 0;
+    check_hip(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+    check_hip(hipStreamSynchronize(st), "flag sync");
+    if (h) throw Error{LCC_ERR_NOT_SPD, "diag(H_eff) - e0 has an entry <= 0: H_eff - e0 is not positive definite"};
+    z = env.w64[4].as<double>();
+  }
+  // z = Q M^-1 r (kept in the range of Q, where every iterate lives)
+  auto precondition64 = [&]() {
+    if (!jacobi) return;
+    check_hip(launch_mul_f64(n, env.minv64.as<double>(), r, z, st), "precondition");
+    ops.project64(z);
+  };
   // bq = Q b ; x <- Q x
   check_hip(hipMemcpyAsync(bq, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "copy b");
   ops.project64(bq);
@@ -112,9 +136,12 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
     check_hip(launch_fill_f64(x, n, 0.0, st), "zero x");
     check_hip(launch_fill_f64(r, n, 0.0, st), "zero r");
   } else if (prec == LCC_FP64) {
+    // (preconditioned) conjugate gradients: rho = r^T z with z = Q M^-1 r (z = r without M)
     double rnorm = residual64();
-    check_hip(hipMemcpyAsync(p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "p = r");
+    precondition64();
+    check_hip(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "p = z");
     double rr = rnorm * rnorm;
+    double rho = jacobi ? ops.dot64(r, z) : rr;
     int it = 0;
     while (std::sqrt(rr) > tol * bn) {
       if (it >= max_iter) { status = LCC_NOT_CONVERGED; break; }
@@ -122,7 +149,7 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
       const double pAp = ops.dot64(p, Ap);
       if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
       if (pAp <= 0.0) throw Error{LCC_ERR_NOT_SPD, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
-      const double alpha = rr / pAp;
+      const double alpha = rho / pAp;
       check_hip(launch_axpby_f64(n, alpha, p, 1.0, x, st), "x update");
       ++it;
       double rr_new;
@@ -134,9 +161,12 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
         rr_new = ops.dot64(r, r);
       }
       if (!finite(rr_new)) throw Error{LCC_ERR_NAN, "non-finite residual"};
-      const double beta = rr_new / rr;
-      check_hip(launch_axpby_f64(n, 1.0, r, beta, p, st), "p update");
+      precondition64();
+      const double rho_new = jacobi ? ops.dot64(r, z) : rr_new;
+      const double beta = rho_new / rho;
+      check_hip(launch_axpby_f64(n, 1.0, z, beta, p, st), "p update");
       rr = rr_new;
+      rho = rho_new;
     }
     inf.iterations = it;
     inf.outer = 1;
@@ -154,6 +184,12 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
       check_hip(launch_convert_f64_f32(n, v, v32, st), "v32");
     }
     ops.v32 = v32;
+    float* z32 = jacobi ? env.w32[5].as<float>() : r32;
+    auto precondition32 = [&]() {
+      if (!jacobi) return;
+      check_hip(launch_mul_f32(n, env.minv32.as<float>(), r32, z32, st), "precondition");
+      ops.project32(z32);
+    };
     // Reliable-update CG: one low-precision Krylov recurrence, with the FP64 true residual
     // r = Q b - A x recomputed (and the accumulated correction folded into the FP64 x)
     // whenever the recurrence residual has dropped by `inner_tol` since the last refresh.
@@ -167,8 +203,10 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
       check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
       check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / sc, r32, st), "scale r32");
       check_hip(launch_fill_f32(d32, n, 0.0f, st), "d = 0");
-      check_hip(hipMemcpyAsync(p32, r32, sizeof(float) * n, hipMemcpyDeviceToDevice, st), "p = r");
+      precondition32();
+      check_hip(hipMemcpyAsync(p32, z32, sizeof(float) * n, hipMemcpyDeviceToDevice, st), "p = z");
       double rr = ops.dot32(r32, r32);
+      double rho = jacobi ? ops.dot32(r32, z32) : rr;
       double rmax = std::sqrt(rr);
       while (true) {
         if (total_it >= max_iter || outer >= max_outer) { status = LCC_NOT_CONVERGED; break; }
@@ -176,7 +214,7 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
         const double pAp = ops.dot32(p32, Ap32);
         if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
         if (pAp <= 0.0) throw Error{LCC_ERR_NOT_SPD, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
-        const double alpha = rr / pAp;
+        const double alpha = rho / pAp;
         check_hip(launch_axpby_f32(n, alpha, p32, 1.0, d32, st), "d update");
         check_hip(launch_axpby_f32(n, -alpha, Ap32, 1.0, r32, st), "r update");
         double rr_new = ops.dot32(r32, r32);
@@ -195,19 +233,23 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
           const double sc_new = rnorm;
           check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
           check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / sc_new, r32, st), "scale r32");
-          // beta from true residual norms; p rescaled to the new units
-          const double rr_true_old = rr * sc * sc;
-          const double rr_true_new = rnorm * rnorm;
-          const double beta = rr_true_new / rr_true_old;
+          // beta from the refreshed residual (rho in true units); p rescaled to the new units
+          precondition32();
+          const double rho_new_units = jacobi ? ops.dot32(r32, z32) : ops.dot32(r32, r32);
+          const double beta = (rho_new_units * sc_new * sc_new) / (rho * sc * sc);
           p_scale = beta * sc / sc_new;
-          check_hip(launch_axpby_f32(n, 1.0, r32, p_scale, p32, st), "p update");
+          check_hip(launch_axpby_f32(n, 1.0, z32, p_scale, p32, st), "p update");
           sc = sc_new;
           rr = ops.dot32(r32, r32);
+          rho = rho_new_units;
           rmax = std::sqrt(rr);
           continue;
         }
-        check_hip(launch_axpby_f32(n, 1.0, r32, rr_new / rr, p32, st), "p update");
+        precondition32();
+        const double rho_new = jacobi ? ops.dot32(r32, z32) : rr_new;
+        check_hip(launch_axpby_f32(n, 1.0, z32, rho_new / rho, p32, st), "p update");
         rr = rr_new;
+        rho = rho_new;
       }
       if (status == LCC_NOT_CONVERGED) {
         check_hip(launch_axpy_f32_into_f64(n, sc, d32, x, st), "x += d");

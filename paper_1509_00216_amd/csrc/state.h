@@ -204,6 +204,9 @@ struct Env {
   DevBuf w64[6], w32[6];
   DevBuf flag;
   bool have32 = false;
+  // diagonal of H_eff (FP64, built on first use) and the Jacobi preconditioner 1 / (diag - e0)
+  DevBuf diag64, minv64, minv32;
+  bool have_diag = false;
 };
 
 struct Hamiltonian {
@@ -254,6 +257,8 @@ Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_de
 // env.cpp
 Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);
 void ensure_fp32(Env& env);
+// diag(H_eff) into env.diag64 (once)
+void compute_diagonal(Env& env);
 void apply_heff(Env& env, int precision, const void* x, void* y);
 // one launch at a time: after_each(phase, kind, launch) runs after each launch is queued
 struct LaunchRef {

@@ -30,7 +30,7 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
            "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan", "lcc_lowest_eigenpair",
            "lcc_lowest_eigenvalue_noalloc", "lcc_build_transition_environments", "lcc_env_input_layout",
-           "lcc_env_ket_tensor"]
+           "lcc_env_ket_tensor", "lcc_env_diagonal"]
 
 
 class LccError(RuntimeError):
@@ -70,7 +70,8 @@ class BlockEntry(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("replace_every", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("replace_every", C.c_int32),
+                ("preconditioner", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -125,6 +126,7 @@ def library() -> C.CDLL:
         "lcc_env_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
         "lcc_env_input_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
         "lcc_env_ket_tensor": (C.c_int32, [P, P]),
+        "lcc_env_diagonal": (C.c_int32, [P, P]),
         "lcc_build_transition_environments": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.POINTER(MpsDesc), C.c_int32,
                                                           C.POINTER(P)]),
         "lcc_env_flops": (C.c_int32, [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -462,10 +464,15 @@ class Env:
         _check(code, self.ctx.handle, allow=(0, 1))
         return {"status": STATUS[code], "theta": th.value, "residual": res.value}
 
+    def diagonal(self, d):
+        """lcc_env_diagonal: diag(H_eff) into d (FP64 device tensor)."""
+        _check(library().lcc_env_diagonal(self.handle, _tensor_ptr(d, "fp64", self.n)), self.ctx.handle)
+
     def solve_local_lcc(self, b, e0: float, x, v=None, precision: str = "fp64", tol: float = 1e-10,
                         max_iter: int = 1000, inner_tol: float = 0.0, max_outer: int = 20,
-                        replace_every: int = 50) -> dict:
-        opts = SolveOpts(PRECISIONS[precision], max_iter, tol, inner_tol, max_outer, replace_every)
+                        replace_every: int = 50, preconditioner: str = "none") -> dict:
+        opts = SolveOpts(PRECISIONS[precision], max_iter, tol, inner_tol, max_outer, replace_every,
+                         {"none": 0, "jacobi": 1}[preconditioner])
         info = SolveInfo()
         code = library().lcc_solve_local_lcc(self.handle, C.byref(opts), _tensor_ptr(b, "fp64", self.n),
                                              float(e0), _tensor_ptr(v, "fp64", self.n) if v is not None else None,

@@ -84,9 +84,12 @@ def test_first_order_rhs_and_solve(label, spec_make, m1, m0, ket_center):
 
     b = -(u - e1 * v)
     vhat = v / v.norm()
-    e0 = C.lower_bound_shift(spec, 0.5)
-    benv = ctx.build_environments(ham, bra, site)
     heff = fock.effective_hamiltonian(spec, bra, blocks)
+    if spec["eri"] is None:
+        e0 = C.lower_bound_shift(spec, 0.5)
+    else:  # below the lowest eigenvalue of the dense H_eff, passed identically to both sides
+        e0 = float(np.linalg.eigvalsh(heff)[0]) - 0.5
+    benv = ctx.build_environments(ham, bra, site)
     bref = -(u_ref - e1_ref * v_ref)
     vh = v_ref / np.linalg.norm(v_ref)
     xs = OS.dense_solution(heff, bref, e0, vh)
