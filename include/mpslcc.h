@@ -20,7 +20,9 @@
  *  - Asynchronous calls run on the context's stream; synchronous calls say so.
  *
  * Ownership: handles are owned by the library and freed by their destroy call
- * (destroy(NULL) is a no-op).  Host input arrays are copied; the caller may free them after
+ * (destroy(NULL) is a no-op).  A context must outlive every use of the Hamiltonians,
+ * environments, batches and sweeps made on it; their destroy calls do not touch the context and
+ * may come in any order.  Host input arrays are copied; the caller may free them after
  * the call returns.  Device vectors belong to the caller; the library keeps no pointer to
  * them after a call returns.  A context is not thread safe; distinct contexts are.
  */

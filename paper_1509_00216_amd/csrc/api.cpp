@@ -242,12 +242,11 @@ lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ha
   });
 }
 
+// The destroy calls do not touch the context: objects may be destroyed in any order (a garbage
+// collector may finalise a context before the environments made on it).  Device memory is
+// released with hipFree, which waits for the device work in flight.
 void lcc_env_destroy(lcc_env env) {
   if (!env || !env->owned) return;
-  if (env->e && env->e->ctx) {
-    (void)hipSetDevice(env->e->ctx->device);
-    (void)hipStreamSynchronize(env->e->ctx->stream);
-  }
   delete env;
 }
 
@@ -446,7 +445,6 @@ lcc_status lcc_batch_create(lcc_context ctx, int32_t n, const lcc_env* envs, lcc
 
 void lcc_batch_destroy(lcc_batch batch) {
   if (!batch) return;
-  (void)hipSetDevice(batch->ctx->device);
   delete batch;
 }
 
@@ -496,8 +494,6 @@ lcc_status lcc_sweep_create(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_
 
 void lcc_sweep_destroy(lcc_sweep sweep) {
   if (!sweep) return;
-  (void)hipSetDevice(sweep->ctx->device);
-  (void)hipStreamSynchronize(sweep->ctx->stream);
   delete sweep;
 }
 

@@ -156,9 +156,10 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
       const int gi = (int)groups.size();
       groups.push_back(g);
       for (int t = 0; t < tiles_m * g.tiles_n; ++t) tiles.push_back(GemmTile{gi, t});
-      // MFMA work issued.  FP64 / FP32 kernels skip the 16 x 16 sub-tiles outside the block
-      // (m, n padded to 16) and pad k to 4 per term (term walk) or to 16 per group of quads
-      // (packed); the BF16x3 kernels run whole tiles and pad k to 32 per term or per group.
+      // MFMA work issued.  The term-walk kernels skip the 16 x 16 sub-tiles outside the block
+      // (m, n padded to 16) and pad k to 4 (FP64 / FP32) or 32 (BF16x3) per term; the packed
+      // kernels pad k to 16 per group of quads (FP64 / FP32, same sub-tile skip) or run whole
+      // tiles with k padded to 32 (BF16x3).
       const int64_t nk = (int64_t)(g.slot_end - g.slot_begin) * 4;
       int64_t k4 = 0, k32 = 0;
       for (int t = g0.term_begin; t < g0.term_end; ++t) {
@@ -171,7 +172,7 @@ std::vector<GemmLaunch> finalize(const GemmBuilder& b, bool ta, bool tb, hipStre
         L.exec_flops[p][0] += live * k4;
         L.exec_flops[p][1] += live * ((nk + 15) / 16 * 16);
       }
-      L.exec_flops[LCC_BF16X3][0] += whole * k32;
+      L.exec_flops[LCC_BF16X3][0] += live * k32;
       L.exec_flops[LCC_BF16X3][1] += whole * ((nk + 31) / 32 * 32);
       L.elems_written += (double)g.m * g.n;
     }

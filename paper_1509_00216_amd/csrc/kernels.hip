@@ -76,6 +76,15 @@ struct Mfma<1> {
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
+// MODE 2: FP32 operands staged as for MODE 1, split into bf16 hi + lo as they are read from LDS
+// and multiplied on v_mfma_f32_16x16x32_bf16 (hi*hi + hi*lo + lo*hi, FP32 accumulation);
+// accumulator layout as MODE 1.
+template <>
+struct Mfma<2> {
+  typedef float T;
+  typedef f4 Acc;
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 // ------------------------------------------------------------------------------------------
 // Packed-k operand staging.  A workgroup consumes its group's k-quads (SlotRec, four
@@ -652,22 +661,29 @@ struct KPitch {
 };
 
 // MFMAs of one staged chunk of the term-walk kernel (LDS tiles [k][m], [k][n]); ni, nj, arow,
-// bcol as for packed_chunk.
+// bcol as for packed_chunk.  A full chunk is walked in BK/4 steps where step s gives lane group
+// g = lane/16 the k index s + (BK/4) g: the four groups then read LDS rows BK/4 apart, which the
+// row pitch (r + 2 words for FP32) puts on disjoint banks.  A partial chunk (the last chunk of a
+// short term) takes k = 4 s + g instead, so that steps wholly past the term's end are skipped.
+// The sum over k is the same for any assignment that A and B share.
 template <int MODE, int BK, int TM, int TN, class TA_, class TB_>
 __device__ __forceinline__ void terms_chunk(const TA_& As, const TB_& Bs, int arow, int bcol, int kmax, int ni,
                                             int nj, typename Mfma<MODE>::Acc (&acc)[TM][TN]) {
   typedef typename Mfma<MODE>::T T;
   const int lane = threadIdx.x & 63;
+  // FP32 full chunk: row of step st = st + (BK/4) g; otherwise 4 st + g
+  const bool spread = MODE == 1 && kmax >= BK;
+  const int r0 = spread ? (BK / 4) * (lane >> 4) : (lane >> 4);
+  const int rs = spread ? 1 : 4;
 #pragma unroll
-  for (int kk = 0; kk < BK; kk += 4) {
-    if (kk < kmax) {
+  for (int st = 0; st < BK / 4; ++st) {
+    if (spread || 4 * st < kmax) {
+      const int row = r0 + rs * st;
       T a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-        a[i] = As[kk + (lane >> 4)][arow + i * 16];
+      for (int i = 0; i < TM; ++i) a[i] = As[row][arow + i * 16];
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        b[j] = Bs[kk + (lane >> 4)][bcol + j * 16];
+      for (int j = 0; j < TN; ++j) b[j] = Bs[row][bcol + j * 16];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -677,12 +693,74 @@ __device__ __forceinline__ void terms_chunk(const TA_& As, const TB_& Bs, int ar
   }
 }
 
+// hi = bf16(v), lo = bf16(v - hi) of the eight k values of a lane's row
+template <class TS>
+__device__ __forceinline__ void split8(const TS& S, int k0, int col, bf8& hi, bf8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = S[k0 + e][col];
+    const __bf16 h = (__bf16)v;
+    hi[e] = h;
+    lo[e] = (__bf16)(v - (float)h);
+  }
+}
+
+// BF16x3 MFMAs of one staged 32-k chunk of FP32 operands (LDS tiles [k][m], [k][n]): lane l takes
+// the eight k values 8 (l/16) .. 8 (l/16) + 7 of its row and column (rows 8 apart between lane
+// groups: disjoint banks), splits them into bf16 hi + lo and accumulates hi*hi + hi*lo + lo*hi with
+// v_mfma_f32_16x16x32_bf16 (the lo*lo term is below the representation error of the split).
+template <int TM, int TN, class TA_, class TB_>
+__device__ __forceinline__ void terms_chunk_bf16x3(const TA_& As, const TB_& Bs, int arow, int bcol, int ni, int nj,
+                                                   f4 (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  const int k0 = 8 * (lane >> 4);
+  // the operand with fewer sub-tiles is split once and held; the other is split one sub-tile
+  // at a time (fewer live registers)
+  if constexpr (TN <= TM) {
+    bf8 bh[TN], bl[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) split8(Bs, k0, bcol + j * 16, bh[j], bl[j]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      if (i < ni) {
+        bf8 ah, al;
+        split8(As, k0, arow + i * 16, ah, al);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if (j < nj) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+  } else {
+    bf8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) split8(As, k0, arow + i * 16, ah[i], al[i]);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      if (j < nj) {
+        bf8 bh, bl;
+        split8(Bs, k0, bcol + j * 16, bh, bl);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          if (i < ni) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+  }
+}
+
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(64 * WM * WN)
-gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
-                 const GemmTile* __restrict__ tiles, int n_tiles,
-                 Bases<typename Mfma<MODE>::T> bases, const Bases<typename Mfma<MODE>::T>* __restrict__ table,
-                 const int* __restrict__ active) {
+__device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
+                                                const GemmTile* __restrict__ tiles, int n_tiles,
+                                                Bases<typename Mfma<MODE>::T> bases,
+                                                const Bases<typename Mfma<MODE>::T>* __restrict__ table,
+                                                const int* __restrict__ active) {
   typedef typename Mfma<MODE>::T T;
   typedef typename Mfma<MODE>::Acc Acc;
   constexpr int BK = 128 / (int)sizeof(T);  // one 128-byte line of a row per chunk
@@ -759,7 +837,10 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
       LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, k0, term.k);
       LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, k0, term.k);
     }
-    terms_chunk<MODE, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
+    if constexpr (MODE == 2)
+      terms_chunk_bf16x3<TM, TN>(As, Bs, arow, bcol, ni, nj, acc);
+    else
+      terms_chunk<MODE, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
   }
 
   const gmut<T> C = global_mut(bt.get(g.c_base) + g.c_off);
@@ -778,113 +859,22 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
       }
 }
 
-// ------------------------------------------------------------------------------------------
-// Term-walk BF16x3 split-product GEMM on v_mfma_f32_16x16x32_bf16.  FP32 operands are split while
-// staged: hi = bf16(x), lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi with FP32
-// accumulation (the lo*lo term is below the representation error of the split).
-// Lane l holds A[l%16][8(l/16) + i], B[8(l/16) + i][l%16] (i = 0..7); accumulator element r
-// at row 4(l/16) + r, column l%16.  LDS holds A as [m][k] and B as [n][k] so that each
-// lane's eight k values are contiguous.
-// ------------------------------------------------------------------------------------------
-template <bool TA, bool TB, int BM, int BN, int WM, int WN>
+template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
+gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
+                  const GemmTile* __restrict__ tiles, int n_tiles, Bases<typename Mfma<MODE>::T> bases,
+                  const Bases<typename Mfma<MODE>::T>* __restrict__ table, const int* __restrict__ active) {
+  gemm_terms_body<MODE, TA, TB, BM, BN, WM, WN>(terms, groups, tiles, n_tiles, bases, table, active);
+}
+
+// The BF16x3 term walk: the split of each operand read into hi and lo needs registers; the bound
+// of four waves per SIMD keeps the kernel at that occupancy.
+template <bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(4)))
 gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
-                   const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
-                   const Bases<float>* __restrict__ table, const int* __restrict__ active) {
-  constexpr int BK = 32;
-  constexpr int KP = BK + 8;  // row pitch in bf16 elements (16-byte aligned rows)
-  constexpr int TM = BM / WM / 16;
-  constexpr int TN = BN / WN / 16;
-  constexpr int NT = 64 * WM * WN;
-  typedef ALoader<float, TA, BM, BK, NT> LA;
-  typedef BLoader<float, TB, BN, BK, NT> LB;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][KP];
-
-  __shared__ BaseTable<float> bt;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-
-  const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
-  const GemmGroup g = groups[tile.group];
-  const Bases<float>* row = nullptr;
-  if (table) {  // batched launch: per-problem operands, converged problems skipped
-    if (active && !active[g.problem]) return;
-    row = table + g.problem;
-  }
-  bt.stage(bases, row);
-  __syncthreads();
-  const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
-  const int row0 = tm * BM, col0 = tn * BN;
-  const int arow = wm * (BM / WM) + (lane & 15), bcol = wn * (BN / WN) + (lane & 15);
-
-  f4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-  float ra[LA::N], rb[LB::N];
-  int t = g.term_begin, k0 = 0;
-  GemmTerm term;
-  if (t < g.term_end) {
-    term = terms[t];
-    LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, 0, term.k);
-    LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, 0, term.k);
-  }
-  while (t < g.term_end) {
-    const float alpha = (float)term.alpha;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < LA::N; ++i) {
-      int mm, kk;
-      LA::coords(i, mm, kk);
-      const float v = alpha * ra[i];
-      const __bf16 h = (__bf16)v;
-      Ah[mm][kk] = h;
-      Al[mm][kk] = (__bf16)(v - (float)h);
-    }
-#pragma unroll
-    for (int i = 0; i < LB::N; ++i) {
-      int nn, kk;
-      LB::coords(i, nn, kk);
-      const float v = rb[i];
-      const __bf16 h = (__bf16)v;
-      Bh[nn][kk] = h;
-      Bl[nn][kk] = (__bf16)(v - (float)h);
-    }
-    __syncthreads();
-    k0 += BK;
-    if (k0 >= term.k) {
-      ++t;
-      k0 = 0;
-      if (t < g.term_end) term = terms[t];
-    }
-    if (t < g.term_end) {
-      LA::load(ra, bt.get(term.a_base) + term.a_off, term.lda, row0, g.m, k0, term.k);
-      LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, k0, term.k);
-    }
-    bf16x3_chunk<TM, TN>(Ah, Al, Bh, Bl, arow, bcol, acc);
-  }
-
-  const gmut<float> C = global_mut(bt.get(g.c_base) + g.c_off);
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gr = row0 + wm * (BM / WM) + i * 16 + 4 * (lane >> 4) + r;
-        const int gc = col0 + wn * (BN / WN) + j * 16 + (lane & 15);
-        if (gr < g.m && gc < g.n) {
-          const gmut<float> p = C + (int64_t)gr * g.ldc + gc;
-          *p = g.accumulate ? *p + acc[i][j][r] : acc[i][j][r];
-        }
-      }
+                         const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
+                         const Bases<float>* __restrict__ table, const int* __restrict__ active) {
+  gemm_terms_body<2, TA, TB, BM, BN, WM, WN>(terms, groups, tiles, n_tiles, bases, table, active);
 }
 
 // ------------------------------------------------------------------------------------------

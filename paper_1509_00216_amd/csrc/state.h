@@ -32,7 +32,7 @@ struct DevBuf {
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && hipFree(p) != hipSuccess) (void)hipGetLastError();  // leave no stale error behind
     p = nullptr;
     bytes = 0;
   }

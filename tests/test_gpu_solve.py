@@ -178,3 +178,23 @@ def test_batch_with_zero_rhs_member(chain, ctx):
     assert status == "LCC_OK"
     assert abs(infos[0]["hylleraas"] - chain["jstar"]) <= 1e-8
     assert infos[1]["iterations"] == 0 and float(xs[1].abs().max()) == 0.0
+
+
+def test_destroy_order_leaves_no_error():
+    """Handles may be destroyed in any order (a garbage collector may finalise a context before
+    the environments made on it); later work on a new context is unaffected."""
+    torch, lcc = need_gpu()
+    spec, mps = C.make("hubbard1d_k8_m64")
+    ctx = lcc.Context(0)
+    ham = ctx.create_hamiltonian(spec)
+    env = ctx.build_environments(ham, mps)
+    ctx.close()
+    env.close()
+    ham.close()
+    ctx2 = lcc.Context(0)
+    env2 = ctx2.build_environments(ctx2.create_hamiltonian(spec), mps)
+    x = to_dev(torch, env2.pack(M.random_two_site_vector(mps, 3)), torch.float64)
+    y = torch.empty_like(x)
+    env2.apply_heff(x, y, "fp64")
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
