@@ -111,6 +111,14 @@ typedef struct {
   double e_const;
   int32_t switch_bond;     /* bond from which two-operator channels are labelled by their
                               right partners; < 0 selects n_orb/2 + 1 */
+  const int32_t* site_order; /* n_orb or NULL (identity): chain position p holds orbital
+                              site_order[p], a permutation of 0..n_orb-1; h, eri, u_onsite and
+                              orb_class are indexed by orbital and mapped to chain order */
+  const int32_t* orb_class;  /* n_orb or NULL: 0 core, 1 active, 2 virtual (Theory section: the
+                              occupancy constraints of the three orbital sets) */
+  int32_t part;              /* 0: H; 1: H0, the terms that move no electron between the classes
+                              (partitioned-Hamiltonian equation, Delta n_ex = 0), e_const
+                              included; 2: U = H - H0.  1 and 2 need orb_class. */
 } lcc_ham_desc;
 
 lcc_status lcc_create_hamiltonian(lcc_context ctx, const lcc_ham_desc* desc, lcc_hamiltonian* out);

@@ -58,8 +58,35 @@ def apply_op(states: np.ndarray, amps: np.ndarray, p: int, dagger: bool):
     return st, amps[ok] * sign, ok
 
 
+def in_part(spec: dict, ops) -> bool:
+    """Theory section, partitioned Hamiltonian: with orbital classes (0 core, 1 active, 2
+    virtual) H0 keeps the operator strings that transfer no electron between the classes (in
+    every class as many creators as annihilators) and U = H - H0 the others.  spec['part']: 0
+    the whole H, 1 H0, 2 U."""
+    part = spec.get("part", 0)
+    if not part:
+        return True
+    bal = [0, 0, 0]
+    for p, dag in ops:
+        bal[int(spec["orb_class"][p // 2])] += 1 if dag else -1
+    keeps = bal == [0, 0, 0]
+    return keeps if part == 1 else not keeps
+
+
+def constant(spec: dict) -> float:
+    """The constant term: part of H and H0, not of U."""
+    return 0.0 if spec.get("part", 0) == 2 else float(spec.get("e_const", 0.0))
+
+
 def operator_strings(spec: dict):
-    """Yield (coefficient, [(spin_orbital, dagger), ...]) in written operator order."""
+    """Yield (coefficient, [(spin_orbital, dagger), ...]) in written operator order (only the
+    strings of the selected part of the Hamiltonian, see in_part)."""
+    for coef, ops in _all_operator_strings(spec):
+        if in_part(spec, ops):
+            yield coef, ops
+
+
+def _all_operator_strings(spec: dict):
     n = spec["n_orb"]
     h = spec["h"]
     for i in range(n):
@@ -104,10 +131,10 @@ def hamiltonian_matrix(spec: dict, basis: np.ndarray | None = None) -> sp.csr_ma
         rows.append(pos[valid])
         cols.append(idx[valid])
         vals.append(coef * amp[valid])
-    if spec.get("e_const", 0.0) != 0.0:
+    if constant(spec) != 0.0:
         rows.append(col_index)
         cols.append(col_index)
-        vals.append(np.full(dim, spec["e_const"]))
+        vals.append(np.full(dim, constant(spec)))
     if not rows:
         return sp.csr_matrix((dim, dim))
     r = np.concatenate(rows)

@@ -106,8 +106,8 @@ def build_mpo(spec: dict) -> dict:
                 put(j, before, "H", coef * mat, True)
             else:
                 put(j, before, before + tuple(here), mat, False)
-    if spec.get("e_const", 0.0) != 0.0:
-        put(0, (), "H", spec["e_const"] * ID, True)
+    if fock.constant(spec) != 0.0:
+        put(0, (), "H", fock.constant(spec) * ID, True)
     # channel sets per bond
     chans = [set() for _ in range(K + 1)]
     chans[0].add(())
@@ -232,8 +232,8 @@ def build_mpo_twosided(spec: dict, switch: int | None = None) -> dict:
                 old = fixed[j].get((a, b))
                 assert old is None or np.array_equal(old, m), "inconsistent label transition"
                 fixed[j][(a, b)] = m
-    if spec.get("e_const", 0.0) != 0.0:
-        coef_entries[0][("I", "H")] = coef_entries[0].get(("I", "H"), 0.0) + spec["e_const"] * ID
+    if fock.constant(spec) != 0.0:
+        coef_entries[0][("I", "H")] = coef_entries[0].get(("I", "H"), 0.0) + fock.constant(spec) * ID
         seen("I", 0, 0)
         seen("H", 1, K)
     # pass-through of every channel inside its range of bonds

@@ -157,11 +157,46 @@ lcc_status lcc_create_hamiltonian(lcc_context ctx, const lcc_ham_desc* d, lcc_ha
     hd.K = d->n_orb;
     hd.N = d->n_elec;
     hd.two_sz = d->two_sz;
-    hd.h.assign(d->h, d->h + K * K);
-    if (d->eri) hd.eri.assign(d->eri, d->eri + K * K * K * K);
-    if (d->u_onsite) hd.u.assign(d->u_onsite, d->u_onsite + K);
+    // chain position p holds orbital o[p]: every index of h, eri, u and orb_class is mapped
+    std::vector<size_t> o(K);
+    for (size_t p = 0; p < K; ++p) o[p] = p;
+    if (d->site_order) {
+      std::vector<char> seen(K, 0);
+      for (size_t p = 0; p < K; ++p) {
+        const int v = d->site_order[p];
+        if (v < 0 || v >= (int)K || seen[v]) throw Error{LCC_ERR_ARG, "site_order must be a permutation of 0..n_orb-1"};
+        seen[v] = 1;
+        o[p] = (size_t)v;
+      }
+    }
+    hd.h.resize(K * K);
+    for (size_t p = 0; p < K; ++p)
+      for (size_t q = 0; q < K; ++q) hd.h[p * K + q] = d->h[o[p] * K + o[q]];
+    if (d->eri) {
+      hd.eri.resize(K * K * K * K);
+      for (size_t p = 0; p < K; ++p)
+        for (size_t q = 0; q < K; ++q)
+          for (size_t r = 0; r < K; ++r)
+            for (size_t t = 0; t < K; ++t)
+              hd.eri[((p * K + q) * K + r) * K + t] = d->eri[((o[p] * K + o[q]) * K + o[r]) * K + o[t]];
+    }
+    if (d->u_onsite) {
+      hd.u.resize(K);
+      for (size_t p = 0; p < K; ++p) hd.u[p] = d->u_onsite[o[p]];
+    }
     hd.e_const = d->e_const;
     hd.switch_bond = d->switch_bond;
+    if (d->part < 0 || d->part > 2) throw Error{LCC_ERR_ARG, "part must be 0 (H), 1 (H0) or 2 (U)"};
+    if (d->part != 0 && !d->orb_class) throw Error{LCC_ERR_ARG, "a partition needs orb_class"};
+    hd.part = d->part;
+    if (d->orb_class) {
+      hd.orb_class.resize(K);
+      for (size_t p = 0; p < K; ++p) {
+        const int c = d->orb_class[o[p]];
+        if (c < 0 || c > 2) throw Error{LCC_ERR_ARG, "orb_class entries must be 0 (core), 1 (active) or 2 (virtual)"};
+        hd.orb_class[p] = c;
+      }
+    }
     for (double v : hd.h)
       if (!std::isfinite(v)) throw Error{LCC_ERR_NAN, "non-finite h"};
     for (double v : hd.eri)

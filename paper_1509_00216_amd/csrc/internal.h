@@ -44,9 +44,11 @@ struct Mpo {
 };
 struct HamDesc {
   int K, N, two_sz;
-  std::vector<double> h, eri, u;
+  std::vector<double> h, eri, u;  // in chain order
   double e_const;
   int switch_bond;
+  std::vector<int> orb_class;     // chain order; empty = no partition
+  int part = 0;                   // 0: H, 1: H0 (class-number-preserving terms), 2: U = H - H0
 };
 // Builds the MPO; returns an empty string on success or an error message.
 std::string build_mpo(const HamDesc& d, Mpo& out);

@@ -150,8 +150,18 @@ std::string build_mpo(const HamDesc& d, Mpo& out) {
   if (K < 2 || K > 64) return "n_orb must be in [2, 64]";
   // ---- operator strings, site-sorted with permutation sign
   std::vector<Term> terms;
+  // Partition (Theory section, partitioned Hamiltonian): H0 keeps the terms that move no
+  // electron between the orbital classes (every class has as many creators as annihilators),
+  // U the others.
+  auto in_part = [&](std::initializer_list<uint16_t> ops) {
+    if (d.part == 0) return true;
+    int bal[3] = {0, 0, 0};
+    for (uint16_t o : ops) bal[d.orb_class[op_site(o)]] += op_dag(o) ? 1 : -1;
+    const bool keeps = bal[0] == 0 && bal[1] == 0 && bal[2] == 0;
+    return d.part == 1 ? keeps : !keeps;
+  };
   auto push = [&](double coef, std::initializer_list<uint16_t> ops) {
-    if (coef == 0.0) return;
+    if (coef == 0.0 || !in_part(ops)) return;
     Term t;
     t.coef = coef;
     t.n = (int)ops.size();
@@ -238,7 +248,8 @@ std::string build_mpo(const HamDesc& d, Mpo& out) {
       touch(lab.at(t, b0), b0, b1);
     }
   }
-  if (d.e_const != 0.0) {
+  const double e_const = d.part == 2 ? 0.0 : d.e_const;  // the constant belongs to H0
+  if (e_const != 0.0) {
     touch(kLabelI, 0, 0);
     touch(kLabelH, 1, K);
   }
@@ -323,9 +334,9 @@ std::string build_mpo(const HamDesc& d, Mpo& out) {
     }
   }
   if (!err.empty()) return err;
-  if (d.e_const != 0.0) {
+  if (e_const != 0.0) {
     MpoEntry& w = entry(0, index[0].at(kLabelI), index[1].at(kLabelH));
-    for (int q = 0; q < 4; ++q) w.m[q * 4 + q] += d.e_const;
+    for (int q = 0; q < 4; ++q) w.m[q * 4 + q] += e_const;
   }
   // pass-through of every channel across the sites inside its range
   for (const auto& kv : range) {

@@ -42,7 +42,8 @@ class LccError(RuntimeError):
 class HamDesc(C.Structure):
     _fields_ = [("n_orb", C.c_int32), ("n_elec", C.c_int32), ("two_sz", C.c_int32),
                 ("h", C.POINTER(C.c_double)), ("eri", C.POINTER(C.c_double)),
-                ("u_onsite", C.POINTER(C.c_double)), ("e_const", C.c_double), ("switch_bond", C.c_int32)]
+                ("u_onsite", C.POINTER(C.c_double)), ("e_const", C.c_double), ("switch_bond", C.c_int32),
+                ("site_order", C.POINTER(C.c_int32)), ("orb_class", C.POINTER(C.c_int32)), ("part", C.c_int32)]
 
 
 class Sector(C.Structure):
@@ -290,13 +291,19 @@ class Hamiltonian:
         return wi, wo, m
 
 
-def create_hamiltonian(ctx: Context | None, spec: dict, switch_bond: int = -1) -> Hamiltonian:
+def create_hamiltonian(ctx: Context | None, spec: dict, switch_bond: int = -1, site_order=None) -> Hamiltonian:
+    """spec: n_orb, n_elec, two_sz, h, eri or None, u or None, e_const, and optionally orb_class
+    (0 core, 1 active, 2 virtual per orbital) with part (0 H, 1 H0, 2 U)."""
     n = spec["n_orb"]
     h = np.ascontiguousarray(spec["h"], dtype=np.float64)
     eri = None if spec.get("eri") is None else np.ascontiguousarray(spec["eri"], dtype=np.float64)
     u = None if spec.get("u") is None else np.ascontiguousarray(spec["u"], dtype=np.float64)
+    order = None if site_order is None else np.ascontiguousarray(site_order, dtype=np.int32)
+    cls = None if spec.get("orb_class") is None else np.ascontiguousarray(spec["orb_class"], dtype=np.int32)
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
     d = HamDesc(n, spec["n_elec"], spec["two_sz"], _dptr(h), _dptr(eri) if eri is not None else None,
-                _dptr(u) if u is not None else None, float(spec.get("e_const", 0.0)), switch_bond)
+                _dptr(u) if u is not None else None, float(spec.get("e_const", 0.0)), switch_bond,
+                ip(order), ip(cls), int(spec.get("part", 0)))
     out = C.c_void_p()
     ch = ctx.handle if ctx is not None else None
     _check(library().lcc_create_hamiltonian(ch, C.byref(d), C.byref(out)), ch)

@@ -190,3 +190,28 @@ def random_orthogonal(n: int, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     q, r = np.linalg.qr(rng.standard_normal((n, n)))
     return q * np.sign(np.diag(r))
+
+
+def with_partition(spec: dict, orb_class, part: int) -> dict:
+    """The same Hamiltonian with orbital classes (0 core, 1 active, 2 virtual per orbital) and a
+    selected part: 0 the whole H, 1 H0, 2 U (see the partitioned-Hamiltonian equation)."""
+    out = dict(spec)
+    out["orb_class"] = np.ascontiguousarray(orb_class, dtype=np.int32)
+    out["part"] = int(part)
+    out["name"] = spec["name"] + ("", "_H0", "_U")[int(part)]
+    return out
+
+
+def reorder(spec: dict, order) -> dict:
+    """The Hamiltonian with orbital order[p] placed at chain position p."""
+    o = np.asarray(order)
+    out = dict(spec)
+    out["h"] = np.ascontiguousarray(spec["h"][np.ix_(o, o)])
+    if spec.get("eri") is not None:
+        out["eri"] = np.ascontiguousarray(spec["eri"][np.ix_(o, o, o, o)])
+    if spec.get("u") is not None:
+        out["u"] = np.ascontiguousarray(spec["u"][o])
+    if spec.get("orb_class") is not None:
+        out["orb_class"] = np.ascontiguousarray(spec["orb_class"][o])
+    out["name"] = spec["name"] + "_reordered"
+    return out
