@@ -68,7 +68,7 @@ def kernel_name(precision: str, launch: dict) -> str:
     tb = "true" if launch["b_colmajor"] else "false"
     bm, bn = launch["tile"]
     waves = {(64, 64): (2, 2), (16, 64): (1, 4), (64, 16): (4, 1), (32, 32): (2, 2), (128, 64): (2, 2),
-             (64, 128): (2, 2), (32, 64): (2, 2), (64, 32): (2, 2)}[(bm, bn)]
+             (64, 128): (2, 2), (32, 64): (2, 2), (64, 32): (2, 2), (128, 128): (4, 2)}[(bm, bn)]
     kind = "packed" if launch.get("packed") else "terms"
     if precision == "bf16x3":
         return f"gemm_bf16x3_{kind}_kernel<{ta}, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
@@ -90,6 +90,58 @@ def measured_traffic(kname: str, tiles: int, workload: str):
         return None
     ent = rec.get("kernels", {}).get(f"{kname} x{tiles}")
     return None if ent is None else ent.get("traffic_bytes")
+
+
+def _counter_rows(root: str, counter: str) -> list:
+    """(kernel name, workgroups, value) of every dispatch in the rocprofv3 counter CSVs under root."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                wg = int(r.get("Workgroup_Size") or 1)
+                rows.append((r["Kernel_Name"], int(r["Grid_Size"]) // max(wg, 1), float(r["Counter_Value"])))
+    return rows
+
+
+def write_pmc_summary(fetch_dir: str, write_dir: str, workload: str, commands: list) -> dict:
+    """profiles/pmc_traffic_<workload>.txt from two rocprofv3 --pmc runs of `--apply-only`
+    (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch): per kernel and workgroup count, the mean of
+    each counter and the HBM bytes they stand for, scaled by what the same counter reads for the
+    run's device copy of known size (256 MiB read and written)."""
+    import re
+    copy_bytes = 256.0 * 1024 * 1024
+    out = {"workload": workload, "source_sha1": source_digest(), "commands": commands, "kernels": {}}
+    means = {}
+    for key, root, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        per = {}
+        copy = 0.0
+        for name, wgs, val in _counter_rows(root, counter):
+            if "copy" in name.lower():
+                copy = max(copy, val)
+                continue
+            m = re.search(r"(gemm_\w+_kernel<[^>]*>|reduce_kernel<\w+>)", name)
+            if not m:
+                continue
+            per.setdefault(f"{m.group(1)} x{wgs}", []).append(val)
+        if copy <= 0:
+            raise RuntimeError(f"no copy dispatch in {root}: the calibration needs it")
+        out.setdefault("copy_kib", {})[key] = copy
+        out.setdefault("scale", {})[key] = copy_bytes / (copy * 1024.0)
+        means[key] = {k: (len(v), sum(v) / len(v)) for k, v in per.items()}
+    for k in sorted(set(means["fetch"]) & set(means["write"])):
+        n, f = means["fetch"][k]
+        _, w = means["write"][k]
+        out["kernels"][k] = {"dispatches": n, "fetch_kib": f, "write_kib": w,
+                             "traffic_bytes": f * 1024.0 * out["scale"]["fetch"] + w * 1024.0 * out["scale"]["write"]}
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.txt")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    return out
 
 
 def cpu_baseline_worker(workload: str, target_s: float) -> None:
@@ -406,9 +458,20 @@ def main():
                     help="skip the extra keys (3-band M=2000 cluster; 64 batched problems)")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/pmc_traffic_<workload>.txt from the rocprofv3 counter output of two "
+                         "--apply-only runs (FETCH_SIZE, WRITE_SIZE); no GPU needed")
     args = ap.parse_args()
     if args.cpu_baseline_worker:
         return cpu_baseline_worker(args.workload, args.cpu_baseline_seconds)
+    if args.pmc_summary:
+        cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 150 rocprofv3 --pmc {c} --output-format csv -d "
+               "<out>/{d} -o apply -- python3 $R/bench.py --workload %s --apply-only 3 --apply-precision fp32"
+               % args.workload)
+        rec = write_pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload,
+                                [cmd.format(c="FETCH_SIZE", d="fetch"), cmd.format(c="WRITE_SIZE", d="write")])
+        print(json.dumps({"mode": "pmc-summary", "kernels": len(rec["kernels"]), "scale": rec["scale"]}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)

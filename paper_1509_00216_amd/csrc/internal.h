@@ -122,10 +122,11 @@ struct Bases {
   T* p[NUM_BASES];
 };
 
-// Tile shapes of the grouped GEMM: output rows x cols per workgroup of four waves.
-constexpr int kNumTileShapes = 8;
-constexpr int kTileShapes[kNumTileShapes][2] = {{64, 64}, {16, 64}, {64, 16}, {32, 32},
-                                                {128, 64}, {64, 128}, {32, 64}, {64, 32}};
+// Tile shapes of the grouped GEMM: output rows x cols per workgroup (four waves; eight for
+// 128 x 128).
+constexpr int kNumTileShapes = 9;
+constexpr int kTileShapes[kNumTileShapes][2] = {{64, 64}, {16, 64}, {64, 16}, {32, 32}, {128, 64},
+                                                {64, 128}, {32, 64}, {64, 32}, {128, 128}};
 enum TileShape { TILE_64x64 = 0, TILE_16x64 = 1 };
 
 // Launchers (kernels.hip).  All asynchronous on `stream`.

@@ -933,6 +933,7 @@ static hipError_t launch_bf_shape(const GemmDesc& d, const Bases<float>& b, hipS
     case 5: return FN<__VA_ARGS__ 64, 128, 2, 2>(d, b, stream, table, active);  \
     case 6: return FN<__VA_ARGS__ 32, 64, 2, 2>(d, b, stream, table, active);   \
     case 7: return FN<__VA_ARGS__ 64, 32, 2, 2>(d, b, stream, table, active);   \
+    case 8: return FN<__VA_ARGS__ 128, 128, 4, 2>(d, b, stream, table, active); \
     default: return hipErrorInvalidValue;                                  \
   }
 

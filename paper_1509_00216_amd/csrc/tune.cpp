@@ -129,8 +129,12 @@ double choose_kernels(Env& env, int precision, const void* x, void* y, int reps)
 
 }  // namespace
 
+// Bumped whenever the planner or the kernel set changes what a cached entry means.
+constexpr int64_t kPlannerVersion = 2;
+
 uint64_t histogram_signature(const Env& env) {
   uint64_t h = 1469598103934665603ull;
+  fnv(h, kPlannerVersion);
   fnv(h, env.D_mid);
   fnv(h, env.ctx->t_budget_elems);
   for (const Bond* b : {&env.bl, &env.br}) {
