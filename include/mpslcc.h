@@ -351,13 +351,15 @@ lcc_status lcc_solve_local_lcc(lcc_env env, const lcc_solve_opts* opts, const do
 
 /* ---------------------------------------------------------------------------------------
  * Sweep (Implementation section: one local problem at a time, sweeping over the sites).
- * A left-to-right sweep of two-site blocks starting at `first_site`: right environments of
- * every bond are built once; after each local solve the two-site tensor is split by an SVD per
- * middle-bond sector (a blocked one-sided Jacobi SVD on the device), the m_max largest singular values over all sectors are kept
- * (ties: sector (N, 2Sz) ascending, then index), the left factor becomes the new
- * left-canonical site tensor, the left environment is extended by it on the device, and
- * S V^T times the next site's right-canonical tensor becomes the initial guess of the next
- * local problem.
+ * Two-site blocks starting at `first_site`, moving right (advance) or left (retreat): the
+ * environments of every bond are kept.  After each local solve the two-site tensor is split by
+ * an SVD per middle-bond sector (a blocked one-sided Jacobi SVD on the device), the m_max
+ * largest singular values over all sectors are kept (ties: sector (N, 2Sz) ascending, then
+ * index), except those below 1e-10 times the largest, which count as zero.  Moving right, the left factor becomes the new left-canonical site tensor, the left
+ * environment is extended by it on the device, and S V^T times the next site's right-canonical
+ * tensor becomes the initial guess of the next local problem; moving left, the right factor
+ * becomes the right-canonical tensor of the block's right site and the previous site's
+ * left-canonical tensor times U S the next guess.
  * ------------------------------------------------------------------------------------- */
 typedef struct lcc_sweep_s* lcc_sweep;
 typedef struct {
@@ -377,15 +379,48 @@ lcc_status lcc_sweep_create(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_
                             lcc_sweep* out);
 void lcc_sweep_destroy(lcc_sweep sweep);
 /* Environment of the current block (layout, apply, solve).  Borrowed: valid until the next
- * lcc_sweep_advance; lcc_env_destroy on it is a no-op. */
+ * lcc_sweep_advance or lcc_sweep_retreat; lcc_env_destroy on it is a no-op. */
 lcc_status lcc_sweep_env(lcc_sweep sweep, lcc_env* out);
 /* Copy the initial guess of the current block into x_dev (zeros before the first advance). */
 lcc_status lcc_sweep_guess(lcc_sweep sweep, double* x_dev);
 /* Split the solved tensor x_dev (current block's layout), truncate to m_max, move one site
  * to the right.  Fails with LCC_ERR_STATE at the last block.  Synchronous. */
 lcc_status lcc_sweep_advance(lcc_sweep sweep, const double* x_dev, int32_t m_max, lcc_sweep_info* info);
+/* Split as lcc_sweep_advance, keep the right factor, move one site to the left.  Fails with
+ * LCC_ERR_STATE at the first block.  Synchronous. */
+lcc_status lcc_sweep_retreat(lcc_sweep sweep, const double* x_dev, int32_t m_max, lcc_sweep_info* info);
+/* Left site of the current block. */
+lcc_status lcc_sweep_position(lcc_sweep sweep, int32_t* site);
 /* Singular values of the last split, all sectors, descending: call with out == NULL for *count. */
 lcc_status lcc_sweep_singular_values(lcc_sweep sweep, int32_t* count, double* out);
+
+/* First-order problems on a sweep (Theory section: the first-order equation of the perturbation
+ * series, solved by minimising the Hylleraas functional one block at a time; the projector
+ * approximation changes only the right-hand side).  The sweep's MPS is Phi1, built on H0 (the
+ * Hamiltonian of lcc_sweep_create, e.g. part = 1 of lcc_ham_desc); `ref` is Phi0 (canonical
+ * around any block, norm 1), `op` the operator O of the right-hand side -Q O Phi0 with
+ * Q = 1 - |Phi0><Phi0| (O = U for the first-order equation, O = H for the projector
+ * approximation), `u` (or NULL) the perturbation U for the third-order energy.  Environments
+ * between Phi1 and Phi0 (transition-element figure) for O and for the identity, and of U on
+ * Phi1, are kept for every bond and follow the sweep.  The handles must outlive the sweep.
+ * Errors: LCC_ERR_QN if the sector or orbital count differs, LCC_ERR_STATE if nothing is
+ * attached. */
+lcc_status lcc_sweep_attach_reference(lcc_sweep sweep, lcc_hamiltonian op, lcc_hamiltonian u, const lcc_mps_desc* ref);
+/* At the current block, with P its environment basis and v = P^T Phi0: b = -(P^T O Phi0 - c v)
+ * into b_dev, v / |v| into v_dev (device arrays of the block's layout, n_elements each) and |v|
+ * into *v_norm.  With c = <Phi0|O|Phi0>, b is -P^T Q O Phi0; solving (P^T H0 P - E0) x = b with
+ * x orthogonal to v (lcc_solve_local_lcc with v_dev; the block's basis follows Phi1 and need
+ * not hold Phi0, and when |v| is at rounding level the constraint is void and v_dev is not
+ * used) gives the block's Phi1, and the Hylleraas value of the solve is the second-order energy
+ * <Phi0|O|Phi1>.  Synchronous. */
+lcc_status lcc_sweep_first_order_rhs(lcc_sweep sweep, double c, double* b_dev, double* v_dev, double* v_norm);
+/* x^T (P^T U P) x and x^T x for the block's tensor x_dev: with E1 = <Phi0|U|Phi0> the
+ * third-order energy of the Wigner 2n+1 expressions is xux - E1 xx.  Synchronous. */
+lcc_status lcc_sweep_u_expectation(lcc_sweep sweep, const double* x_dev, double* xux, double* xx);
+/* <Phi|H|Phi> of an MPS canonical around the block (site, site + 1) (E0 = <Phi0|H0|Phi0>,
+ * c = <Phi0|O|Phi0> of the first-order right-hand side).  Synchronous. */
+lcc_status lcc_mps_expectation(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t site,
+                               double* value);
 
 /* ---------------------------------------------------------------------------------------
  * Batched local solves (many independent two-site problems, e.g. the sites of several sweeps

@@ -13,6 +13,8 @@ from __future__ import annotations
 
 import numpy as np
 
+SV_CUT = 1e-10  # singular values below SV_CUT * the largest are treated as zero
+
 from . import blocksparse as BS
 from . import solve as OS
 from .mpo import LOCAL_QN
@@ -57,8 +59,11 @@ def split(x: dict, mps: dict, m_max: int):
         cand.extend((float(v), qi, i, q) for i, v in enumerate(s))
     cand.sort(key=lambda c: (-c[0], c[1], c[2]))
     keep = {}
+    # singular values at the rounding level of the largest are zeros of the exact tensor: their
+    # vectors are not determined, so they are never kept (reading: relative cut 1e-10)
+    cut = SV_CUT * (cand[0][0] if cand else 0.0)
     for c in cand[:m_max]:
-        if c[0] > 0.0:
+        if c[0] > cut:
             keep[c[3]] = max(keep.get(c[3], 0), c[2] + 1)
     new_bond = [(q[0], q[1], keep[q]) for q in secs if q in keep]
     new_index = {q: i for i, (q0, q1, _) in enumerate(new_bond) for q in [(q0, q1)]}

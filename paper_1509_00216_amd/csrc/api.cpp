@@ -560,6 +560,76 @@ lcc_status lcc_sweep_advance(lcc_sweep sweep, const double* x, int32_t m_max, lc
   });
 }
 
+lcc_status lcc_sweep_retreat(lcc_sweep sweep, const double* x, int32_t m_max, lcc_sweep_info* info) {
+  if (!sweep || !x) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_retreat(*sweep->s, x, m_max, info);
+    sweep->view.e = sweep_env(*sweep->s);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_position(lcc_sweep sweep, int32_t* site) {
+  if (!sweep || !site) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  *site = sweep_site(*sweep->s);
+  return LCC_OK;
+}
+
+lcc_status lcc_sweep_attach_reference(lcc_sweep sweep, lcc_hamiltonian op, lcc_hamiltonian u, const lcc_mps_desc* ref) {
+  if (!sweep || !op || !ref) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_attach_reference(*sweep->s, op->h, u ? &u->h : nullptr, *ref);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_first_order_rhs(lcc_sweep sweep, double c, double* b, double* v, double* v_norm) {
+  if (!sweep || !b || !v || !v_norm) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  if (!std::isfinite(c)) return fail(nullptr, LCC_ERR_ARG, "c must be finite");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_first_order_rhs(*sweep->s, c, b, v, v_norm);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_u_expectation(lcc_sweep sweep, const double* x, double* xux, double* xx) {
+  if (!sweep || !x || !xux || !xx) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_u_expectation(*sweep->s, x, xux, xx);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_mps_expectation(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t site,
+                               double* value) {
+  if (!ham || !mps || !value) return fail(ctx, LCC_ERR_ARG, "NULL argument");
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    // <Phi| H |Phi> as the transition operator of Phi with itself at the block (site, site + 1),
+    // applied to Phi's own two-site tensor there
+    std::unique_ptr<Env> e(build_transition_env(&ctx->c, ham->h, *mps, *mps, site));
+    DevBuf y;
+    y.alloc(sizeof(double) * std::max<int64_t>(e->n_elements, 1));
+    apply_heff(*e, LCC_FP64, e->x0.p, y.p);
+    Context* c = &ctx->c;
+    hipStream_t st = c->stream;
+    check_hip(launch_dot_f64(e->x0.as<double>(), y.as<double>(), e->n_elements, c->dot_partial.as<double>(),
+                             c->dot_out.as<double>(), st), "dot");
+    check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+    check_hip(hipStreamSynchronize(st), "expectation");
+    *value = c->host_scalar[0];
+    return LCC_OK;
+  });
+}
+
 lcc_status lcc_sweep_singular_values(lcc_sweep sweep, int32_t* count, double* out) {
   if (!sweep || !count) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
   const std::vector<double>& v = sweep_singular_values(*sweep->s);

@@ -583,7 +583,6 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int
   return make_env(ctx, mpo, site, mps.bonds[site], mps.bonds[site + 2], L, R);
 }
 
-namespace {
 // The MPO of the identity operator: one channel on every bond, the identity on every site.
 Mpo identity_mpo(int K) {
   Mpo m;
@@ -600,7 +599,6 @@ Mpo identity_mpo(int K) {
   }
   return m;
 }
-}  // namespace
 
 // Transition operator <bra| H |ket> with the bra's two-site block (site, site+1) cut out: left
 // and right environments between the two MPS (transition-element figure), then the same
@@ -633,28 +631,36 @@ Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_de
   for (int j = K - 1; j >= site + 2; --j) R = right_step(R, bra, ket, j, mpo, st);
   std::unique_ptr<Env> env(make_env(ctx, mpo, site, bra.bonds[site], bra.bonds[site + 2], ket.bonds[site],
                                     ket.bonds[site + 2], L, R, true));
-  // the ket's own two-site tensor at the block: x0[a,s1,s2,b] = sum_c A_site^{s1}[a,c] A_{site+1}^{s2}[c,b]
+  build_ket_tensor(*env, ket, ket, st);
+  return env.release();
+}
+
+// The ket's own two-site tensor at the block of a transition operator (input layout):
+// x0[a,s1,s2,b] = sum_c A_site^{s1}[a,c] A_{site+1}^{s2}[c,b], with the two site tensors taken from
+// t1 (site) and t2 (site + 1).
+void build_ket_tensor(Env& E, const DeviceMps& t1, const DeviceMps& t2, hipStream_t st) {
+  const int site = E.site;
   std::map<std::pair<int, int>, const SiteBlock*> A1, A2;
-  for (const SiteBlock& b : ket.sites[site]) A1[{b.l, b.s}] = &b;
-  for (const SiteBlock& b : ket.sites[site + 1]) A2[{b.l, b.s}] = &b;
+  for (const SiteBlock& b : t1.sites[site]) A1[{b.l, b.s}] = &b;
+  for (const SiteBlock& b : t2.sites[site + 1]) A2[{b.l, b.s}] = &b;
   GemmBuilder g;
-  for (const lcc_block_entry& blk : env->layout_in) {
+  for (const lcc_block_entry& blk : E.layout_in) {
     auto i1 = A1.find({blk.left, blk.s1});
     if (i1 == A1.end()) continue;
     auto i2 = A2.find({i1->second->r, blk.s2});
     if (i2 == A2.end() || i2->second->r != blk.right) continue;
     g.group(BASE_X, blk.offset, blk.ld, blk.rows, blk.cols, false);
-    g.term(BASE_MPS, i1->second->off, i1->second->cols, BASE_MPS, i2->second->off, i2->second->cols,
+    g.term(BASE_MPS, i1->second->off, i1->second->cols, BASE_ENV, i2->second->off, i2->second->cols,
            i1->second->cols, 1.0);
   }
-  env->x0.alloc(sizeof(double) * std::max<int64_t>(env->n_in, 1));
-  check_hip(launch_fill_f64(env->x0.as<double>(), env->n_in, 0.0, st), "zero ket tensor");
+  E.x0.alloc(sizeof(double) * std::max<int64_t>(E.n_in, 1));
+  check_hip(launch_fill_f64(E.x0.as<double>(), E.n_in, 0.0, st), "zero ket tensor");
   Bases<double> b{};
-  b.p[BASE_MPS] = ket.data.as<double>();
-  b.p[BASE_X] = env->x0.as<double>();
+  b.p[BASE_MPS] = t1.data.as<double>();
+  b.p[BASE_ENV] = t2.data.as<double>();
+  b.p[BASE_X] = E.x0.as<double>();
   run_gemm64(finalize(g, false, false, st), b, st);
   check_hip(hipStreamSynchronize(st), "ket tensor");
-  return env.release();
 }
 
 // The contraction plan of an environment for given planner parameters: channel chunks and

@@ -253,6 +253,9 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bra_l, const B
               const Bond& ket_r, const Environment& L, const Environment& R, bool transition);
 Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& bra, const lcc_mps_desc& ket,
                           int site);
+// x0 of a transition operator from the ket's site tensors (site from t1, site + 1 from t2)
+void build_ket_tensor(Env& env, const DeviceMps& t1, const DeviceMps& t2, hipStream_t st);
+Mpo identity_mpo(int K);
 
 // env.cpp
 Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);
@@ -295,8 +298,13 @@ Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md
 void sweep_destroy(Sweep* s);
 Env* sweep_env(Sweep& s);
 void sweep_advance(Sweep& s, const double* x, int m_max, lcc_sweep_info* info);
+void sweep_retreat(Sweep& s, const double* x, int m_max, lcc_sweep_info* info);
 void sweep_copy_guess(Sweep& s, double* x);
 const std::vector<double>& sweep_singular_values(Sweep& s);
+int sweep_site(const Sweep& s);
+void sweep_attach_reference(Sweep& s, const Hamiltonian& op, const Hamiltonian* u, const lcc_mps_desc& ref);
+void sweep_first_order_rhs(Sweep& s, double c, double* b, double* v, double* v_norm);
+void sweep_u_expectation(Sweep& s, const double* x, double* xux, double* xx);
 // solver.cpp
 lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, double e0, const double* v,
                        double* x, lcc_solve_info* info);

@@ -63,6 +63,7 @@ struct SvdSlot {  // one workgroup of a round: job and pair index in the round-r
 constexpr int kSvdThreads = 1024;
 constexpr int kSvdMaxSweeps = 60;
 constexpr double kSvdTol = 1e-14;  // |w_i . w_j| <= tol ||w_i|| ||w_j|| counts as orthogonal
+constexpr double kSvCut = 1e-10;  // singular values below kSvCut * the largest count as zero
 constexpr int kSvdMaxW = 8;        // columns per block (a pair of blocks: at most 16 columns)
 constexpr int kSvdLdsCols = 120 * 1024 / (int)sizeof(double);  // LDS budget for a pair's columns, elements
 constexpr int kSvdInner = 1;       // Jacobi sweeps per visit of a block pair (more when it is the whole matrix)
@@ -255,70 +256,124 @@ svd_finalize_kernel(const SvdJob* __restrict__ jobs, double* __restrict__ work, 
 
 }  // namespace
 
+// Environments of one operator between the sweep's MPS (the bra) and a ket: the reference MPS
+// of a first-order problem (transition families) or the sweep's own MPS.
+struct Family {
+  Mpo own;                        // the identity operator of the overlap family
+  const Mpo* mpo = nullptr;
+  bool transition = false;
+  std::vector<Environment> L, R;  // L[j], R[j]: environments at MPS bond j
+};
+
 struct Sweep {
   Context* ctx = nullptr;
-  const Hamiltonian* ham = nullptr;
-  DeviceMps mps;
-  std::vector<Environment> R;  // R[j]: right environment at MPS bond j (j >= first + 2)
-  Environment L;
-  Bond bl;  // current left bond of the block
+  int K = 0, N = 0, two_sz = 0;
+  std::vector<Bond> bonds;     // current bonds of the MPS
+  std::vector<DeviceMps> t;    // site tensors, one buffer each; t[site], t[site+1] are the block's
+  Family h;                    // the operator of the local problem
   int site = 0, first = 0;
   std::unique_ptr<Env> env;
   DevBuf guess;      // initial guess of the current local problem (n_elements), valid if have_guess
   bool have_guess = false;
   std::vector<double> last_sv;  // singular values of the last split, descending
+  // first-order problems: the reference MPS and the operator O of the right-hand side (transition
+  // families), the overlap with the reference, and the perturbation U on the sweep's own MPS
+  bool have_ref = false;
+  DeviceMps ref;
+  Family op, ov, u;
+  bool have_u = false;
+  std::unique_ptr<Env> env_op, env_ov, env_u;
 };
 
-Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int first) {
-  hipStream_t st = ctx->stream;
-  const Mpo& mpo = ham.mpo;
-  const int K = mpo.K;
-  if (md.n_sites != K) throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
-  if (first < 0 || first + 1 >= K) throw Error{LCC_ERR_ARG, "first two-site block must satisfy 0 <= site < K-1"};
-  std::unique_ptr<Sweep> S(new Sweep());
-  S->ctx = ctx;
-  S->ham = &ham;
-  S->first = S->site = first;
-  load_mps(md, ham.desc.N, ham.desc.two_sz, st, S->mps);
-  S->L = unit_env(st);
-  for (int j = 0; j < first; ++j) S->L = left_step(S->L, S->mps, j, mpo, st);
-  S->R.resize(K + 1);
-  S->R[K] = unit_env(st);
-  for (int j = K - 1; j >= first + 2; --j) S->R[j] = right_step(S->R[j + 1], S->mps, j, mpo, st);
-  const int wl = channel_of_kind(mpo, first, 0), wr = channel_of_kind(mpo, first + 2, 1);
-  if (first > 0 && wl >= 0) check_identity(S->L, wl, S->mps.bonds[first], st, "left");
-  if (first + 2 < K && wr >= 0) check_identity(S->R[first + 2], wr, S->mps.bonds[first + 2], st, "right");
-  S->bl = S->mps.bonds[first];
-  S->env.reset(make_env(ctx, mpo, first, S->bl, S->mps.bonds[first + 2], S->L, S->R[first + 2]));
-  return S.release();
+namespace {
+
+// Site j of an MPS as a one-site MPS with its own buffer (bonds j and j + 1 set).
+DeviceMps site_copy(const DeviceMps& m, int j, hipStream_t st) {
+  DeviceMps o;
+  o.K = m.K;
+  o.bonds.resize(m.K + 1);
+  o.bonds[j] = m.bonds[j];
+  o.bonds[j + 1] = m.bonds[j + 1];
+  o.sites.resize(m.K);
+  int64_t tot = 0;
+  for (const SiteBlock& b : m.sites[j]) {
+    SiteBlock c = b;
+    c.off = tot;
+    tot += (int64_t)b.rows * b.cols;
+    o.sites[j].push_back(c);
+  }
+  o.data.alloc(sizeof(double) * std::max<int64_t>(tot, 1));
+  for (size_t i = 0; i < m.sites[j].size(); ++i)
+    check_hip(hipMemcpyAsync(o.data.as<double>() + o.sites[j][i].off, m.data.as<double>() + m.sites[j][i].off,
+                             sizeof(double) * (size_t)m.sites[j][i].rows * m.sites[j][i].cols, hipMemcpyDeviceToDevice,
+                             st),
+              "site copy");
+  return o;
 }
 
-void sweep_destroy(Sweep* s) { delete s; }
-Env* sweep_env(Sweep& s) { return s.env.get(); }
+const DeviceMps& ket_of(const Sweep& S, const Family& f, int j) { return f.transition ? S.ref : S.t[j]; }
 
-void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
+// L[j + 1] from L[j] and the site tensor t[j]
+void extend_left(Sweep& S, Family& f, int j) {
+  f.L[j + 1] = left_step(f.L[j], S.t[j], ket_of(S, f, j), j, *f.mpo, S.ctx->stream);
+}
+// R[j] from R[j + 1] and the site tensor t[j]
+void extend_right(Sweep& S, Family& f, int j) {
+  f.R[j] = right_step(f.R[j + 1], S.t[j], ket_of(S, f, j), j, *f.mpo, S.ctx->stream);
+}
+
+// a family's environments left and right of the current block
+void build_family(Sweep& S, Family& f) {
+  hipStream_t st = S.ctx->stream;
+  f.L.clear();
+  f.R.clear();
+  f.L.resize(S.K + 1);
+  f.R.resize(S.K + 1);
+  f.L[0] = unit_env(st);
+  for (int j = 0; j < S.site; ++j) extend_left(S, f, j);
+  f.R[S.K] = unit_env(st);
+  for (int j = S.K - 1; j >= S.site + 2; --j) extend_right(S, f, j);
+}
+
+void drop_block_envs(Sweep& S) {
+  S.env_op.reset();
+  S.env_ov.reset();
+  S.env_u.reset();
+}
+
+// The split of the solved two-site tensor: per middle-bond sector an SVD (singular values
+// descending at s_off; left vectors as a row-major nrows x r matrix at v_off; right vectors as a
+// row-major r x ncols matrix at u_off; r = min(nrows, ncols)), and the global truncation to the
+// m_max largest singular values (ties by sector (N, 2Sz), then index).
+struct SplitSector {
+  int r;
+  int64_t s_off, u_off, v_off;
+};
+struct SplitResult {
+  std::vector<SplitSector> sp;
+  DevBuf Sv, U, V;
+  std::vector<int> keep;      // kept singular vectors per sector
+  Bond nb;                    // the new bond: the sectors with keep > 0
+  std::vector<int> new_index; // sector -> index in nb (-1 if dropped)
+  std::vector<double> sv;     // all singular values, descending
+  double total = 0, kept_w = 0, largest_dropped = 0;
+  float ms_svd = 0;
+};
+
+SplitResult split_block(Sweep& S, const double* x, int m_max) {
   hipStream_t st = S.ctx->stream;
   typedef std::chrono::steady_clock clk;
-  const auto ms_since = [](clk::time_point t) {
-    return (float)std::chrono::duration<double, std::milli>(clk::now() - t).count();
-  };
   const clk::time_point t_start = clk::now();
-  const Mpo& mpo = S.ham->mpo;
-  const int K = mpo.K;
-  if (S.site + 2 >= K) throw Error{LCC_ERR_STATE, "the sweep is already at the last two-site block"};
-  if (m_max < 1) throw Error{LCC_ERR_ARG, "m_max must be >= 1"};
   Env& E = *S.env;
   const int nsec = (int)E.sectors.size();
-  // ---- SVD per middle sector (one workgroup each): singular values descending at s_off, left
-  // vectors as a row-major nrows x r matrix at v_off, right vectors as a row-major r x ncols
-  // matrix at u_off (r = min(nrows, ncols)).
-  struct Split { int r; int64_t s_off, u_off, v_off; };
-  std::vector<Split> sp(nsec);
+  SplitResult out;
+  std::vector<SplitSector>& sp = out.sp;
+  sp.resize(nsec);
   std::vector<SvdJob> jobs(nsec);
   int64_t s_tot = 0, u_tot = 0, v_tot = 0, w_tot = 0;
   for (int q = 0; q < nsec; ++q) {
     const MiddleSector& M = E.sectors[q];
-    Split& p = sp[q];
+    SplitSector& p = sp[q];
     p.r = std::min(M.nrows, M.ncols);
     p.s_off = s_tot; s_tot += p.r;
     p.u_off = u_tot; u_tot += (int64_t)M.ncols * p.r;
@@ -348,10 +403,10 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     rounds = std::max(rounds, N - 1);
     for (int k = 0; k < std::max(1, N / 2); ++k) slots.push_back(SvdSlot{q, k});
   }
-  DevBuf Sv, U, V, Wk, rot, done, djobs, dslots;
-  Sv.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
-  U.alloc(sizeof(double) * std::max<int64_t>(u_tot, 1));
-  V.alloc(sizeof(double) * std::max<int64_t>(v_tot, 1));
+  DevBuf Wk, rot, done, djobs, dslots;
+  out.Sv.alloc(sizeof(double) * std::max<int64_t>(s_tot, 1));
+  out.U.alloc(sizeof(double) * std::max<int64_t>(u_tot, 1));
+  out.V.alloc(sizeof(double) * std::max<int64_t>(v_tot, 1));
   Wk.alloc(sizeof(double) * std::max<int64_t>(w_tot, 1));
   rot.alloc(sizeof(int) * std::max(nsec, 1));
   done.alloc(sizeof(int) * std::max(nsec, 1));
@@ -385,13 +440,12 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     }
     if (!converged) throw Error{LCC_ERR_NAN, "Jacobi SVD did not converge in a sector (non-finite input?)"};
     hipLaunchKernelGGL(svd_finalize_kernel, dim3(nsec), dim3(kSvdThreads), 0, st, djobs.as<SvdJob>(), Wk.as<double>(),
-                       Sv.as<double>(), V.as<double>(), U.as<double>());
+                       out.Sv.as<double>(), out.V.as<double>(), out.U.as<double>());
     check_hip(hipGetLastError(), "jacobi svd finalize");
   }
-  check_hip(hipMemcpyAsync(hs.data(), Sv.p, sizeof(double) * s_tot, hipMemcpyDeviceToHost, st), "sv copy");
+  check_hip(hipMemcpyAsync(hs.data(), out.Sv.p, sizeof(double) * s_tot, hipMemcpyDeviceToHost, st), "sv copy");
   check_hip(hipStreamSynchronize(st), "svd");
-  const float ms_svd = ms_since(t_start);
-  // ---- global truncation: the m_max largest singular values; ties by sector (N, 2Sz), then index
+  out.ms_svd = (float)std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
   struct Cand { double v; int q, i; };
   std::vector<Cand> cand;
   for (int q = 0; q < nsec; ++q)
@@ -401,35 +455,111 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     if (a.q != b.q) return a.q < b.q;
     return a.i < b.i;
   });
-  std::vector<int> keep(nsec, 0);
-  double total = 0, kept_w = 0, largest_dropped = 0;
+  out.keep.assign(nsec, 0);
+  // singular values at the rounding level of the largest are zeros of the exact tensor: their
+  // vectors are not determined (one-sided Jacobi forms them as W / sigma), so they are never kept
+  const double cut = kSvCut * (cand.empty() ? 0.0 : cand[0].v);
   for (size_t c = 0; c < cand.size(); ++c) {
-    total += cand[c].v * cand[c].v;
-    if ((int)c < m_max && cand[c].v > 0.0) {
-      keep[cand[c].q] = std::max(keep[cand[c].q], cand[c].i + 1);
-      kept_w += cand[c].v * cand[c].v;
-    } else if (largest_dropped == 0.0) {
-      largest_dropped = cand[c].v;
+    out.total += cand[c].v * cand[c].v;
+    if ((int)c < m_max && cand[c].v > cut) {
+      out.keep[cand[c].q] = std::max(out.keep[cand[c].q], cand[c].i + 1);
+      out.kept_w += cand[c].v * cand[c].v;
+    } else if (out.largest_dropped == 0.0) {
+      out.largest_dropped = cand[c].v;
     }
   }
-  S.last_sv.clear();
-  for (const Cand& c : cand) S.last_sv.push_back(c.v);
-  // ---- new bond l+1 and the left-canonical site tensor A_l
-  Bond nb;
-  std::vector<int> new_index(nsec, -1);
+  for (const Cand& c : cand) out.sv.push_back(c.v);
+  out.new_index.assign(nsec, -1);
   for (int q = 0; q < nsec; ++q)
-    if (keep[q] > 0) {
-      new_index[q] = (int)nb.q.size();
-      nb.index[E.sectors[q].q] = (int)nb.q.size();
-      nb.q.push_back(E.sectors[q].q);
-      nb.dim.push_back(keep[q]);
+    if (out.keep[q] > 0) {
+      out.new_index[q] = (int)out.nb.q.size();
+      out.nb.index[E.sectors[q].q] = (int)out.nb.q.size();
+      out.nb.q.push_back(E.sectors[q].q);
+      out.nb.dim.push_back(out.keep[q]);
     }
-  if (nb.q.empty()) throw Error{LCC_ERR_ARG, "the two-site tensor is zero"};
+  if (out.nb.q.empty()) throw Error{LCC_ERR_ARG, "the two-site tensor is zero"};
+  return out;
+}
+
+void fill_info(const SplitResult& R, int site, float ms_env, float ms_guess, float ms_total, lcc_sweep_info* info) {
+  if (!info) return;
+  *info = lcc_sweep_info{};
+  info->site = site;
+  info->kept = 0;
+  for (int k : R.keep) info->kept += k;
+  info->n_singular = (int32_t)R.sv.size();
+  info->discarded_weight = R.total > 0 ? (R.total - R.kept_w) / R.total : 0.0;
+  info->largest_discarded = R.largest_dropped;
+  info->ms_svd = R.ms_svd;
+  info->ms_env = ms_env;
+  info->ms_guess = ms_guess;
+  info->ms_total = ms_total;
+}
+
+// dst[i*keep + k] = src[i*ld + k] * s[k]  (i < rows, k < keep)
+__global__ void scale_cols_kernel(double* __restrict__ dst, const double* __restrict__ src, const double* __restrict__ s,
+                                  int rows, int keep, int ld) {
+  const int64_t n = (int64_t)rows * keep;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / keep), k = (int)(e % keep);
+    dst[e] = src[(int64_t)i * ld + k] * s[k];
+  }
+}
+
+}  // namespace
+
+Sweep* sweep_create(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int first) {
+  hipStream_t st = ctx->stream;
+  const Mpo& mpo = ham.mpo;
+  const int K = mpo.K;
+  if (md.n_sites != K) throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
+  if (first < 0 || first + 1 >= K) throw Error{LCC_ERR_ARG, "first two-site block must satisfy 0 <= site < K-1"};
+  std::unique_ptr<Sweep> S(new Sweep());
+  S->ctx = ctx;
+  S->K = K;
+  S->N = ham.desc.N;
+  S->two_sz = ham.desc.two_sz;
+  S->first = S->site = first;
+  DeviceMps mps;
+  load_mps(md, ham.desc.N, ham.desc.two_sz, st, mps);
+  S->bonds = mps.bonds;
+  for (int j = 0; j < K; ++j) S->t.push_back(site_copy(mps, j, st));
+  check_hip(hipStreamSynchronize(st), "site copies");
+  S->h.mpo = &mpo;
+  build_family(*S, S->h);
+  const int wl = channel_of_kind(mpo, first, 0), wr = channel_of_kind(mpo, first + 2, 1);
+  if (first > 0 && wl >= 0) check_identity(S->h.L[first], wl, S->bonds[first], st, "left");
+  if (first + 2 < K && wr >= 0) check_identity(S->h.R[first + 2], wr, S->bonds[first + 2], st, "right");
+  S->env.reset(make_env(ctx, mpo, first, S->bonds[first], S->bonds[first + 2], S->h.L[first], S->h.R[first + 2]));
+  return S.release();
+}
+
+void sweep_destroy(Sweep* s) { delete s; }
+Env* sweep_env(Sweep& s) { return s.env.get(); }
+
+void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
+  hipStream_t st = S.ctx->stream;
+  typedef std::chrono::steady_clock clk;
+  const auto ms_since = [](clk::time_point t) {
+    return (float)std::chrono::duration<double, std::milli>(clk::now() - t).count();
+  };
+  const clk::time_point t_start = clk::now();
+  const Mpo& mpo = *S.h.mpo;
+  const int K = S.K;
+  if (S.site + 2 >= K) throw Error{LCC_ERR_STATE, "the sweep is already at the last two-site block"};
+  if (m_max < 1) throw Error{LCC_ERR_ARG, "m_max must be >= 1"};
+  Env& E = *S.env;
+  const int nsec = (int)E.sectors.size();
+  SplitResult R = split_block(S, x, m_max);
+  S.last_sv = R.sv;
+  const std::vector<int>& keep = R.keep;
+  // ---- new bond l+1 and the left-canonical site tensor A_l (left vectors, first keep columns)
+  const int l = S.site;
   DeviceMps one;
   one.K = K;
   one.bonds.resize(K + 1);
-  one.bonds[S.site] = S.bl;
-  one.bonds[S.site + 1] = nb;
+  one.bonds[l] = S.bonds[l];
+  one.bonds[l + 1] = R.nb;
   one.sites.resize(K);
   int64_t a_site = 0;
   std::vector<std::pair<int, int>> src;  // (sector, row) of each block
@@ -438,29 +568,36 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     const MiddleSector& M = E.sectors[q];
     for (size_t i = 0; i < M.rows.size(); ++i) {
       const int a = M.rows[i].first, s1 = M.rows[i].second;
-      SiteBlock b{a, s1, new_index[q], a_site, S.bl.dim[a], keep[q]};
+      SiteBlock b{a, s1, R.new_index[q], a_site, S.bonds[l].dim[a], keep[q]};
       a_site += (int64_t)b.rows * b.cols;
-      one.sites[S.site].push_back(b);
+      one.sites[l].push_back(b);
       src.push_back({q, (int)i});
     }
   }
   one.data.alloc(sizeof(double) * std::max<int64_t>(a_site, 1));
   for (size_t k = 0; k < src.size(); ++k) {
-    const SiteBlock& b = one.sites[S.site][k];
+    const SiteBlock& b = one.sites[l][k];
     const MiddleSector& M = E.sectors[src[k].first];
-    const Split& p = sp[src[k].first];
-    // rows row_off .. row_off + M_a of the row-major nrows x r left-vector matrix, first keep columns
+    const SplitSector& p = R.sp[src[k].first];
     check_hip(hipMemcpy2DAsync(one.data.as<double>() + b.off, sizeof(double) * b.cols,
-                               V.as<double>() + p.v_off + (int64_t)M.row_off[src[k].second] * p.r, sizeof(double) * p.r,
+                               R.V.as<double>() + p.v_off + (int64_t)M.row_off[src[k].second] * p.r, sizeof(double) * p.r,
                                sizeof(double) * b.cols, b.rows, hipMemcpyDeviceToDevice, st),
               "A block copy");
   }
-  // ---- extend the left environment by the new site tensor
+  // ---- extend the left environments by the new site tensor
   const clk::time_point t_env = clk::now();
-  Environment Lnew = left_step(S.L, one, S.site, mpo, st);
+  S.t[l] = std::move(one);
+  S.bonds[l + 1] = R.nb;
+  extend_left(S, S.h, l);
+  if (S.have_ref) {
+    extend_left(S, S.op, l);
+    extend_left(S, S.ov, l);
+    if (S.have_u) extend_left(S, S.u, l);
+  }
+  drop_block_envs(S);
   // ---- next block (l+1, l+2)
-  const int next = S.site + 1;
-  std::unique_ptr<Env> nenv(make_env(S.ctx, mpo, next, nb, S.mps.bonds[next + 2], Lnew, S.R[next + 2]));
+  const int next = l + 1;
+  std::unique_ptr<Env> nenv(make_env(S.ctx, mpo, next, R.nb, S.bonds[next + 2], S.h.L[next], S.h.R[next + 2]));
   const float ms_env = ms_since(t_env);
   const clk::time_point t_guess = clk::now();
   // ---- next guess: rows (q, s2) x cols (s3, c) = sum_b (S V^T)_q[:, (s2, b)] B_{l+2}^{s3}[b -> c]
@@ -479,25 +616,25 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
     const int64_t n = (int64_t)keep[q] * M.ncols;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(scale_rows_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, st, C.as<double>() + c_off[q],
-                       U.as<double>() + sp[q].u_off, Sv.as<double>() + sp[q].s_off, keep[q], M.ncols, M.ncols);
+                       R.U.as<double>() + R.sp[q].u_off, R.Sv.as<double>() + R.sp[q].s_off, keep[q], M.ncols, M.ncols);
   }
   check_hip(hipGetLastError(), "scale rows");
   S.guess.alloc(sizeof(double) * std::max<int64_t>(nenv->n_elements, 1));
   check_hip(launch_fill_f64(S.guess.as<double>(), nenv->n_elements, 0.0, st), "zero guess");
   {
-    // site l+2 tensor blocks by (left sector b, s3)
+    const DeviceMps& B3 = S.t[next + 1];  // site l+2 blocks by (left sector b, s3)
     std::map<std::pair<int, int>, const SiteBlock*> B;
-    for (const SiteBlock& b : S.mps.sites[next + 1]) B[{b.l, b.s}] = &b;
+    for (const SiteBlock& b : B3.sites[next + 1]) B[{b.l, b.s}] = &b;
     GemmBuilder gb;
     for (const lcc_block_entry& e : nenv->layout) {
       // e.left = new sector index (q), e.s1 = s2, e.s2 = s3, e.right = c
       int q_old = -1;
       for (int q = 0; q < nsec; ++q)
-        if (new_index[q] == e.left) q_old = q;
+        if (R.new_index[q] == e.left) q_old = q;
       const MiddleSector& M = E.sectors[q_old];
-      const QN qc = S.mps.bonds[next + 2].q[e.right];
+      const QN qc = S.bonds[next + 2].q[e.right];
       const QN qb = qc - local_qn(e.s2);
-      const int b = S.mps.bonds[next + 1].find(qb);
+      const int b = S.bonds[next + 1].find(qb);
       if (b < 0) continue;
       auto it = B.find({b, e.s2});
       if (it == B.end()) continue;
@@ -513,30 +650,141 @@ void sweep_advance(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
       const std::vector<GemmLaunch> Ls = finalize(gb, false, false, st);
       Bases<double> bs{};
       bs.p[BASE_X] = C.as<double>();
-      bs.p[BASE_MPS] = S.mps.data.as<double>();
+      bs.p[BASE_MPS] = B3.data.as<double>();
       bs.p[BASE_Y] = S.guess.as<double>();
       run_gemm64(Ls, bs, st);
-      check_hip(hipStreamSynchronize(st), "guess");
     }
+    check_hip(hipStreamSynchronize(st), "guess");
   }
   S.have_guess = true;
-  if (info) {
-    *info = lcc_sweep_info{};
-    info->site = S.site;
-    info->kept = 0;
-    for (int q = 0; q < nsec; ++q) info->kept += keep[q];
-    info->n_singular = (int32_t)cand.size();
-    info->discarded_weight = total > 0 ? (total - kept_w) / total : 0.0;
-    info->largest_discarded = largest_dropped;
-    info->ms_svd = ms_svd;
-    info->ms_env = ms_env;
-    info->ms_guess = ms_since(t_guess);
-    info->ms_total = ms_since(t_start);
-  }
-  S.L = std::move(Lnew);
-  S.bl = nb;
+  fill_info(R, l, ms_env, ms_since(t_guess), ms_since(t_start), info);
   S.env = std::move(nenv);
   S.site = next;
+}
+
+// The mirror of sweep_advance: the right vectors of the split become the right-canonical tensor
+// of site l+1, the right environments are extended by it, and A_{l-1} contracted with U S is the
+// initial guess of the local problem at (l-1, l).
+void sweep_retreat(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
+  hipStream_t st = S.ctx->stream;
+  typedef std::chrono::steady_clock clk;
+  const auto ms_since = [](clk::time_point t) {
+    return (float)std::chrono::duration<double, std::milli>(clk::now() - t).count();
+  };
+  const clk::time_point t_start = clk::now();
+  const Mpo& mpo = *S.h.mpo;
+  const int K = S.K;
+  if (S.site == 0) throw Error{LCC_ERR_STATE, "the sweep is already at the first two-site block"};
+  if (m_max < 1) throw Error{LCC_ERR_ARG, "m_max must be >= 1"};
+  Env& E = *S.env;
+  const int nsec = (int)E.sectors.size();
+  SplitResult R = split_block(S, x, m_max);
+  S.last_sv = R.sv;
+  const std::vector<int>& keep = R.keep;
+  const int l = S.site;
+  // ---- new bond l+1 and the right-canonical site tensor B_{l+1} (right vectors, first keep rows)
+  DeviceMps one;
+  one.K = K;
+  one.bonds.resize(K + 1);
+  one.bonds[l + 1] = R.nb;
+  one.bonds[l + 2] = S.bonds[l + 2];
+  one.sites.resize(K);
+  int64_t b_site = 0;
+  std::vector<std::pair<int, int>> src;  // (sector, column block) of each block
+  for (int q = 0; q < nsec; ++q) {
+    if (keep[q] == 0) continue;
+    const MiddleSector& M = E.sectors[q];
+    for (size_t i = 0; i < M.cols.size(); ++i) {
+      const int s2 = M.cols[i].first, b = M.cols[i].second;
+      SiteBlock sb{R.new_index[q], s2, b, b_site, keep[q], S.bonds[l + 2].dim[b]};
+      b_site += (int64_t)sb.rows * sb.cols;
+      one.sites[l + 1].push_back(sb);
+      src.push_back({q, (int)i});
+    }
+  }
+  one.data.alloc(sizeof(double) * std::max<int64_t>(b_site, 1));
+  for (size_t k = 0; k < src.size(); ++k) {
+    const SiteBlock& b = one.sites[l + 1][k];
+    const MiddleSector& M = E.sectors[src[k].first];
+    const SplitSector& p = R.sp[src[k].first];
+    // rows 0 .. keep of the row-major r x ncols right-vector matrix, columns col_off .. + M_b
+    check_hip(hipMemcpy2DAsync(one.data.as<double>() + b.off, sizeof(double) * b.cols,
+                               R.U.as<double>() + p.u_off + M.col_off[src[k].second], sizeof(double) * M.ncols,
+                               sizeof(double) * b.cols, b.rows, hipMemcpyDeviceToDevice, st),
+              "B block copy");
+  }
+  const clk::time_point t_env = clk::now();
+  S.t[l + 1] = std::move(one);
+  S.bonds[l + 1] = R.nb;
+  extend_right(S, S.h, l + 1);
+  if (S.have_ref) {
+    extend_right(S, S.op, l + 1);
+    extend_right(S, S.ov, l + 1);
+    if (S.have_u) extend_right(S, S.u, l + 1);
+  }
+  drop_block_envs(S);
+  // ---- previous block (l-1, l)
+  const int prev = l - 1;
+  std::unique_ptr<Env> nenv(make_env(S.ctx, mpo, prev, S.bonds[prev], R.nb, S.h.L[prev], S.h.R[l + 1]));
+  const float ms_env = ms_since(t_env);
+  const clk::time_point t_guess = clk::now();
+  // ---- guess: rows (a'', s0) x cols (s1, q) = sum_a A_{l-1}^{s0}[a'' -> a] (U S)_q[(a, s1), :]
+  DevBuf C;
+  std::vector<int64_t> c_off(nsec, -1);
+  int64_t c_tot = 0;
+  for (int q = 0; q < nsec; ++q)
+    if (keep[q] > 0) {
+      c_off[q] = c_tot;
+      c_tot += (int64_t)E.sectors[q].nrows * keep[q];
+    }
+  C.alloc(sizeof(double) * std::max<int64_t>(c_tot, 1));
+  for (int q = 0; q < nsec; ++q) {
+    if (keep[q] == 0) continue;
+    const MiddleSector& M = E.sectors[q];
+    const int64_t n = (int64_t)M.nrows * keep[q];
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, st, C.as<double>() + c_off[q],
+                       R.V.as<double>() + R.sp[q].v_off, R.Sv.as<double>() + R.sp[q].s_off, M.nrows, keep[q], R.sp[q].r);
+  }
+  check_hip(hipGetLastError(), "scale cols");
+  S.guess.alloc(sizeof(double) * std::max<int64_t>(nenv->n_elements, 1));
+  check_hip(launch_fill_f64(S.guess.as<double>(), nenv->n_elements, 0.0, st), "zero guess");
+  {
+    const DeviceMps& A0 = S.t[prev];  // site l-1 blocks by (left sector a'', s0)
+    std::map<std::pair<int, int>, const SiteBlock*> A;
+    for (const SiteBlock& b : A0.sites[prev]) A[{b.l, b.s}] = &b;
+    GemmBuilder gb;
+    for (const lcc_block_entry& e : nenv->layout) {
+      // e.left = a'' (bond l-1), e.s1 = s0, e.s2 = s1, e.right = new sector index (q)
+      int q_old = -1;
+      for (int q = 0; q < nsec; ++q)
+        if (R.new_index[q] == e.right) q_old = q;
+      const MiddleSector& M = E.sectors[q_old];
+      auto it = A.find({e.left, e.s1});
+      if (it == A.end()) continue;
+      const SiteBlock& Ab = *it->second;  // a'' -> a on bond l
+      int row = -1;
+      for (size_t i = 0; i < M.rows.size(); ++i)
+        if (M.rows[i].first == Ab.r && M.rows[i].second == e.s2) row = (int)i;
+      if (row < 0) continue;
+      gb.group(BASE_Y, e.offset, e.ld, e.rows, e.cols, false);
+      gb.term(BASE_MPS, Ab.off, Ab.cols, BASE_X, c_off[q_old] + (int64_t)M.row_off[row] * keep[q_old], keep[q_old],
+              Ab.cols, 1.0);
+    }
+    if (!gb.groups.empty()) {
+      const std::vector<GemmLaunch> Ls = finalize(gb, false, false, st);
+      Bases<double> bs{};
+      bs.p[BASE_X] = C.as<double>();
+      bs.p[BASE_MPS] = A0.data.as<double>();
+      bs.p[BASE_Y] = S.guess.as<double>();
+      run_gemm64(Ls, bs, st);
+    }
+    check_hip(hipStreamSynchronize(st), "guess");
+  }
+  S.have_guess = true;
+  fill_info(R, l, ms_env, ms_since(t_guess), ms_since(t_start), info);
+  S.env = std::move(nenv);
+  S.site = prev;
 }
 
 void sweep_copy_guess(Sweep& S, double* x) {
@@ -549,5 +797,102 @@ void sweep_copy_guess(Sweep& S, double* x) {
 }
 
 const std::vector<double>& sweep_singular_values(Sweep& S) { return S.last_sv; }
+
+int sweep_site(const Sweep& S) { return S.site; }
+
+// ---------------------------------------------------------------------------------------
+// First-order problems (Theory section, the first-order equation): the reference MPS Phi0 and
+// the operator O of the right-hand side -Q O Phi0 (O = U; O = H for the projector approximation),
+// the overlap with Phi0, and optionally U on the sweep's own MPS for the third-order energy.
+// ---------------------------------------------------------------------------------------
+void sweep_attach_reference(Sweep& S, const Hamiltonian& op, const Hamiltonian* u, const lcc_mps_desc& ref) {
+  hipStream_t st = S.ctx->stream;
+  if (op.mpo.K != S.K || (u && u->mpo.K != S.K) || ref.n_sites != S.K)
+    throw Error{LCC_ERR_ARG, "the operators and the reference MPS must have the sweep's orbital count"};
+  if (op.desc.N != S.N || op.desc.two_sz != S.two_sz || (u && (u->desc.N != S.N || u->desc.two_sz != S.two_sz)))
+    throw Error{LCC_ERR_QN, "the operators must act in the sweep's (N, 2Sz) sector"};
+  S.have_ref = false;
+  drop_block_envs(S);
+  DeviceMps r;
+  load_mps(ref, S.N, S.two_sz, st, r);
+  S.ref = std::move(r);
+  S.op = Family();
+  S.op.mpo = &op.mpo;
+  S.op.transition = true;
+  S.ov = Family();
+  {
+    // the identity operator through the MPO compiler: no integrals, constant 1
+    HamDesc id;
+    id.K = S.K;
+    id.N = S.N;
+    id.two_sz = S.two_sz;
+    id.h.assign((size_t)S.K * S.K, 0.0);
+    id.e_const = 1.0;
+    id.switch_bond = -1;
+    const std::string err = build_mpo(id, S.ov.own);
+    if (!err.empty()) throw Error{LCC_ERR_STATE, "identity operator: " + err};
+  }
+  S.ov.mpo = &S.ov.own;
+  S.ov.transition = true;
+  build_family(S, S.op);
+  build_family(S, S.ov);
+  S.have_u = u != nullptr;
+  S.u = Family();
+  if (u) {
+    S.u.mpo = &u->mpo;
+    build_family(S, S.u);
+  }
+  S.have_ref = true;
+}
+
+namespace {
+Env* transition_block(Sweep& S, Family& f) {
+  const int l = S.site;
+  std::unique_ptr<Env> e(make_env(S.ctx, *f.mpo, l, S.bonds[l], S.bonds[l + 2], S.ref.bonds[l], S.ref.bonds[l + 2],
+                                  f.L[l], f.R[l + 2], true));
+  build_ket_tensor(*e, S.ref, S.ref, S.ctx->stream);
+  return e.release();
+}
+double dot_dev(Context* c, const double* a, const double* b, int64_t n) {
+  hipStream_t st = c->stream;
+  check_hip(launch_dot_f64(a, b, n, c->dot_partial.as<double>(), c->dot_out.as<double>(), st), "dot");
+  check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+  check_hip(hipStreamSynchronize(st), "dot sync");
+  return c->host_scalar[0];
+}
+}  // namespace
+
+// b = -(P^T O Phi0 - c v) with v = P^T Phi0 (P: the environment basis of the current block);
+// v is returned scaled to norm 1 (as the solver's projection takes it) and |v| in *v_norm
+void sweep_first_order_rhs(Sweep& S, double c, double* b, double* v, double* v_norm) {
+  if (!S.have_ref) throw Error{LCC_ERR_STATE, "no reference MPS attached to the sweep"};
+  hipStream_t st = S.ctx->stream;
+  if (!S.env_op) S.env_op.reset(transition_block(S, S.op));
+  if (!S.env_ov) S.env_ov.reset(transition_block(S, S.ov));
+  const int64_t n = S.env->n_elements;
+  if (S.env_op->n_elements != n || S.env_ov->n_elements != n)
+    throw Error{LCC_ERR_STATE, "internal: block layouts of the sweep and its transition operators differ"};
+  apply_heff(*S.env_ov, LCC_FP64, S.env_ov->x0.p, v);
+  apply_heff(*S.env_op, LCC_FP64, S.env_op->x0.p, b);
+  // b = -b + c v
+  check_hip(launch_axpby_f64(n, c, v, -1.0, b, st), "rhs");
+  const double nv = std::sqrt(std::max(0.0, dot_dev(S.ctx, v, v, n)));
+  if (nv > 0.0) check_hip(launch_axpby_f64(n, 0.0, v, 1.0 / nv, v, st), "normalise v");
+  check_hip(hipStreamSynchronize(st), "rhs");
+  *v_norm = nv;
+}
+
+// x^T U_eff x and x^T x of the current block's tensor
+void sweep_u_expectation(Sweep& S, const double* x, double* xux, double* xx) {
+  if (!S.have_ref || !S.have_u) throw Error{LCC_ERR_STATE, "no perturbation operator attached to the sweep"};
+  const int l = S.site;
+  if (!S.env_u) S.env_u.reset(make_env(S.ctx, *S.u.mpo, l, S.bonds[l], S.bonds[l + 2], S.u.L[l], S.u.R[l + 2]));
+  const int64_t n = S.env->n_elements;
+  DevBuf y;
+  y.alloc(sizeof(double) * std::max<int64_t>(n, 1));
+  apply_heff(*S.env_u, LCC_FP64, x, y.p);
+  *xux = dot_dev(S.ctx, x, y.as<double>(), n);
+  *xx = dot_dev(S.ctx, x, x, n);
+}
 
 }  // namespace lcc

@@ -30,7 +30,9 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_sweep_guess", "lcc_sweep_advance", "lcc_sweep_singular_values", "lcc_context_set_tune_cache",
            "lcc_env_autotune", "lcc_context_set_overlap", "lcc_context_set_plan", "lcc_lowest_eigenpair",
            "lcc_lowest_eigenvalue_noalloc", "lcc_build_transition_environments", "lcc_env_input_layout",
-           "lcc_env_ket_tensor", "lcc_env_diagonal"]
+           "lcc_env_ket_tensor", "lcc_env_diagonal", "lcc_sweep_retreat", "lcc_sweep_position",
+           "lcc_sweep_attach_reference", "lcc_sweep_first_order_rhs", "lcc_sweep_u_expectation",
+           "lcc_mps_expectation"]
 
 
 class LccError(RuntimeError):
@@ -155,6 +157,12 @@ def library() -> C.CDLL:
         "lcc_sweep_guess": (C.c_int32, [P, P]),
         "lcc_sweep_advance": (C.c_int32, [P, P, C.c_int32, C.POINTER(SweepInfo)]),
         "lcc_sweep_singular_values": (C.c_int32, [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "lcc_sweep_retreat": (C.c_int32, [P, P, C.c_int32, C.POINTER(SweepInfo)]),
+        "lcc_sweep_position": (C.c_int32, [P, C.POINTER(C.c_int32)]),
+        "lcc_sweep_attach_reference": (C.c_int32, [P, P, P, C.POINTER(MpsDesc)]),
+        "lcc_sweep_first_order_rhs": (C.c_int32, [P, C.c_double, P, P, C.POINTER(C.c_double)]),
+        "lcc_sweep_u_expectation": (C.c_int32, [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "lcc_mps_expectation": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(C.c_double)]),
         "lcc_batch_destroy": (None, [P]),
         "lcc_batch_solve": (C.c_int32, [P, C.POINTER(SolveOpts), C.POINTER(P), C.POINTER(C.c_double), C.POINTER(P),
                                         C.POINTER(P), C.POINTER(SolveInfo)]),
@@ -584,7 +592,8 @@ def solve_local_lcc_batched(envs: list, bs: list, e0s: list, xs: list, vs: list 
 
 
 class Sweep:
-    """lcc_sweep: left-to-right two-site sweep (SVD split, truncation, environment update)."""
+    """lcc_sweep: two-site sweep in both directions (SVD split, truncation, environment update),
+    optionally with a reference MPS for first-order problems."""
 
     def __init__(self, ctx: Context, ham: Hamiltonian, mps: dict, first_site: int):
         self.ctx = ctx
@@ -615,13 +624,49 @@ class Sweep:
     def guess(self, x):
         _check(library().lcc_sweep_guess(self.handle, C.c_void_p(x.data_ptr())), self.ctx.handle)
 
+    @staticmethod
+    def _info(info) -> dict:
+        return {"site": info.site, "kept": info.kept, "n_singular": info.n_singular,
+                "discarded_weight": info.discarded_weight, "largest_discarded": info.largest_discarded,
+                "ms_svd": info.ms_svd, "ms_env": info.ms_env, "ms_guess": info.ms_guess, "ms_total": info.ms_total}
+
     def advance(self, x, m_max: int) -> dict:
         info = SweepInfo()
         _check(library().lcc_sweep_advance(self.handle, C.c_void_p(x.data_ptr()), int(m_max), C.byref(info)),
                self.ctx.handle)
-        return {"site": info.site, "kept": info.kept, "n_singular": info.n_singular,
-                "discarded_weight": info.discarded_weight, "largest_discarded": info.largest_discarded,
-                "ms_svd": info.ms_svd, "ms_env": info.ms_env, "ms_guess": info.ms_guess, "ms_total": info.ms_total}
+        return self._info(info)
+
+    def retreat(self, x, m_max: int) -> dict:
+        info = SweepInfo()
+        _check(library().lcc_sweep_retreat(self.handle, C.c_void_p(x.data_ptr()), int(m_max), C.byref(info)),
+               self.ctx.handle)
+        return self._info(info)
+
+    def position(self) -> int:
+        site = C.c_int32(0)
+        _check(library().lcc_sweep_position(self.handle, C.byref(site)), self.ctx.handle)
+        return site.value
+
+    def attach_reference(self, op: Hamiltonian, u: "Hamiltonian | None", ref: dict):
+        desc, keep = _mps_desc(ref)
+        _check(library().lcc_sweep_attach_reference(self.handle, op.handle, u.handle if u is not None else None,
+                                                    C.byref(desc)), self.ctx.handle)
+        del keep
+        self.refs = (op, u)  # the sweep refers to their MPOs
+
+    def first_order_rhs(self, c: float, b, v) -> float:
+        """b = -(P^T O Phi0 - c P^T Phi0), v = P^T Phi0 / |P^T Phi0|; returns |P^T Phi0|."""
+        n = C.c_double(0.0)
+        _check(library().lcc_sweep_first_order_rhs(self.handle, float(c), C.c_void_p(b.data_ptr()),
+                                                   C.c_void_p(v.data_ptr()), C.byref(n)), self.ctx.handle)
+        return n.value
+
+    def u_expectation(self, x) -> tuple:
+        """(x^T U_eff x, x^T x) of the block tensor x."""
+        a, b = C.c_double(0.0), C.c_double(0.0)
+        _check(library().lcc_sweep_u_expectation(self.handle, C.c_void_p(x.data_ptr()), C.byref(a), C.byref(b)),
+               self.ctx.handle)
+        return a.value, b.value
 
     def singular_values(self) -> np.ndarray:
         lib = library()
@@ -631,3 +676,70 @@ class Sweep:
         _check(lib.lcc_sweep_singular_values(self.handle, C.byref(n), _dptr(out)))
         return out
 
+
+
+def mps_expectation(ctx: Context, ham: Hamiltonian, mps: dict, site: int | None = None) -> float:
+    """lcc_mps_expectation: <Phi|H|Phi> of an MPS canonical around the block (site, site + 1)."""
+    if site is None:
+        site = mps["center"]
+    desc, keep = _mps_desc(mps)
+    out = C.c_double(0.0)
+    _check(library().lcc_mps_expectation(ctx.handle, ham.handle, C.byref(desc), int(site), C.byref(out)), ctx.handle)
+    del keep
+    return out.value
+
+
+def first_order_sweeps(ctx: Context, h0: Hamiltonian, op: Hamiltonian, psi1: dict, psi0: dict, e0: float, c: float,
+                       m_max: int, sweeps: int = 2, u: Hamiltonian | None = None, e1: float = 0.0,
+                       precision: str = "fp64", tol: float = 1e-10, max_iter: int = 2000) -> dict:
+    """First-order MPS-LCC: Phi1 (initial MPS psi1, canonical around its first block) is optimised
+    by sweeps of two-site Hylleraas minimisations, (P^T H0 P - E0) x = -P^T Q O Phi0 with x
+    orthogonal to P^T Phi0 at every block (lcc_sweep_first_order_rhs, lcc_solve_local_lcc), the
+    solved tensor split and truncated to m_max as the sweep moves.  A sweep visits every block of
+    the chain once, alternating direction; the first one starts at psi1["center"] and moves right
+    (then left).  O = U (op: the part = 2 Hamiltonian, c = E1) or O = H for the projector
+    approximation (c = <Phi0|H|Phi0>).  Returns the Hylleraas value of every local solve, the last
+    one (E2 = <Phi0|O|Phi1>) and, with u given, E3 = <Phi1|U|Phi1> - E1 <Phi1|Phi1> at the last
+    block.  Sequences library calls only; every step runs on the device."""
+    import torch
+    K = psi1["n_sites"]
+    dev = torch.device("cuda", ctx.device if ctx.device >= 0 else 0)
+    sw = Sweep(ctx, h0, psi1, psi1["center"])
+    try:
+        sw.attach_reference(op, u, psi0)
+        values, infos = [], []
+        direction = 1 if sw.position() < K - 2 else -1
+        x = None
+        for s in range(sweeps):
+            while True:
+                env = sw.env()
+                b = torch.empty(env.n, dtype=torch.float64, device=dev)
+                v = torch.empty_like(b)
+                nv = sw.first_order_rhs(c, b, v)
+                x = torch.empty_like(b)
+                sw.guess(x)
+                # the block's basis need not hold Phi0 (it follows Phi1): below 1e-8 the overlap
+                # is rounding noise and its direction meaningless, and the constraint is void
+                info = env.solve_local_lcc(b, e0, x, v=v if nv > 1e-8 else None, precision=precision, tol=tol,
+                                           max_iter=max_iter, inner_tol=1e-4 if precision != "fp64" else 0.0,
+                                           max_outer=200)
+                if info["status"] not in ("LCC_OK",):
+                    raise LccError(-9, f"local solve at site {sw.position()}: {info['status']}")
+                values.append(info["hylleraas"])
+                infos.append({"site": sw.position(), "sweep": s, "iterations": info["iterations"],
+                              "overlap": nv})
+                at_end = sw.position() == (K - 2 if direction > 0 else 0)
+                if at_end:
+                    break
+                (sw.advance if direction > 0 else sw.retreat)(x, m_max)
+            if s + 1 < sweeps:
+                direction = -direction
+                (sw.advance if direction > 0 else sw.retreat)(x, m_max)
+        out = {"hylleraas": values, "blocks": infos, "e2": values[-1]}
+        if u is not None:
+            xux, xx = sw.u_expectation(x)
+            out["e3"] = xux - e1 * xx
+            out["norm2"] = xx
+        return out
+    finally:
+        sw.close()

@@ -212,3 +212,94 @@ def random_two_site_vector(mps: dict, seed: int) -> dict:
         vec[key] = rng.standard_normal((bl[ia][2], br[ib][2]))
     nrm = np.sqrt(sum(float(np.sum(v * v)) for v in vec.values()))
     return {k: v / nrm for k, v in vec.items()}
+
+
+def mps_from_amplitudes(full: np.ndarray, n_sites: int, n_elec: int, two_sz: int, tol: float = 1e-13) -> dict:
+    """Exact MPS (center 0: sites 2..K-1 right-canonical) of a state given by its amplitudes over
+    all 4^K site configurations (site 0 most significant, local index n_up + 2 n_dn), built by
+    SVDs per (N, 2Sz) block from the right; singular values below tol * the largest are dropped.
+    An input generator: it reshapes a given state, nothing of the method is computed here."""
+    K = n_sites
+    qn_loc = np.array(LOCAL_QN)
+
+    def row_qn(n_rows_sites):
+        # (N, 2Sz) of every configuration of sites 0..n_rows_sites-1
+        q = np.zeros((1, 2), dtype=np.int64)
+        for _ in range(n_rows_sites):
+            q = (q[:, None, :] + qn_loc[None, :, :]).reshape(-1, 2)
+        return q
+
+    T = np.asarray(full, dtype=float).reshape(4 ** (K - 1), 4)  # rows: sites 0..K-2; cols (s, b) on bond K
+    right = [(n_elec, two_sz, 1)]  # sectors of the bond right of the current site
+    sites = [None] * K
+    bonds = [None] * (K + 1)
+    bonds[K] = right
+    for j in range(K - 1, 1, -1):
+        rq = row_qn(j)
+        # columns (s_j, b): QN of the left part they need
+        col_need = []
+        off_b = np.concatenate([[0], np.cumsum([d for _, _, d in right])])
+        for s in range(4):
+            for ib, (n, sz, d) in enumerate(right):
+                col_need.append((s, ib, n - LOCAL_QN[s][0], sz - LOCAL_QN[s][1]))
+        new_sectors, blocks, Tnew_parts = [], [], []
+        keys = sorted({(int(a), int(b)) for a, b in rq})
+        for (qn_, qz) in keys:
+            rows = np.nonzero((rq[:, 0] == qn_) & (rq[:, 1] == qz))[0]
+            cols = [(s, ib) for (s, ib, n, z) in col_need if (n, z) == (qn_, qz)]
+            if not cols:
+                continue
+            idx = np.concatenate([s * off_b[-1] + np.arange(off_b[ib], off_b[ib + 1]) for s, ib in cols])
+            M = T[np.ix_(rows, idx)]
+            if not np.any(M):
+                continue
+            U, S, Vt = np.linalg.svd(M, full_matrices=False)
+            r = int(np.sum(S > tol * S[0]))
+            if r == 0:
+                continue
+            new_sectors.append((qn_, qz, r))
+            c0 = 0
+            for s, ib in cols:
+                d = right[ib][2]
+                blocks.append([len(new_sectors) - 1, s, ib, np.ascontiguousarray(Vt[:r, c0:c0 + d])])
+                c0 += d
+            Tnew_parts.append((rows, U[:, :r] * S[:r]))
+        bonds[j] = new_sectors
+        sites[j] = [tuple(b) for b in blocks]
+        width = sum(d for _, _, d in new_sectors)
+        Tn = np.zeros((T.shape[0], width))
+        off = 0
+        for rows, blk in Tnew_parts:
+            Tn[rows, off:off + blk.shape[1]] = blk
+            off += blk.shape[1]
+        right = new_sectors
+        T = Tn.reshape(4 ** (j - 1), 4 * width)
+    # sites 0 and 1 (the center block): rows s0 (bond 0 -> bond 1), columns (s1, b) on bond 2
+    off_b = np.concatenate([[0], np.cumsum([d for _, _, d in right])])
+    sec1, s0_blocks, s1_blocks = [], [], []
+    for s0 in range(4):
+        n0, z0 = LOCAL_QN[s0]
+        cols = [(s1, ib) for s1 in range(4) for ib, (n, z, d) in enumerate(right)
+                if (n - LOCAL_QN[s1][0], z - LOCAL_QN[s1][1]) == (n0, z0)]
+        if not cols:
+            continue
+        idx = np.concatenate([s1 * off_b[-1] + np.arange(off_b[ib], off_b[ib + 1]) for s1, ib in cols])
+        row = T[s0, idx]
+        if not np.any(row):
+            continue
+        sec1.append((n0, z0, 1))
+        s0_blocks.append([0, s0, len(sec1) - 1, np.ones((1, 1))])
+        c0 = 0
+        for s1, ib in cols:
+            d = right[ib][2]
+            s1_blocks.append([len(sec1) - 1, s1, ib, row[c0:c0 + d].reshape(1, d).copy()])
+            c0 += d
+    order = sorted(range(len(sec1)), key=lambda i: sec1[i][:2])
+    remap = {old: new for new, old in enumerate(order)}
+    bonds[1] = [sec1[i] for i in order]
+    sites[0] = [(0, s, remap[r], a) for (_, s, r, a) in s0_blocks]
+    sites[1] = [(remap[l], s, r, a) for (l, s, r, a) in s1_blocks]
+    bonds[0] = [(0, 0, 1)]
+    # bond sectors are listed in increasing (N, 2Sz) order (the keys were sorted)
+    return {"n_sites": K, "n_elec": n_elec, "two_sz": two_sz, "center": 0, "bonds": bonds,
+            "sites": [list(s) for s in sites]}
