@@ -593,6 +593,16 @@ def main():
         fp64 = {"ms": (time.perf_counter() - t0) * 1e3, "iterations": info64["iterations"],
                 "hylleraas": info64["hylleraas"], "status": info64["status"]}
         log(f"[bench] fp64 solve: {info64}")
+    other = None
+    if args.precision == "fp32":
+        # the same mixed solve with the BF16x3 split-product operator inside the refinement
+        t0 = time.perf_counter()
+        info_bf = solve("bf16x3")
+        torch.cuda.synchronize()
+        other = {"ms": (time.perf_counter() - t0) * 1e3, "applies_low": info_bf["applies_low"],
+                 "applies_fp64": info_bf["applies_fp64"], "hylleraas": info_bf["hylleraas"],
+                 "energy_diff_vs_fp32": abs(info_bf["hylleraas"] - j_mixed), "status": info_bf["status"]}
+        log(f"[bench] bf16x3 mixed solve: {info_bf}")
 
     # --- roofline of the dominant kernel launch of the timed precision (HIP events per launch)
     xx = x64 if args.precision == "fp64" else x64.float()
@@ -632,7 +642,8 @@ def main():
                   "outer": infos[-1]["outer"], "applies_fp64": infos[-1]["applies_fp64"],
                   "applies_low": infos[-1]["applies_low"], "hylleraas": j_mixed,
                   "rel_residual": infos[-1]["rel_residual"], "e0": e0,
-                  "fp64": fp64, "energy_diff_vs_fp64": (abs(j_mixed - fp64["hylleraas"]) if fp64 else None),
+                  "fp64": fp64, "bf16x3": other,
+                  "energy_diff_vs_fp64": (abs(j_mixed - fp64["hylleraas"]) if fp64 else None),
                   "speedup_vs_fp64": (fp64["ms"] / ms_step if fp64 else None)},
         "apply": {p: {"gflops": v["gflops"], "ms": v["ms_wall"], "ms_launches_in_order": v["ms"],
                       "ms_phase1": v["ms_phase1"], "ms_phase2": v["ms_phase2"],
