@@ -391,6 +391,20 @@ lcc_status lcc_sweep_advance(lcc_sweep sweep, const double* x_dev, int32_t m_max
 lcc_status lcc_sweep_retreat(lcc_sweep sweep, const double* x_dev, int32_t m_max, lcc_sweep_info* info);
 /* Left site of the current block. */
 lcc_status lcc_sweep_position(lcc_sweep sweep, int32_t* site);
+/* Split the block tensor x_dev as lcc_sweep_advance does, without moving: the block's left site
+ * gets the left-canonical factor, its right site S V^T (the MPS is then complete, canonical
+ * around the block, and can be read out with lcc_sweep_bond / lcc_sweep_site_tensor).  The
+ * block's environments and local problem are unchanged.  Synchronous. */
+lcc_status lcc_sweep_split_block(lcc_sweep sweep, const double* x_dev, int32_t m_max, lcc_sweep_info* info);
+/* Sectors of MPS bond `bond` (0..n_sites) of the sweep: call with sectors == NULL for *count. */
+lcc_status lcc_sweep_bond(lcc_sweep sweep, int32_t bond, int32_t* count, lcc_sector* sectors);
+/* Site tensor `site` of the sweep's MPS, copied to the host: blocks (left sector, s, right
+ * sector, rows, cols, offset into data_host; row-major FP64).  Call with blocks == NULL or
+ * data_host == NULL for *n_blocks and *n_elements.  The two sites of the current block hold
+ * their last split (lcc_sweep_split_block, or the input MPS before any split).  Synchronous. */
+typedef struct { int32_t left, s, right, rows, cols; int64_t offset; } lcc_site_block;
+lcc_status lcc_sweep_site_tensor(lcc_sweep sweep, int32_t site, int32_t* n_blocks, int64_t* n_elements,
+                                 lcc_site_block* blocks, double* data_host);
 /* Singular values of the last split, all sectors, descending: call with out == NULL for *count. */
 lcc_status lcc_sweep_singular_values(lcc_sweep sweep, int32_t* count, double* out);
 

@@ -608,6 +608,63 @@ lcc_status lcc_sweep_u_expectation(lcc_sweep sweep, const double* x, double* xux
   });
 }
 
+lcc_status lcc_sweep_split_block(lcc_sweep sweep, const double* x, int32_t m_max, lcc_sweep_info* info) {
+  if (!sweep || !x) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    sweep_split_block(*sweep->s, x, m_max, info);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_bond(lcc_sweep sweep, int32_t bond, int32_t* count, lcc_sector* sectors) {
+  if (!sweep || !count) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    const Bond& B = sweep_bond(*sweep->s, bond);
+    if (!sectors) {
+      *count = (int32_t)B.q.size();
+      return LCC_OK;
+    }
+    if (*count < (int32_t)B.q.size()) throw Error{LCC_ERR_ARG, "sector array too small"};
+    for (size_t i = 0; i < B.q.size(); ++i) sectors[i] = lcc_sector{B.q[i].n, B.q[i].sz, B.dim[i]};
+    *count = (int32_t)B.q.size();
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_sweep_site_tensor(lcc_sweep sweep, int32_t site, int32_t* n_blocks, int64_t* n_elements,
+                                 lcc_site_block* blocks, double* data_host) {
+  if (!sweep || !n_blocks || !n_elements) return fail(nullptr, LCC_ERR_ARG, "NULL argument");
+  lcc_context ctx = static_cast<lcc_context>(sweep->ctx->handle);
+  return guarded(ctx, [&]() -> lcc_status {
+    check_hip(hipSetDevice(sweep->ctx->device), "hipSetDevice");
+    const DeviceMps& t = sweep_site_tensor(*sweep->s, site);
+    int64_t total = 0;
+    for (const SiteBlock& b : t.sites[site]) total += (int64_t)b.rows * b.cols;
+    if (!blocks || !data_host) {
+      *n_blocks = (int32_t)t.sites[site].size();
+      *n_elements = total;
+      return LCC_OK;
+    }
+    if (*n_blocks < (int32_t)t.sites[site].size() || *n_elements < total)
+      throw Error{LCC_ERR_ARG, "output arrays too small"};
+    int64_t off = 0;
+    for (size_t i = 0; i < t.sites[site].size(); ++i) {
+      const SiteBlock& b = t.sites[site][i];
+      blocks[i] = lcc_site_block{b.l, b.s, b.r, b.rows, b.cols, off};
+      check_hip(hipMemcpy(data_host + off, t.data.as<double>() + b.off, sizeof(double) * (size_t)b.rows * b.cols,
+                          hipMemcpyDeviceToHost),
+                "site tensor copy");
+      off += (int64_t)b.rows * b.cols;
+    }
+    *n_blocks = (int32_t)t.sites[site].size();
+    *n_elements = total;
+    return LCC_OK;
+  });
+}
+
 lcc_status lcc_mps_expectation(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps, int32_t site,
                                double* value) {
   if (!ham || !mps || !value) return fail(ctx, LCC_ERR_ARG, "NULL argument");

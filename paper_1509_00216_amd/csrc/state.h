@@ -302,6 +302,9 @@ void sweep_retreat(Sweep& s, const double* x, int m_max, lcc_sweep_info* info);
 void sweep_copy_guess(Sweep& s, double* x);
 const std::vector<double>& sweep_singular_values(Sweep& s);
 int sweep_site(const Sweep& s);
+void sweep_split_block(Sweep& s, const double* x, int m_max, lcc_sweep_info* info);
+const Bond& sweep_bond(const Sweep& s, int j);
+const DeviceMps& sweep_site_tensor(const Sweep& s, int j);
 void sweep_attach_reference(Sweep& s, const Hamiltonian& op, const Hamiltonian* u, const lcc_mps_desc& ref);
 void sweep_first_order_rhs(Sweep& s, double c, double* b, double* v, double* v_norm);
 void sweep_u_expectation(Sweep& s, const double* x, double* xux, double* xx);

@@ -787,6 +787,100 @@ void sweep_retreat(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
   S.site = prev;
 }
 
+// Split the block tensor x in place (no move): site l gets the left-canonical factor, site l+1
+// the right factor scaled by the singular values, bond l+1 the kept states.  The environments
+// and the local problem of the block stay as they are.
+void sweep_split_block(Sweep& S, const double* x, int m_max, lcc_sweep_info* info) {
+  hipStream_t st = S.ctx->stream;
+  typedef std::chrono::steady_clock clk;
+  const clk::time_point t_start = clk::now();
+  if (m_max < 1) throw Error{LCC_ERR_ARG, "m_max must be >= 1"};
+  const int K = S.K, l = S.site;
+  Env& E = *S.env;
+  const int nsec = (int)E.sectors.size();
+  SplitResult R = split_block(S, x, m_max);
+  S.last_sv = R.sv;
+  const std::vector<int>& keep = R.keep;
+  DeviceMps a, b;
+  a.K = b.K = K;
+  a.bonds.resize(K + 1);
+  b.bonds.resize(K + 1);
+  a.bonds[l] = S.bonds[l];
+  a.bonds[l + 1] = R.nb;
+  b.bonds[l + 1] = R.nb;
+  b.bonds[l + 2] = S.bonds[l + 2];
+  a.sites.resize(K);
+  b.sites.resize(K);
+  int64_t na = 0, nb = 0;
+  for (int q = 0; q < nsec; ++q) {
+    if (keep[q] == 0) continue;
+    const MiddleSector& M = E.sectors[q];
+    for (size_t i = 0; i < M.rows.size(); ++i) {
+      SiteBlock sb{M.rows[i].first, M.rows[i].second, R.new_index[q], na, S.bonds[l].dim[M.rows[i].first], keep[q]};
+      na += (int64_t)sb.rows * sb.cols;
+      a.sites[l].push_back(sb);
+    }
+    for (size_t i = 0; i < M.cols.size(); ++i) {
+      SiteBlock sb{R.new_index[q], M.cols[i].first, M.cols[i].second, nb, keep[q], S.bonds[l + 2].dim[M.cols[i].second]};
+      nb += (int64_t)sb.rows * sb.cols;
+      b.sites[l + 1].push_back(sb);
+    }
+  }
+  a.data.alloc(sizeof(double) * std::max<int64_t>(na, 1));
+  b.data.alloc(sizeof(double) * std::max<int64_t>(nb, 1));
+  // S V^T of each kept sector (keep x ncols, row-major)
+  DevBuf C;
+  std::vector<int64_t> c_off(nsec, -1);
+  int64_t c_tot = 0;
+  for (int q = 0; q < nsec; ++q)
+    if (keep[q] > 0) {
+      c_off[q] = c_tot;
+      c_tot += (int64_t)keep[q] * E.sectors[q].ncols;
+    }
+  C.alloc(sizeof(double) * std::max<int64_t>(c_tot, 1));
+  size_t ia = 0, ib = 0;
+  for (int q = 0; q < nsec; ++q) {
+    if (keep[q] == 0) continue;
+    const MiddleSector& M = E.sectors[q];
+    const SplitSector& p = R.sp[q];
+    const int64_t n = (int64_t)keep[q] * M.ncols;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, st, C.as<double>() + c_off[q],
+                       R.U.as<double>() + p.u_off, R.Sv.as<double>() + p.s_off, keep[q], M.ncols, M.ncols);
+    for (size_t i = 0; i < M.rows.size(); ++i, ++ia) {
+      const SiteBlock& sb = a.sites[l][ia];
+      check_hip(hipMemcpy2DAsync(a.data.as<double>() + sb.off, sizeof(double) * sb.cols,
+                                 R.V.as<double>() + p.v_off + (int64_t)M.row_off[i] * p.r, sizeof(double) * p.r,
+                                 sizeof(double) * sb.cols, sb.rows, hipMemcpyDeviceToDevice, st),
+                "A block copy");
+    }
+    for (size_t i = 0; i < M.cols.size(); ++i, ++ib) {
+      const SiteBlock& sb = b.sites[l + 1][ib];
+      check_hip(hipMemcpy2DAsync(b.data.as<double>() + sb.off, sizeof(double) * sb.cols,
+                                 C.as<double>() + c_off[q] + M.col_off[i], sizeof(double) * M.ncols,
+                                 sizeof(double) * sb.cols, sb.rows, hipMemcpyDeviceToDevice, st),
+                "SV block copy");
+    }
+  }
+  check_hip(hipGetLastError(), "split block");
+  check_hip(hipStreamSynchronize(st), "split block");
+  S.t[l] = std::move(a);
+  S.t[l + 1] = std::move(b);
+  S.bonds[l + 1] = R.nb;
+  fill_info(R, l, 0.f, 0.f,
+            (float)std::chrono::duration<double, std::milli>(clk::now() - t_start).count(), info);
+}
+
+const Bond& sweep_bond(const Sweep& S, int j) {
+  if (j < 0 || j > S.K) throw Error{LCC_ERR_ARG, "bond index out of range"};
+  return S.bonds[j];
+}
+
+const DeviceMps& sweep_site_tensor(const Sweep& S, int j) {
+  if (j < 0 || j >= S.K) throw Error{LCC_ERR_ARG, "site index out of range"};
+  return S.t[j];
+}
+
 void sweep_copy_guess(Sweep& S, double* x) {
   hipStream_t st = S.ctx->stream;
   if (S.have_guess)

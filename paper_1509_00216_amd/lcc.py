@@ -32,7 +32,7 @@ EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_c
            "lcc_lowest_eigenvalue_noalloc", "lcc_build_transition_environments", "lcc_env_input_layout",
            "lcc_env_ket_tensor", "lcc_env_diagonal", "lcc_sweep_retreat", "lcc_sweep_position",
            "lcc_sweep_attach_reference", "lcc_sweep_first_order_rhs", "lcc_sweep_u_expectation",
-           "lcc_mps_expectation"]
+           "lcc_mps_expectation", "lcc_sweep_split_block", "lcc_sweep_bond", "lcc_sweep_site_tensor"]
 
 
 class LccError(RuntimeError):
@@ -93,6 +93,11 @@ class TuneInfo(C.Structure):
     _fields_ = [("tile_overhead", C.c_double), ("split_k", C.c_int64), ("candidates", C.c_int32),
                 ("launches", C.c_int32), ("packed_launches", C.c_int32), ("from_cache", C.c_int32),
                 ("p2_order", C.c_int32), ("t_colmajor", C.c_int32), ("ms_before", C.c_float), ("ms_after", C.c_float)]
+
+
+class SiteBlock(C.Structure):
+    _fields_ = [("left", C.c_int32), ("s", C.c_int32), ("right", C.c_int32), ("rows", C.c_int32),
+                ("cols", C.c_int32), ("offset", C.c_int64)]
 
 
 class SweepInfo(C.Structure):
@@ -163,6 +168,10 @@ def library() -> C.CDLL:
         "lcc_sweep_first_order_rhs": (C.c_int32, [P, C.c_double, P, P, C.POINTER(C.c_double)]),
         "lcc_sweep_u_expectation": (C.c_int32, [P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "lcc_mps_expectation": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(C.c_double)]),
+        "lcc_sweep_split_block": (C.c_int32, [P, P, C.c_int32, C.POINTER(SweepInfo)]),
+        "lcc_sweep_bond": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(Sector)]),
+        "lcc_sweep_site_tensor": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                              C.POINTER(SiteBlock), C.POINTER(C.c_double)]),
         "lcc_batch_destroy": (None, [P]),
         "lcc_batch_solve": (C.c_int32, [P, C.POINTER(SolveOpts), C.POINTER(P), C.POINTER(C.c_double), C.POINTER(P),
                                         C.POINTER(P), C.POINTER(SolveInfo)]),
@@ -603,6 +612,7 @@ class Sweep:
         del keep
         self.handle = h
         self.ham = ham  # the sweep refers to the Hamiltonian's MPO
+        self.n_sites = mps["n_sites"]
 
     def close(self):
         if self.handle:
@@ -660,6 +670,45 @@ class Sweep:
         _check(library().lcc_sweep_first_order_rhs(self.handle, float(c), C.c_void_p(b.data_ptr()),
                                                    C.c_void_p(v.data_ptr()), C.byref(n)), self.ctx.handle)
         return n.value
+
+    def split_block(self, x, m_max: int) -> dict:
+        info = SweepInfo()
+        _check(library().lcc_sweep_split_block(self.handle, C.c_void_p(x.data_ptr()), int(m_max), C.byref(info)),
+               self.ctx.handle)
+        return self._info(info)
+
+    def bond(self, j: int) -> list:
+        lib = library()
+        n = C.c_int32(0)
+        _check(lib.lcc_sweep_bond(self.handle, j, C.byref(n), None), self.ctx.handle)
+        arr = (Sector * max(n.value, 1))()
+        _check(lib.lcc_sweep_bond(self.handle, j, C.byref(n), arr), self.ctx.handle)
+        return [(arr[i].n, arr[i].two_sz, arr[i].dim) for i in range(n.value)]
+
+    def site_tensor(self, j: int) -> list:
+        """Blocks [(left sector, s, right sector, array)] of site j (copied to the host)."""
+        lib = library()
+        nb, ne = C.c_int32(0), C.c_int64(0)
+        _check(lib.lcc_sweep_site_tensor(self.handle, j, C.byref(nb), C.byref(ne), None, None), self.ctx.handle)
+        blocks = (SiteBlock * max(nb.value, 1))()
+        data = np.zeros(max(ne.value, 1))
+        _check(lib.lcc_sweep_site_tensor(self.handle, j, C.byref(nb), C.byref(ne), blocks, _dptr(data)),
+               self.ctx.handle)
+        out = []
+        for i in range(nb.value):
+            b = blocks[i]
+            a = data[b.offset:b.offset + b.rows * b.cols].reshape(b.rows, b.cols).copy()
+            out.append((b.left, b.s, b.right, a))
+        return out
+
+    def export_mps(self, x, m_max: int, n_elec: int, two_sz: int) -> dict:
+        """The sweep's MPS with the block tensor x split in place, as an MPS dict canonical
+        around the current block."""
+        self.split_block(x, m_max)
+        K = self.n_sites
+        return {"n_sites": K, "n_elec": n_elec, "two_sz": two_sz, "center": self.position(),
+                "bonds": [self.bond(j) for j in range(K + 1)],
+                "sites": [self.site_tensor(j) for j in range(K)]}
 
     def u_expectation(self, x) -> tuple:
         """(x^T U_eff x, x^T x) of the block tensor x."""
@@ -741,5 +790,39 @@ def first_order_sweeps(ctx: Context, h0: Hamiltonian, op: Hamiltonian, psi1: dic
             out["e3"] = xux - e1 * xx
             out["norm2"] = xx
         return out
+    finally:
+        sw.close()
+
+
+def dmrg_sweeps(ctx: Context, ham: Hamiltonian, mps: dict, m_max: int, sweeps: int = 2, steps: int = 40,
+                tol: float = 1e-10, max_restarts: int = 50) -> dict:
+    """Two-site DMRG on the device: at every block the lowest eigenpair of H_eff (restarted
+    Lanczos, lcc_lowest_eigenpair, started from the sweep's guess), then the split and move
+    (lcc_sweep_advance / _retreat); a sweep visits every block once, alternating direction from
+    mps["center"].  Returns the Ritz value of every block and the final MPS (read out with
+    lcc_sweep_split_block at the last block).  Sequences library calls only."""
+    import torch
+    K = mps["n_sites"]
+    dev = torch.device("cuda", ctx.device if ctx.device >= 0 else 0)
+    sw = Sweep(ctx, ham, mps, mps["center"])
+    try:
+        energies = []
+        direction = 1 if sw.position() < K - 2 else -1
+        x = None
+        for s in range(sweeps):
+            while True:
+                env = sw.env()
+                x = torch.empty(env.n, dtype=torch.float64, device=dev)
+                sw.guess(x)
+                info = env.lowest_eigenpair(x, steps=steps, max_restarts=max_restarts, tol=tol, seed=s + 1)
+                energies.append(info["theta"])
+                if sw.position() == (K - 2 if direction > 0 else 0):
+                    break
+                (sw.advance if direction > 0 else sw.retreat)(x, m_max)
+            if s + 1 < sweeps:
+                direction = -direction
+                (sw.advance if direction > 0 else sw.retreat)(x, m_max)
+        out_mps = sw.export_mps(x, m_max, mps["n_elec"], mps["two_sz"])
+        return {"energies": energies, "energy": energies[-1], "mps": out_mps}
     finally:
         sw.close()
