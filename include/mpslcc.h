@@ -254,8 +254,11 @@ lcc_status lcc_env_profile_launches(lcc_env env, lcc_precision precision, const 
  * elements, of the tile-shape choice; split_k in {512, 1024, 2048}: accumulation length of
  * a phase-2 split-K part; p2_order in {0, 1}: phase-2 output blocks one after the other, or
  * their parts interleaved by channel so that parts reading the same intermediate columns are
- * neighbours; t_colmajor in {0, 1}: the phase-1 intermediate stored row- or column-major,
- * the latter computed as X^T Lt^T so that phase 2 reads long contiguous columns) and, per GEMM
+ * neighbours; t_colmajor in {0, 1, 2}: the left enlarged operator first with its intermediate
+ * T = Lt X stored row- or column-major (the latter computed as X^T Lt^T so that phase 2 reads
+ * long contiguous columns), or the right enlarged operator first, T = X Rt^T row-major and
+ * Y += Lt T, which moves the short left-operator products into the accumulation chains; the
+ * same flops either way) and, per GEMM
  * launch, both kernels (term walk / packed k), with
  * `reps` timed applications of `precision` per measurement; keeps the fastest plan and
  * chooses the kernels of all three precisions on it.  With a tuning cache set on the
@@ -272,7 +275,7 @@ typedef struct {
   int32_t packed_launches;    /* ... of which use the packed-k kernel for `precision` */
   int32_t from_cache;         /* 1 if the entry came from the cache */
   int32_t p2_order;           /* phase-2 group order: 0 output-major, 1 channel-major */
-  int32_t t_colmajor;         /* intermediate T blocks: 0 row-major, 1 column-major */
+  int32_t t_colmajor;         /* 0 / 1: left operator first, T row- / column-major; 2: right operator first */
   float ms_before, ms_after;  /* one H_eff x of `precision`, summed launch times */
 } lcc_tune_info;
 lcc_status lcc_env_autotune(lcc_env env, lcc_precision precision, int32_t reps, lcc_tune_info* info);

@@ -128,7 +128,7 @@ lcc_status lcc_context_set_overlap(lcc_context ctx, int32_t side_streams) {
 lcc_status lcc_context_set_plan(lcc_context ctx, double tile_overhead, int64_t split_k, int32_t p2_order,
                                 int32_t t_colmajor) {
   if (!ctx) return fail(nullptr, LCC_ERR_ARG, "ctx is NULL");
-  if (!(tile_overhead >= 0) || split_k < 1 || (p2_order != 0 && p2_order != 1) || (t_colmajor != 0 && t_colmajor != 1))
+  if (!(tile_overhead >= 0) || split_k < 1 || (p2_order != 0 && p2_order != 1) || t_colmajor < 0 || t_colmajor > 2)
     return fail(ctx, LCC_ERR_ARG, "invalid planner parameters");
   ctx->c.plan_params.tile_overhead = tile_overhead;
   ctx->c.plan_params.split_k = split_k;

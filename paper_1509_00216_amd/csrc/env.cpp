@@ -695,6 +695,18 @@ void plan_env(Env& E, const PlanParams& pp) {
     const int w1 = std::get<0>(kv.first);
     for (const auto& src : kv.second) ract[(size_t)w1 * nsec + col_at_in[{std::get<0>(src), std::get<1>(src)}].first] = 1;
   }
+  // Two orders of the factorised product.  Left first (t_colmajor 0 or 1): T_{w1,m} = Lt^{w1} X_m
+  // (nrows(m') x ncols(m), stored row- or column-major), then Y_{m'} += T Rt^{w1 T} with chains
+  // over (w1, column blocks of m).  Right first (t_colmajor 2): T_{w1,m} = X_m Rt^{w1 T}
+  // (nrows(m) x ncols(m'), row-major), then Y_{m'} += Lt^{w1} T with chains over (w1, row blocks
+  // of m).  The flops are the same; the left enlarged operator has about one source block per
+  // output row block, so left first gives short independent phase-1 products and right first
+  // puts those short products in the accumulation chains.
+  const bool right_first = pp.t_colmajor == 2;
+  auto t_size = [&](int m, int mp) -> int64_t {
+    return right_first ? (int64_t)env->sectors_in[m].nrows * env->sectors[mp].ncols
+                       : (int64_t)env->sectors[mp].nrows * env->sectors_in[m].ncols;
+  };
   // Channels are taken in order and cut into chunks whose intermediates fit the workspace
   // budget; each chunk reuses the same intermediate buffer (and, when small, stays in the
   // last-level cache between its two phases).
@@ -709,7 +721,7 @@ void plan_env(Env& E, const PlanParams& pp) {
       if (!lact[(size_t)w1 * nsec + m] || !ract[(size_t)w1 * nsec + m]) continue;
       auto it = sec_index.find(env->sectors_in[m].q + dq_mid[w1]);
       if (it == sec_index.end()) continue;
-      need += (int64_t)env->sectors[it->second].nrows * env->sectors_in[m].ncols;
+      need += t_size(m, it->second);
     }
     if (used > 0 && used + need > budget) {
       ++nchunks;
@@ -721,48 +733,72 @@ void plan_env(Env& E, const PlanParams& pp) {
       auto it = sec_index.find(env->sectors_in[m].q + dq_mid[w1]);
       if (it == sec_index.end()) continue;
       t_off[(size_t)w1 * nsec + m] = used;
-      used += (int64_t)env->sectors[it->second].nrows * env->sectors_in[m].ncols;
+      used += t_size(m, it->second);
     }
     t_max = std::max(t_max, used);
   }
   env->t_elems = t_max;
   env->tbuf.alloc(sizeof(double) * std::max<int64_t>(t_max, 1));
 
-  // ---- phase 1: T_{w1,m}[(a',s1') rows] = sum Lt^{w1}[(a',s1'),(a,s1)] X_m[(a,s1) rows]
   std::vector<GemmBuilder> p1(nchunks);
-  for (int w1 = 0; w1 < D; ++w1)
-    for (int m = 0; m < nsec; ++m) {
-      const int64_t to = t_off[(size_t)w1 * nsec + m];
-      if (to < 0) continue;
-      GemmBuilder& B1 = p1[chunk_of[w1]];
-      const MiddleSector& S = env->sectors_in[m];
-      const MiddleSector& Sp = env->sectors[sec_index[S.q + dq_mid[w1]]];
-      for (size_t i = 0; i < Sp.rows.size(); ++i) {
-        const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
-        // row-major T: the block of rows (a',s1') is Lt X;  column-major T: its transpose,
-        // X^T Lt^T, is a row-major (ncols x dim a') block with leading dimension nrows(q')
-        if (pp.t_colmajor)
-          B1.group(BASE_T, to + Sp.row_off[i], Sp.nrows, S.ncols, bl.dim[ap], false);
-        else
-          B1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
-        auto it = lt.find(std::make_tuple(w1, ap, sp));
-        if (it == lt.end()) continue;
-        for (const auto& src : it->second) {
-          const auto ra = row_at_in[{std::get<0>(src), std::get<1>(src)}];
-          if (ra.first != m) continue;
-          const OperandRef& ref = std::get<2>(src);
-          const int ka = bl0.dim[std::get<0>(src)];
-          const int64_t x_off = S.off + (int64_t)S.row_off[ra.second] * S.ncols;
+  if (!right_first) {
+    // ---- phase 1: T_{w1,m}[(a',s1') rows] = sum Lt^{w1}[(a',s1'),(a,s1)] X_m[(a,s1) rows]
+    for (int w1 = 0; w1 < D; ++w1)
+      for (int m = 0; m < nsec; ++m) {
+        const int64_t to = t_off[(size_t)w1 * nsec + m];
+        if (to < 0) continue;
+        GemmBuilder& B1 = p1[chunk_of[w1]];
+        const MiddleSector& S = env->sectors_in[m];
+        const MiddleSector& Sp = env->sectors[sec_index[S.q + dq_mid[w1]]];
+        for (size_t i = 0; i < Sp.rows.size(); ++i) {
+          const int ap = Sp.rows[i].first, sp = Sp.rows[i].second;
+          // row-major T: the block of rows (a',s1') is Lt X;  column-major T: its transpose,
+          // X^T Lt^T, is a row-major (ncols x dim a') block with leading dimension nrows(q')
           if (pp.t_colmajor)
-            B1.term(BASE_X, x_off, S.ncols, ref.base, ref.off, ka, ka, ref.alpha);
+            B1.group(BASE_T, to + Sp.row_off[i], Sp.nrows, S.ncols, bl.dim[ap], false);
           else
-            B1.term(ref.base, ref.off, ka, BASE_X, x_off, S.ncols, ka, ref.alpha);
+            B1.group(BASE_T, to + (int64_t)Sp.row_off[i] * S.ncols, S.ncols, bl.dim[ap], S.ncols, false);
+          auto it = lt.find(std::make_tuple(w1, ap, sp));
+          if (it == lt.end()) continue;
+          for (const auto& src : it->second) {
+            const auto ra = row_at_in[{std::get<0>(src), std::get<1>(src)}];
+            if (ra.first != m) continue;
+            const OperandRef& ref = std::get<2>(src);
+            const int ka = bl0.dim[std::get<0>(src)];
+            const int64_t x_off = S.off + (int64_t)S.row_off[ra.second] * S.ncols;
+            if (pp.t_colmajor)
+              B1.term(BASE_X, x_off, S.ncols, ref.base, ref.off, ka, ka, ref.alpha);
+            else
+              B1.term(ref.base, ref.off, ka, BASE_X, x_off, S.ncols, ka, ref.alpha);
+          }
         }
       }
-    }
-  // ---- phase 2: Y_{m'}[:, (s2',b')] = sum_{w1,(s2,b)} T_{w1,m}[:, (s2,b)] Rt^{w1}[(s2',b'),(s2,b)]^T
-  // Each output block's chain is cut at chunk boundaries and, inside a chunk, into parts of
-  // about pp.split_k; parts write partial tiles that one ordered reduction adds into y.
+  } else {
+    // ---- phase 1: T_{w1,m}[:, (s2',b')] = sum X_m[:, (s2,b)] Rt^{w1}[(s2',b'),(s2,b)]^T
+    for (int w1 = 0; w1 < D; ++w1)
+      for (int m = 0; m < nsec; ++m) {
+        const int64_t to = t_off[(size_t)w1 * nsec + m];
+        if (to < 0) continue;
+        GemmBuilder& B1 = p1[chunk_of[w1]];
+        const MiddleSector& S = env->sectors_in[m];
+        const MiddleSector& Sp = env->sectors[sec_index[S.q + dq_mid[w1]]];
+        for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
+          const int s2p = Sp.cols[jx].first, bp = Sp.cols[jx].second;
+          B1.group(BASE_T, to + Sp.col_off[jx], Sp.ncols, S.nrows, br.dim[bp], false);
+          auto it = rt.find(std::make_tuple(w1, s2p, bp));
+          if (it == rt.end()) continue;
+          for (const auto& src : it->second) {
+            const auto ca = col_at_in[{std::get<0>(src), std::get<1>(src)}];
+            if (ca.first != m) continue;
+            const OperandRef& ref = std::get<2>(src);
+            const int kb = br0.dim[std::get<1>(src)];
+            B1.term(BASE_X, S.off + S.col_off[ca.second], S.ncols, ref.base, ref.off, kb, kb, ref.alpha);
+          }
+        }
+      }
+  }
+  // ---- phase 2: each output block's chain is cut at chunk boundaries and, inside a chunk, into
+  // parts of about pp.split_k; parts write partial tiles that one ordered reduction adds into y.
   std::vector<GemmBuilder> p2(nchunks);
   std::vector<ReduceGroup> red;
   int64_t work = 0;
@@ -775,110 +811,153 @@ void plan_env(Env& E, const PlanParams& pp) {
     int ldc = 0, m = 0, n = 0;
     std::vector<GemmTerm> terms;
   };
+  // the parts of one output block (gm x gn at y_off, leading dimension ldc) from its chain
+  auto emit_block = [&](std::vector<Emit>& emits, const std::vector<std::vector<GemmTerm>>& per,
+                        const std::vector<std::vector<int>>& per_w1, int jx, int64_t y_off, int ldc, int gm, int gn) {
+    struct Part { int chunk; size_t b, e; };
+    std::vector<Part> parts;
+    for (int c = 0; c < nchunks; ++c) {
+      const auto& T = per[c];
+      if (T.empty()) continue;
+      int64_t ksum = 0;
+      for (const GemmTerm& t : T) ksum += t.k;
+      int np = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + pp.split_k - 1) / pp.split_k), 64);
+      np = std::min<int>(np, (int)T.size());
+      size_t i = 0;
+      int64_t acc = 0;
+      for (int p = 0; p < np; ++p) {
+        const size_t b0 = i;
+        const int64_t goal = (ksum * (p + 1)) / np;
+        const size_t left = (size_t)(np - p - 1);
+        do {
+          acc += T[i].k;
+          ++i;
+        } while (i < T.size() && acc < goal && (T.size() - i) > left);
+        if (p == np - 1) i = T.size();
+        parts.push_back(Part{c, b0, i});
+      }
+    }
+    if (parts.size() <= 1) {
+      Emit em;
+      em.chunk = parts.empty() ? 0 : parts[0].chunk;
+      em.first_w1 = parts.empty() || parts[0].b == parts[0].e ? -1 : per_w1[em.chunk][parts[0].b];
+      em.jx = jx;
+      em.c_base = BASE_Y;
+      em.c_off = y_off;
+      em.ldc = ldc;
+      em.m = gm;
+      em.n = gn;
+      if (!parts.empty()) em.terms.assign(per[em.chunk].begin() + parts[0].b, per[em.chunk].begin() + parts[0].e);
+      emits.push_back(std::move(em));
+      return;
+    }
+    const int64_t mn = (int64_t)gm * gn;
+    const int64_t woff = work;
+    for (size_t p = 0; p < parts.size(); ++p) {
+      Emit em;
+      em.chunk = parts[p].chunk;
+      em.first_w1 = per_w1[em.chunk][parts[p].b];
+      em.jx = jx;
+      em.c_base = BASE_WORK;
+      em.c_off = woff + (int64_t)p * mn;
+      em.ldc = gn;
+      em.m = gm;
+      em.n = gn;
+      em.terms.assign(per[em.chunk].begin() + parts[p].b, per[em.chunk].begin() + parts[p].e);
+      emits.push_back(std::move(em));
+    }
+    work += (int64_t)parts.size() * mn;
+    ReduceGroup rg{};
+    rg.dst_off = y_off;
+    rg.src_off = woff;
+    rg.ldc = ldc;
+    rg.m = gm;
+    rg.n = gn;
+    rg.parts = (int32_t)parts.size();
+    red.push_back(rg);
+  };
   for (int mp = 0; mp < (int)env->sectors.size(); ++mp) {
     const MiddleSector& Sp = env->sectors[mp];
     std::vector<Emit> emits;
-    for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
-      const int s2p = Sp.cols[jx].first, bp = Sp.cols[jx].second;
-      const int gm = Sp.nrows, gn = br.dim[bp];
-      const int64_t y_off = Sp.off + Sp.col_off[jx];
-      std::vector<std::vector<GemmTerm>> per(nchunks);
-      std::vector<std::vector<int>> per_w1(nchunks);
-      for (int w1 = 0; w1 < D; ++w1) {
-        auto si = sec_index_in.find(Sp.q - dq_mid[w1]);
-        if (si == sec_index_in.end()) continue;
-        const int m = si->second;
-        const int64_t to = t_off[(size_t)w1 * nsec + m];
-        if (to < 0) continue;
-        auto it = rt.find(std::make_tuple(w1, s2p, bp));
-        if (it == rt.end()) continue;
-        const MiddleSector& S = env->sectors_in[m];
-        for (const auto& src : it->second) {
-          const auto ca = col_at_in[{std::get<0>(src), std::get<1>(src)}];
-          if (ca.first != m) continue;
-          const OperandRef& ref = std::get<2>(src);
-          const int kb = br0.dim[std::get<1>(src)];
-          GemmTerm t{};
-          t.a_base = BASE_T;
-          if (pp.t_colmajor) {  // columns (s2,b) of a column-major block: stored k x m
-            t.a_off = to + (int64_t)S.col_off[ca.second] * gm;
-            t.lda = gm;
-          } else {
-            t.a_off = to + S.col_off[ca.second];
-            t.lda = S.ncols;
+    if (!right_first) {
+      // Y_{m'}[:, (s2',b')] = sum_{w1,(s2,b)} T_{w1,m}[:, (s2,b)] Rt^{w1}[(s2',b'),(s2,b)]^T
+      for (size_t jx = 0; jx < Sp.cols.size(); ++jx) {
+        const int s2p = Sp.cols[jx].first, bp = Sp.cols[jx].second;
+        const int gm = Sp.nrows, gn = br.dim[bp];
+        std::vector<std::vector<GemmTerm>> per(nchunks);
+        std::vector<std::vector<int>> per_w1(nchunks);
+        for (int w1 = 0; w1 < D; ++w1) {
+          auto si = sec_index_in.find(Sp.q - dq_mid[w1]);
+          if (si == sec_index_in.end()) continue;
+          const int m = si->second;
+          const int64_t to = t_off[(size_t)w1 * nsec + m];
+          if (to < 0) continue;
+          auto it = rt.find(std::make_tuple(w1, s2p, bp));
+          if (it == rt.end()) continue;
+          const MiddleSector& S = env->sectors_in[m];
+          for (const auto& src : it->second) {
+            const auto ca = col_at_in[{std::get<0>(src), std::get<1>(src)}];
+            if (ca.first != m) continue;
+            const OperandRef& ref = std::get<2>(src);
+            const int kb = br0.dim[std::get<1>(src)];
+            GemmTerm t{};
+            t.a_base = BASE_T;
+            if (pp.t_colmajor) {  // columns (s2,b) of a column-major block: stored k x m
+              t.a_off = to + (int64_t)S.col_off[ca.second] * gm;
+              t.lda = gm;
+            } else {
+              t.a_off = to + S.col_off[ca.second];
+              t.lda = S.ncols;
+            }
+            t.b_base = ref.base;
+            t.b_off = ref.off;
+            t.ldb = kb;
+            t.k = kb;
+            t.alpha = ref.alpha;
+            per[chunk_of[w1]].push_back(t);
+            per_w1[chunk_of[w1]].push_back(w1);
+            flops2 += 2.0 * gm * (double)gn * kb;
           }
-          t.b_base = ref.base;
-          t.b_off = ref.off;
-          t.ldb = kb;
-          t.k = kb;
-          t.alpha = ref.alpha;
-          per[chunk_of[w1]].push_back(t);
-          per_w1[chunk_of[w1]].push_back(w1);
-          flops2 += 2.0 * gm * (double)gn * kb;
         }
+        emit_block(emits, per, per_w1, (int)jx, Sp.off + Sp.col_off[jx], Sp.ncols, gm, gn);
       }
-      struct Part { int chunk; size_t b, e; };
-      std::vector<Part> parts;
-      for (int c = 0; c < nchunks; ++c) {
-        const auto& T = per[c];
-        if (T.empty()) continue;
-        int64_t ksum = 0;
-        for (const GemmTerm& t : T) ksum += t.k;
-        int np = (int)std::min<int64_t>(std::max<int64_t>(1, (ksum + pp.split_k - 1) / pp.split_k), 64);
-        np = std::min<int>(np, (int)T.size());
-        size_t i = 0;
-        int64_t acc = 0;
-        for (int p = 0; p < np; ++p) {
-          const size_t b0 = i;
-          const int64_t goal = (ksum * (p + 1)) / np;
-          const size_t left = (size_t)(np - p - 1);
-          do {
-            acc += T[i].k;
-            ++i;
-          } while (i < T.size() && acc < goal && (T.size() - i) > left);
-          if (p == np - 1) i = T.size();
-          parts.push_back(Part{c, b0, i});
+    } else {
+      // Y_{m'}[(a',s1') rows, :] = sum_{w1,(a,s1)} Lt^{w1}[(a',s1'),(a,s1)] T_{w1,m}[(a,s1) rows, :]
+      for (size_t ix = 0; ix < Sp.rows.size(); ++ix) {
+        const int ap = Sp.rows[ix].first, sp = Sp.rows[ix].second;
+        const int gm = bl.dim[ap], gn = Sp.ncols;
+        std::vector<std::vector<GemmTerm>> per(nchunks);
+        std::vector<std::vector<int>> per_w1(nchunks);
+        for (int w1 = 0; w1 < D; ++w1) {
+          auto si = sec_index_in.find(Sp.q - dq_mid[w1]);
+          if (si == sec_index_in.end()) continue;
+          const int m = si->second;
+          const int64_t to = t_off[(size_t)w1 * nsec + m];
+          if (to < 0) continue;
+          auto it = lt.find(std::make_tuple(w1, ap, sp));
+          if (it == lt.end()) continue;
+          const MiddleSector& S = env->sectors_in[m];
+          for (const auto& src : it->second) {
+            const auto ra = row_at_in[{std::get<0>(src), std::get<1>(src)}];
+            if (ra.first != m) continue;
+            const OperandRef& ref = std::get<2>(src);
+            const int ka = bl0.dim[std::get<0>(src)];
+            GemmTerm t{};
+            t.a_base = ref.base;
+            t.a_off = ref.off;
+            t.lda = ka;
+            t.b_base = BASE_T;
+            t.b_off = to + (int64_t)S.row_off[ra.second] * Sp.ncols;
+            t.ldb = Sp.ncols;
+            t.k = ka;
+            t.alpha = ref.alpha;
+            per[chunk_of[w1]].push_back(t);
+            per_w1[chunk_of[w1]].push_back(w1);
+            flops2 += 2.0 * gm * (double)gn * ka;
+          }
         }
+        emit_block(emits, per, per_w1, (int)ix, Sp.off + (int64_t)Sp.row_off[ix] * Sp.ncols, Sp.ncols, gm, gn);
       }
-      if (parts.size() <= 1) {
-        Emit em;
-        em.chunk = parts.empty() ? 0 : parts[0].chunk;
-        em.first_w1 = parts.empty() || parts[0].b == parts[0].e ? -1 : per_w1[em.chunk][parts[0].b];
-        em.jx = (int)jx;
-        em.c_base = BASE_Y;
-        em.c_off = y_off;
-        em.ldc = Sp.ncols;
-        em.m = gm;
-        em.n = gn;
-        if (!parts.empty())
-          em.terms.assign(per[em.chunk].begin() + parts[0].b, per[em.chunk].begin() + parts[0].e);
-        emits.push_back(std::move(em));
-        continue;
-      }
-      const int64_t mn = (int64_t)gm * gn;
-      const int64_t woff = work;
-      for (size_t p = 0; p < parts.size(); ++p) {
-        Emit em;
-        em.chunk = parts[p].chunk;
-        em.first_w1 = per_w1[em.chunk][parts[p].b];
-        em.jx = (int)jx;
-        em.c_base = BASE_WORK;
-        em.c_off = woff + (int64_t)p * mn;
-        em.ldc = gn;
-        em.m = gm;
-        em.n = gn;
-        em.terms.assign(per[em.chunk].begin() + parts[p].b, per[em.chunk].begin() + parts[p].e);
-        emits.push_back(std::move(em));
-      }
-      work += (int64_t)parts.size() * mn;
-      ReduceGroup rg{};
-      rg.dst_off = y_off;
-      rg.src_off = woff;
-      rg.ldc = Sp.ncols;
-      rg.m = gm;
-      rg.n = gn;
-      rg.parts = (int32_t)parts.size();
-      red.push_back(rg);
     }
     // Emission order of the sector's groups.  Output-major (0): block by block, each block's
     // parts in channel order.  Channel-major (1): by the first channel of each part, so that
@@ -902,8 +981,14 @@ void plan_env(Env& E, const PlanParams& pp) {
   env->plan.flops2 = flops2;
   env->plan.chunks.resize(nchunks);
   for (int c = 0; c < nchunks; ++c) {
-    env->plan.chunks[c].phase1 = finalize(p1[c], pp.t_colmajor != 0, pp.t_colmajor != 0, st, pp.tile_overhead);
-    env->plan.chunks[c].phase2 = finalize(p2[c], pp.t_colmajor != 0, true, st, pp.tile_overhead, pp.p2_order == 0);
+    if (right_first) {
+      // phase 1: A = X (row-major), B = Rt (stored n-major); phase 2: A = Lt, B = T (row-major)
+      env->plan.chunks[c].phase1 = finalize(p1[c], false, true, st, pp.tile_overhead);
+      env->plan.chunks[c].phase2 = finalize(p2[c], false, false, st, pp.tile_overhead, pp.p2_order == 0);
+    } else {
+      env->plan.chunks[c].phase1 = finalize(p1[c], pp.t_colmajor != 0, pp.t_colmajor != 0, st, pp.tile_overhead);
+      env->plan.chunks[c].phase2 = finalize(p2[c], pp.t_colmajor != 0, true, st, pp.tile_overhead, pp.p2_order == 0);
+    }
   }
   {
     std::vector<ReduceTile> rtl;

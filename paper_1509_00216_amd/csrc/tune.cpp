@@ -3,7 +3,8 @@
 // The block-size histogram of a two-site problem (bond sectors and their dimensions, the MPO
 // bond dimension) fixes the shapes of all block products.  For a histogram the tuner times,
 // on the device, every candidate of the planner parameters (the per-tile cost that picks tile
-// shapes, the split-K length and the group order of phase 2, the layout of the intermediate) and, for every launch of a plan, both GEMM kernels
+// shapes, the split-K length and the group order of phase 2, the order of the two enlarged
+// operators and the layout of the intermediate) and, for every launch of a plan, both GEMM kernels
 // (term walk, packed k), then keeps the fastest plan and per-launch kernel choice.  The result
 // is stored in a text cache keyed by a signature of the histogram, so that later environments
 // with the same histogram (the same site of another sweep, another process) are planned the
@@ -130,7 +131,7 @@ double choose_kernels(Env& env, int precision, const void* x, void* y, int reps)
 }  // namespace
 
 // Bumped whenever the planner or the kernel set changes what a cached entry means.
-constexpr int64_t kPlannerVersion = 2;
+constexpr int64_t kPlannerVersion = 3;
 
 uint64_t histogram_signature(const Env& env) {
   uint64_t h = 1469598103934665603ull;
@@ -196,7 +197,7 @@ void autotune(Env& env, int precision, int reps, lcc_tune_info* info) {
     for (double ov : kOverheads)
       for (int64_t sk : kSplits)
       for (int order = 0; order < 2; ++order)
-      for (int cm = 0; cm < 2; ++cm) {
+      for (int cm = 0; cm < 3; ++cm) {
         PlanParams pp;
         pp.tile_overhead = ov;
         pp.split_k = sk;

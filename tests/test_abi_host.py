@@ -111,9 +111,10 @@ def test_argument_errors():
     assert e.value.code == -7
     # planner and scheduling setters validate their arguments on a host-only context
     ctx.set_plan(8192.0, 1024, 1, 1)
+    ctx.set_plan(8192.0, 1024, 1, 2)
     ctx.set_overlap(0)
     for bad in ((float("nan"), 1024, 0, 0), (-1.0, 1024, 0, 0), (2048.0, 0, 0, 0), (2048.0, 1024, 2, 0),
-                (2048.0, 1024, 0, 2)):
+                (2048.0, 1024, 0, 3), (2048.0, 1024, 0, -1)):
         with pytest.raises(lcc.LccError) as e:
             ctx.set_plan(*bad)
         assert e.value.code == -1, bad
