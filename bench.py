@@ -509,7 +509,7 @@ def main():
     t_env = time.perf_counter() - t0
     f1, f2 = env.flops()
     F = f1 + f2
-    log(f"[bench] environments in {t_env:.2f}s: n={env.n} D_mid={env.mpo_bond_dim} F_alg={F:.4e} (phase1 {f1:.3e}, phase2 {f2:.3e})")
+    log(f"[bench] environments in {t_env:.2f}s: n={env.n} D_mid={env.mpo_bond_dim} F_alg={F:.4e} (left operator {f1:.3e}, right operator {f2:.3e})")
     tune = None
     if not args.no_tune:
         t0 = time.perf_counter()
@@ -533,7 +533,7 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.apply_only
         print(json.dumps({"mode": "apply-only", "workload": args.workload, "precision": prec, "applies": args.apply_only,
-                          "ms_per_apply": ms, "flops_per_apply": F, "phase1_flops": f1, "phase2_flops": f2,
+                          "ms_per_apply": ms, "flops_per_apply": F, "left_flops": f1, "right_flops": f2,
                           "gflops": F / (ms * 1e-3) / 1e9, "copy_bytes": src.numel() * 8}), flush=True)
         return
     e0, e0_rule = shift_for(spec, env, args.workload)

@@ -88,7 +88,7 @@ lcc_status lcc_context_set_overlap(lcc_context ctx, int32_t side_streams);
  * The path is copied. */
 lcc_status lcc_context_set_tune_cache(lcc_context ctx, const char* path);
 /* Planner parameters for environments built afterwards on this context when no tuning-cache
- * entry applies (meanings as in lcc_tune_info; defaults 2048, 2048, 0, 0). */
+ * entry applies (meanings as in lcc_tune_info; defaults 2048, 2048, 0, 2). */
 lcc_status lcc_context_set_plan(lcc_context ctx, double tile_overhead, int64_t split_k, int32_t p2_order,
                                 int32_t t_colmajor);
 
@@ -210,9 +210,10 @@ lcc_status lcc_env_ket_tensor(lcc_env env, double* x_dev);
  * double*, lcc_env_layout length.  LCC_ERR_STATE for a transition operator.  Synchronous. */
 lcc_status lcc_env_diagonal(lcc_env env, double* d_dev);
 
-/* Flop counts of one H_eff x: 2*m*n*k summed over every block product the plan performs
- * (phase 1: enlarged left operator times x; phase 2: times enlarged right operator).
- * Only symmetry-allowed blocks and nonzero MPO entries are counted; no padding. */
+/* Flop counts of one H_eff x: 2*m*n*k summed over every block product the plan performs,
+ * split into the products with the enlarged left operator (phase1) and with the enlarged
+ * right operator (phase2), whichever order the plan runs them in.  Only symmetry-allowed
+ * blocks and nonzero MPO entries are counted; no padding. */
 lcc_status lcc_env_flops(lcc_env env, double* phase1, double* phase2);
 
 /* y = H_eff x.  precision LCC_FP64: x, y are double*; LCC_FP32 / LCC_BF16X3: float*.

@@ -233,13 +233,17 @@ class MiddleBondEnvironments:
             out[(a, s1, s2, b)] = ys[i][r0:r0 + blk.shape[0], c0:c0 + blk.shape[1]].copy()
         return out
 
-    def apply(self, x: dict, counter: dict | None = None) -> dict:
-        """y = H_eff x.  T_{w1,q} = Lt^{w1} X_q is formed only where Lt^{w1} and Rt^{w1} both
-        read sector q and q + dq(w1) is a sector; `counter` receives the multiply-add work as
-        counter['phase1'] and counter['phase2']."""
+    def apply(self, x: dict, counter: dict | None = None, order: str = "left") -> dict:
+        """y = H_eff x, per (w1, q) pair where Lt^{w1} and Rt^{w1} both read sector q and
+        q' = q + dq(w1) is a sector.  order "left": T = Lt^{w1} X_q, then Y_q' += T Rt^{w1 T};
+        order "right": T = X_q Rt^{w1 T}, then Y_q' += Lt^{w1} T.  `counter` receives the
+        multiply-add work of the products with the enlarged left operator as counter['left']
+        and with the enlarged right operator as counter['right']."""
+        if order not in ("left", "right"):
+            raise ValueError(order)
         cnt = counter if counter is not None else {}
-        cnt.setdefault("phase1", 0)
-        cnt.setdefault("phase2", 0)
+        cnt.setdefault("left", 0)
+        cnt.setdefault("right", 0)
         X = self.to_sectors(x)
         Y = [np.zeros_like(m) for m in X]
         index = {S["q"]: i for i, S in enumerate(self.secs)}
@@ -251,21 +255,26 @@ class MiddleBondEnvironments:
                 mp = index.get((q[0] + self.dq[w1][0], q[1] + self.dq[w1][1]))
                 if mp is None:
                     continue
-                T = np.zeros((self.secs[mp]["nrows"], self.secs[m]["ncols"]))
-                for (tgt, src), blk in self.lt[w1].items():
-                    i, r0 = self.row_at[src]
-                    if i != m:
-                        continue
-                    _, t0 = self.row_at[tgt]
-                    T[t0:t0 + blk.shape[0], :] += blk @ X[m][r0:r0 + blk.shape[1], :]
-                    cnt["phase1"] += 2 * blk.shape[0] * blk.shape[1] * X[m].shape[1]
-                for (tgt, src), blk in self.rt[w1].items():
-                    j, c0 = self.col_at[src]
-                    if j != m:
-                        continue
-                    _, d0 = self.col_at[tgt]
-                    Y[mp][:, d0:d0 + blk.shape[0]] += T[:, c0:c0 + blk.shape[1]] @ blk.T
-                    cnt["phase2"] += 2 * T.shape[0] * blk.shape[1] * blk.shape[0]
+                lt = [(self.row_at[tgt][1], self.row_at[src][1], blk)
+                      for (tgt, src), blk in self.lt[w1].items() if self.row_at[src][0] == m]
+                rt = [(self.col_at[tgt][1], self.col_at[src][1], blk)
+                      for (tgt, src), blk in self.rt[w1].items() if self.col_at[src][0] == m]
+                if order == "left":
+                    T = np.zeros((self.secs[mp]["nrows"], self.secs[m]["ncols"]))
+                    for t0, r0, blk in lt:
+                        T[t0:t0 + blk.shape[0], :] += blk @ X[m][r0:r0 + blk.shape[1], :]
+                        cnt["left"] += 2 * blk.shape[0] * blk.shape[1] * X[m].shape[1]
+                    for d0, c0, blk in rt:
+                        Y[mp][:, d0:d0 + blk.shape[0]] += T[:, c0:c0 + blk.shape[1]] @ blk.T
+                        cnt["right"] += 2 * T.shape[0] * blk.shape[1] * blk.shape[0]
+                else:
+                    T = np.zeros((self.secs[m]["nrows"], self.secs[mp]["ncols"]))
+                    for d0, c0, blk in rt:
+                        T[:, d0:d0 + blk.shape[0]] += X[m][:, c0:c0 + blk.shape[1]] @ blk.T
+                        cnt["right"] += 2 * X[m].shape[0] * blk.shape[1] * blk.shape[0]
+                    for t0, r0, blk in lt:
+                        Y[mp][t0:t0 + blk.shape[0], :] += blk @ T[r0:r0 + blk.shape[1], :]
+                        cnt["left"] += 2 * blk.shape[0] * blk.shape[1] * T.shape[1]
         return self.from_sectors(Y, x)
 
 

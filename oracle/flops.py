@@ -17,11 +17,16 @@ canonical (L, then the MPO pair, then R), with W12^{w,w2} = sum_{w1} W_l^{w,w1} 
 
 factorised over the middle MPO bond (H_eff = sum_{w1} Lt^{w1} (x) Rt^{w1}, where Lt absorbs
 W_l into L and Rt absorbs W_{l+1} into R), with the two-site vector stored per middle-bond
-sector q as a matrix X_q (rows (a, s1), columns (s2, b)):
-  phase 1  T_{w1,q}  = Lt^{w1} X_q    2 M_a' M_a ncols(q) per nonzero block of Lt^{w1}
-  phase 2  Y_{q'}   += T_{w1,q} Rt^{w1 T}   2 nrows(q') M_b M_b' per nonzero block of Rt^{w1}
+sector q as a matrix X_q (rows (a, s1), columns (s2, b)), in either order:
+  left operator first
+    T_{w1,q}  = Lt^{w1} X_q          2 M_a' M_a ncols(q) per nonzero block of Lt^{w1}
+    Y_{q'}   += T_{w1,q} Rt^{w1 T}   2 nrows(q') M_b M_b' per nonzero block of Rt^{w1}
+  right operator first
+    T_{w1,q}  = X_q Rt^{w1 T}        2 nrows(q) M_b M_b' per nonzero block of Rt^{w1}
+    Y_{q'}   += Lt^{w1} T_{w1,q}     2 M_a' M_a ncols(q') per nonzero block of Lt^{w1}
   for the (w1, q) pairs where both Lt^{w1} and Rt^{w1} read sector q and q' = q + dq(w1)
-  is a sector of the block.
+  is a sector of the block.  The counts are reported per operator ('left': products with Lt,
+  'right': products with Rt), whichever runs first.
 
 `mpo` is a dict in the oracle's format (oracle.mpo): per bond the channel shifts 'dq', per
 site 'W' = {(w_in, w_out): 4x4 array}; any exact MPO of the Hamiltonian may be passed.
@@ -230,8 +235,11 @@ def enlarged_structure(mps: dict, mpo: dict):
     return secs, lt, rt
 
 
-def factorised_flops(mps: dict, mpo: dict) -> dict:
-    """Counts of the middle-bond factorisation: {'phase1', 'phase2', 'total'} (integers)."""
+def factorised_flops(mps: dict, mpo: dict, order: str = "left") -> dict:
+    """Counts of the middle-bond factorisation, {'left', 'right', 'total'} (integers), with the
+    left (order "left") or the right (order "right") enlarged operator applied first."""
+    if order not in ("left", "right"):
+        raise ValueError(order)
     l = mps["center"]
     bl, br = mps["bonds"][l], mps["bonds"][l + 2]
     secs, lt, rt = enlarged_structure(mps, mpo)
@@ -252,10 +260,13 @@ def factorised_flops(mps: dict, mpo: dict) -> dict:
             mp = index.get((q[0] + dq[w1][0], q[1] + dq[w1][1]))
             if mp is None:
                 continue
+            # the operand a product with Lt (Rt) multiplies: X_q, or T with the other side done
+            ncols = secs[m]["ncols"] if order == "left" else secs[mp]["ncols"]
+            nrows = secs[mp]["nrows"] if order == "left" else secs[m]["nrows"]
             for (tgt, src) in reads_l[m]:
                 if sec_of_row[tgt] == mp:
-                    p1 += 2 * bl[tgt[0]][2] * bl[src[0]][2] * secs[m]["ncols"]
+                    p1 += 2 * bl[tgt[0]][2] * bl[src[0]][2] * ncols
             for (tgt, src) in reads_r[m]:
                 if sec_of_col[tgt] == mp:
-                    p2 += 2 * secs[mp]["nrows"] * br[src[1]][2] * br[tgt[1]][2]
-    return {"phase1": p1, "phase2": p2, "total": p1 + p2}
+                    p2 += 2 * nrows * br[src[1]][2] * br[tgt[1]][2]
+    return {"left": p1, "right": p2, "total": p1 + p2}

@@ -977,8 +977,9 @@ void plan_env(Env& E, const PlanParams& pp) {
   }
   double flops1 = 0;
   for (const GemmBuilder& B1 : p1) flops1 += B1.flops;
-  env->plan.flops1 = flops1;
-  env->plan.flops2 = flops2;
+  // reported as (enlarged left operator products, enlarged right operator products)
+  env->plan.flops1 = right_first ? flops2 : flops1;
+  env->plan.flops2 = right_first ? flops1 : flops2;
   env->plan.chunks.resize(nchunks);
   for (int c = 0; c < nchunks; ++c) {
     if (right_first) {

@@ -55,7 +55,7 @@ struct PlanParams {
   double tile_overhead = 2048.0;  // per-tile cost, in output elements, of the tile-shape choice
   int64_t split_k = 2048;         // accumulation length per phase-2 part (split-K)
   int p2_order = 0;               // phase-2 group order: 0 output-major, 1 channel-major
-  int t_colmajor = 0;             // 0 / 1: left operator first, T row- / column-major; 2: right operator first
+  int t_colmajor = 2;             // 0 / 1: left operator first, T row- / column-major; 2: right operator first
 };
 
 struct Context {

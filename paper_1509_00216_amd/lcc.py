@@ -244,7 +244,7 @@ class Context:
         """Side streams for the independent launches of one GEMM phase (0 = in order)."""
         _check(library().lcc_context_set_overlap(self.handle, int(side_streams)), self.handle)
 
-    def set_plan(self, tile_overhead: float = 2048.0, split_k: int = 2048, p2_order: int = 0, t_colmajor: int = 0):
+    def set_plan(self, tile_overhead: float = 2048.0, split_k: int = 2048, p2_order: int = 0, t_colmajor: int = 2):
         """Planner parameters of environments built afterwards (when no tuning-cache entry applies)."""
         _check(library().lcc_context_set_plan(self.handle, float(tile_overhead), int(split_k), int(p2_order),
                                               int(t_colmajor)), self.handle)

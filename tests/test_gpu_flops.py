@@ -21,16 +21,18 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("order", ["left", "right"])
 @pytest.mark.parametrize("label,make", CASES, ids=[c[0] for c in CASES])
-def test_planner_flops_equal_oracle_count(label, make):
+def test_planner_flops_equal_oracle_count(label, make, order):
     torch, lcc = need_gpu()
     spec, mps = make()
     ctx = lcc.Context(0)
+    ctx.set_plan(2048.0, 2048, 0, 0 if order == "left" else 2)
     ham = ctx.create_hamiltonian(spec)
-    say(f"[flops] {label}: build")
+    say(f"[flops] {label}, {order} operator first: build")
     env = ctx.build_environments(ham, mps)
     f1, f2 = env.flops()
-    ref = OF.factorised_flops(mps, product_mpo(ham))
-    say(f"  planner {f1:.0f} + {f2:.0f}   oracle {ref['phase1']} + {ref['phase2']}")
-    assert (int(f1), int(f2)) == (ref["phase1"], ref["phase2"])
+    ref = OF.factorised_flops(mps, product_mpo(ham), order)
+    say(f"  planner {f1:.0f} + {f2:.0f}   oracle {ref['left']} + {ref['right']}")
+    assert (int(f1), int(f2)) == (ref["left"], ref["right"])
     assert env.flops_per_apply == float(ref["total"])

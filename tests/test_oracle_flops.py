@@ -2,7 +2,8 @@
 
 The counts are integers computed from block tables only.  They are pinned to
 * the multiply-add work that the oracle's two contractions of H_eff x actually perform
-  (the canonical L, W, R order and the factorisation over the middle MPO bond), counted
+  (the canonical L, W, R order and the factorisation over the middle MPO bond, with either
+  enlarged operator applied first), counted
   product by product while they run, on systems where both contractions are also checked
   against the Fock-space H_eff of O1 (so the counted work is a correct contraction);
 * the O(M^3) cost of the H0 term (Implementation section): scaling every sector dimension
@@ -47,13 +48,14 @@ def test_counts_equal_the_work_of_both_contractions(name):
     can = OF.canonical_flops(mps, mpo)
     assert (can["k1"], can["k2"], can["k3"]) == (cnt["k1"], cnt["k2"], cnt["k3"])
     assert min(can["k1"], can["k2"], can["k3"]) > 0
-    # middle-bond factorisation
-    cnt2 = {}
-    y2 = BS.MiddleBondEnvironments(spec, mps, mpo).apply(x, counter=cnt2)
-    assert np.linalg.norm(BS.flatten(y2, blocks) - y1) <= 1e-13 * np.linalg.norm(y1)
-    fac = OF.factorised_flops(mps, mpo)
-    assert (fac["phase1"], fac["phase2"]) == (cnt2["phase1"], cnt2["phase2"])
-    assert fac["phase1"] > 0 and fac["phase2"] > 0
+    # middle-bond factorisation, both orders
+    for order in ("left", "right"):
+        cnt2 = {}
+        y2 = BS.MiddleBondEnvironments(spec, mps, mpo).apply(x, counter=cnt2, order=order)
+        assert np.linalg.norm(BS.flatten(y2, blocks) - y1) <= 1e-13 * np.linalg.norm(y1)
+        fac = OF.factorised_flops(mps, mpo, order)
+        assert (fac["left"], fac["right"]) == (cnt2["left"], cnt2["right"])
+        assert fac["left"] > 0 and fac["right"] > 0
 
 
 def test_counts_scale_as_the_cube_of_the_bond_dimension():
@@ -62,8 +64,9 @@ def test_counts_scale_as_the_cube_of_the_bond_dimension():
     doubled = dict(mps, bonds=[[(n, z, 2 * d) for n, z, d in bond] for bond in mps["bonds"]])
     a, b = OF.canonical_flops(mps, mpo), OF.canonical_flops(doubled, mpo)
     assert (b["k1"], b["k2"], b["k3"]) == (8 * a["k1"], 4 * a["k2"], 8 * a["k3"])
-    fa, fb = OF.factorised_flops(mps, mpo), OF.factorised_flops(doubled, mpo)
-    assert (fb["phase1"], fb["phase2"]) == (8 * fa["phase1"], 8 * fa["phase2"])
+    for order in ("left", "right"):
+        fa, fb = OF.factorised_flops(mps, mpo, order), OF.factorised_flops(doubled, mpo, order)
+        assert (fb["left"], fb["right"]) == (8 * fa["left"], 8 * fa["right"])
 
 
 def test_count_is_independent_of_vector_values():
@@ -74,7 +77,8 @@ def test_count_is_independent_of_vector_values():
     x = M.random_two_site_vector(mps, 9)
     for k in list(x)[::3]:
         x[k] = np.zeros_like(x[k])
-    cnt = {}
-    BS.MiddleBondEnvironments(spec, mps, mpo).apply(x, counter=cnt)
-    fac = OF.factorised_flops(mps, mpo)
-    assert (fac["phase1"], fac["phase2"]) == (cnt["phase1"], cnt["phase2"])
+    for order in ("left", "right"):
+        cnt = {}
+        BS.MiddleBondEnvironments(spec, mps, mpo).apply(x, counter=cnt, order=order)
+        fac = OF.factorised_flops(mps, mpo, order)
+        assert (fac["left"], fac["right"]) == (cnt["left"], cnt["right"])
