@@ -68,8 +68,11 @@ lcc_status lcc_context_create(int32_t device, void* stream, lcc_context* out) {
       c->c.stream = static_cast<hipStream_t>(stream);
       c->c.dot_partial.alloc(sizeof(double) * kDotBlocks);
       c->c.dot_out.alloc(sizeof(double) * 8);
-      check_hip(hipHostMalloc(reinterpret_cast<void**>(&c->c.host_scalar), sizeof(double) * 8, hipHostMallocDefault),
+      check_hip(hipHostMalloc(reinterpret_cast<void**>(&c->c.host_scalar), sizeof(double) * kHostScalars,
+                              hipHostMallocMapped | hipHostMallocCoherent),
                 "hipHostMalloc");
+      check_hip(hipHostGetDevicePointer(reinterpret_cast<void**>(&c->c.host_scalar_dev), c->c.host_scalar, 0),
+                "hipHostGetDevicePointer");
     }
     *out = c.release();
     return LCC_OK;
@@ -88,6 +91,8 @@ void lcc_context_destroy(lcc_context ctx) {
     }
     for (hipEvent_t e : ctx->c.ev_join) (void)hipEventDestroy(e);
     if (ctx->c.ev_fork) (void)hipEventDestroy(ctx->c.ev_fork);
+    for (hipEvent_t e : ctx->c.ev_status)
+      if (e) (void)hipEventDestroy(e);
     if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
   }
   delete ctx;

@@ -1314,23 +1314,24 @@ void bases_of(Env& env, int precision, const void* x, void* y, Bases<double>& b6
 }
 
 void launch_one(const GemmLaunch& L, int precision, const Bases<double>& b64, const Bases<float>& b32,
-                hipStream_t st) {
+                hipStream_t st, const int* active = nullptr) {
   hipError_t e;
   if (precision == LCC_FP64)
-    e = launch_gemm_f64(L.desc(LCC_FP64), b64, st);
+    e = launch_gemm_f64(L.desc(LCC_FP64), b64, st, nullptr, active);
   else if (precision == LCC_FP32)
-    e = launch_gemm_f32(L.desc(LCC_FP32), b32, st);
+    e = launch_gemm_f32(L.desc(LCC_FP32), b32, st, nullptr, active);
   else
-    e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), b32, st);
+    e = launch_gemm_bf16x3(L.desc(LCC_BF16X3), b32, st, nullptr, active);
   check_hip(e, "gemm launch");
 }
 
-void launch_reduce(const Plan& P, int precision, const Bases<double>& b64, const Bases<float>& b32, hipStream_t st) {
+void launch_reduce(const Plan& P, int precision, const Bases<double>& b64, const Bases<float>& b32, hipStream_t st,
+                   const int* active = nullptr) {
   hipError_t e = precision == LCC_FP64
                      ? launch_reduce_f64(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
-                                         P.n_reduce_tiles, b64, st)
+                                         P.n_reduce_tiles, b64, st, nullptr, active)
                      : launch_reduce_f32(P.reduce_groups.as<ReduceGroup>(), P.reduce_tiles.as<ReduceTile>(),
-                                         P.n_reduce_tiles, b32, st);
+                                         P.n_reduce_tiles, b32, st, nullptr, active);
   check_hip(e, "reduce launch");
 }
 
@@ -1353,10 +1354,11 @@ void ensure_side_streams(Context& C) {
 // H_eff x.  The launches of one phase (one per tile shape) are independent: with side streams
 // enabled on the context they run concurrently (the longest on the context stream, the others
 // spread over the side streams), so that short launches fill the tail of long ones; the
-// phases, chunks and the reduction stay ordered on the context stream.
-void apply_heff(Env& env, int precision, const void* x, void* y) {
+// phases, chunks and the reduction stay ordered on the context stream.  With `active` given
+// (a device word), every workgroup returns at once while it reads 0.
+void apply_heff(Env& env, int precision, const void* x, void* y, const int* active) {
   Context& C = *env.ctx;
-  if (C.overlap <= 0) {
+  if (C.overlap <= 0 && !active) {
     apply_heff_each(env, precision, x, y, no_callback, nullptr);
     return;
   }
@@ -1370,8 +1372,8 @@ void apply_heff(Env& env, int precision, const void* x, void* y) {
   for (const Plan::Chunk& Ch : P.chunks)
     for (int ph = 1; ph <= 2; ++ph) {
       const std::vector<GemmLaunch>& Ls = ph == 1 ? Ch.phase1 : Ch.phase2;
-      if (Ls.size() <= 1) {
-        for (const GemmLaunch& L : Ls) launch_one(L, precision, b64, b32, st);
+      if (Ls.size() <= 1 || C.overlap <= 0) {
+        for (const GemmLaunch& L : Ls) launch_one(L, precision, b64, b32, st, active);
         continue;
       }
       std::vector<int> order(Ls.size());
@@ -1381,13 +1383,13 @@ void apply_heff(Env& env, int precision, const void* x, void* y) {
       check_hip(hipEventRecord(C.ev_fork, st), "fork");
       for (int k = 0; k < nside; ++k) check_hip(hipStreamWaitEvent(C.side[k], C.ev_fork, 0), "fork wait");
       for (size_t i = 0; i < order.size(); ++i)
-        launch_one(Ls[order[i]], precision, b64, b32, i == 0 ? st : C.side[(i - 1) % nside]);
+        launch_one(Ls[order[i]], precision, b64, b32, i == 0 ? st : C.side[(i - 1) % nside], active);
       for (int k = 0; k < nside; ++k) {
         check_hip(hipEventRecord(C.ev_join[k], C.side[k]), "join");
         check_hip(hipStreamWaitEvent(st, C.ev_join[k], 0), "join wait");
       }
     }
-  launch_reduce(P, precision, b64, b32, st);
+  launch_reduce(P, precision, b64, b32, st, active);
 }
 
 // Every launch of one H_eff x in order on the context stream: for each channel chunk its

@@ -378,11 +378,9 @@ gemm_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restric
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
-  const Bases<T>* row = nullptr;
-  if (table) {  // batched launch: per-problem operands, converged problems skipped
-    if (active && !active[g.problem]) return;
-    row = table + g.problem;
-  }
+  // a problem whose active flag is 0 is skipped (batched: converged; single: halted solve)
+  if (active && !active[table ? g.problem : 0]) return;
+  const Bases<T>* row = table ? table + g.problem : nullptr;  // batched: per-problem operands
   bt.stage(bases, row);
   __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
@@ -510,11 +508,9 @@ gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
-  const Bases<float>* row = nullptr;
-  if (table) {  // batched launch: per-problem operands, converged problems skipped
-    if (active && !active[g.problem]) return;
-    row = table + g.problem;
-  }
+  // a problem whose active flag is 0 is skipped (batched: converged; single: halted solve)
+  if (active && !active[table ? g.problem : 0]) return;
+  const Bases<float>* row = table ? table + g.problem : nullptr;  // batched: per-problem operands
   bt.stage(bases, row);
   __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
@@ -780,11 +776,9 @@ __device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ ter
 
   const GemmTile tile = tiles[xcd_remap(blockIdx.x, n_tiles)];
   const GemmGroup g = groups[tile.group];
-  const Bases<T>* row = nullptr;
-  if (table) {  // batched launch: per-problem operands, converged problems skipped
-    if (active && !active[g.problem]) return;
-    row = table + g.problem;
-  }
+  // a problem whose active flag is 0 is skipped (batched: converged; single: halted solve)
+  if (active && !active[table ? g.problem : 0]) return;
+  const Bases<T>* row = table ? table + g.problem : nullptr;  // batched: per-problem operands
   bt.stage(bases, row);
   __syncthreads();
   const int tm = tile.tile / g.tiles_n, tn = tile.tile % g.tiles_n;
@@ -960,10 +954,8 @@ reduce_kernel(const ReduceGroup* __restrict__ groups, const ReduceTile* __restri
               const Bases<T>* __restrict__ table, const int* __restrict__ active) {
   const ReduceTile tile = tiles[blockIdx.x];
   const ReduceGroup g = groups[tile.group];
-  if (table) {
-    if (active && !active[g.problem]) return;
-    bases = table[g.problem];
-  }
+  if (active && !active[table ? g.problem : 0]) return;
+  if (table) bases = table[g.problem];
   const int64_t mn = (int64_t)g.m * g.n;
   const T* __restrict__ src = bases.p[BASE_WORK] + g.src_off;
   T* __restrict__ dst = bases.p[BASE_Y] + g.dst_off;

@@ -3,8 +3,20 @@
 // low-precision CG.  All dot products accumulate in FP64 and every scalar of the
 // recurrences is FP64; only the operator products and the vector updates of the inner
 // solve run in FP32.
+//
+// Inside an iteration nothing returns to the host.  The scalars live in a CgScalars record in
+// device memory, and each vector update is fused with the dot product after it and the scalar
+// step that uses it (cg.hip): an iteration is the operator product plus three small launches.
+// The last of them writes the status words to mapped host memory; after queueing iteration
+// i the host waits for the status of iteration i-1, so the device has the next iteration
+// queued (near the end of the recurrence it waits for iteration i itself).  The device halts the recurrence itself (converged, refresh due, error),
+// which makes the iteration queued behind the halt change nothing; its operator product
+// returns at once.  Refreshes of the mixed solve (FP64 residual, rescaling) and the final
+// energy read scalars back synchronously; they happen a few times per solve.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <string>
 
 #include "state.h"
 
@@ -18,47 +30,112 @@ struct Ops {
   double e0;
   const double* v64;   // may be null
   float* v32;          // FP32 copy of v (inner solve) or null
+  CgScalars* S;        // device record of the recurrence
   int applies64 = 0, applies_low = 0;
 
+  double* partial() const { return env.ctx->dot_partial.as<double>(); }
+  // dot products read back to the host through mapped memory (set-up, refreshes, final energy)
   double dot64(const double* a, const double* b) {
     Context* c = env.ctx;
-    check_hip(launch_dot_f64(a, b, n, c->dot_partial.as<double>(), c->dot_out.as<double>(), st), "dot");
-    check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+    check_hip(launch_dot_f64(a, b, n, partial(), c->host_scalar_dev, st), "dot");
     check_hip(hipStreamSynchronize(st), "dot sync");
     return c->host_scalar[0];
   }
   double dot32(const float* a, const float* b) {
     Context* c = env.ctx;
-    check_hip(launch_dot_f32(a, b, n, c->dot_partial.as<double>(), c->dot_out.as<double>(), st), "dot");
-    check_hip(hipMemcpyAsync(c->host_scalar, c->dot_out.p, sizeof(double), hipMemcpyDeviceToHost, st), "dot copy");
+    check_hip(launch_dot_f32(a, b, n, partial(), c->host_scalar_dev, st), "dot");
     check_hip(hipStreamSynchronize(st), "dot sync");
     return c->host_scalar[0];
   }
-  // z <- z - (v.z) v
+  // z <- z - (v.z) v, with v.z kept on the device
   void project64(double* z) {
     if (!v64) return;
-    const double c = dot64(v64, z);
-    check_hip(launch_axpby_f64(n, -c, v64, 1.0, z, st), "project");
+    check_hip(launch_dot_f64(v64, z, n, partial(), &S->c, st), "dot");
+    check_hip(launch_cg_deflate<double>(n, &S->c, v64, z, st), "project");
   }
   void project32(float* z) {
     if (!v32) return;
-    const double c = dot32(v32, z);
-    check_hip(launch_axpby_f32(n, -c, v32, 1.0, z, st), "project");
+    check_hip(launch_dot_f32(v32, z, n, partial(), &S->c, st), "dot");
+    check_hip(launch_cg_deflate<float>(n, &S->c, v32, z, st), "project");
   }
   // out = Q (H - e0) Q in ; `in` is assumed to lie in range(Q) already (all iterates do)
-  void A64(const double* in, double* out) {
-    apply_heff(env, LCC_FP64, in, out);
+  void A64(const double* in, double* out, bool guarded = false) {
+    apply_heff(env, LCC_FP64, in, out, guarded ? &S->run : nullptr);
     ++applies64;
     check_hip(launch_axpby_f64(n, -e0, in, 1.0, out, st), "shift");
     project64(out);
   }
-  void A32(int prec, const float* in, float* out) {
-    apply_heff(env, prec, in, out);
+  // Ap = Q (H - e0) p and alpha = rho / p^T Ap on the device; the product is skipped while the
+  // recurrence is halted
+  void Ap64(const double* p, double* Ap) {
+    apply_heff(env, LCC_FP64, p, Ap, &S->run);
+    ++applies64;
+    check_hip(launch_cg_shift<double>(n, e0, p, Ap, v64, S, partial(), st), "shift, p^T A p");
+  }
+  void Ap32(int prec, const float* p, float* Ap) {
+    apply_heff(env, prec, p, Ap, &S->run);
     ++applies_low;
-    check_hip(launch_axpby_f32(n, -e0, in, 1.0, out, st), "shift");
-    project32(out);
+    check_hip(launch_cg_shift<float>(n, e0, p, Ap, v32, S, partial(), st), "shift, p^T A p");
   }
 };
+
+// Status of the recurrence.  The direction update of every iteration posts a CgStatus into
+// one of two mapped slots.  Before queueing the next iteration the host waits for the
+// iteration before the last one queued, so that the device keeps one iteration in its queue.
+// An iteration queued behind a halt does nothing, but still dispatches the launches of its
+// operator product; so when the last status seen puts the residual within a few of its
+// latest per-iteration drops of the threshold that stops the recurrence, the host waits for
+// the last iteration as well.
+struct StatusPoll {
+  static constexpr double kSafety = 2.0;  // drops larger than kSafety x the last one are rare
+  hipStream_t st;
+  Context* ctx;
+  const CgScalars* S;
+  int64_t posted = 0;
+  int64_t seen = -1;    // last iteration whose status was read
+  double margin = 0.0;  // its margin
+  bool near = true;     // no status seen yet
+  CgStatus* slot_dev() { return reinterpret_cast<CgStatus*>(ctx->host_scalar_dev + 4) + (posted & 1); }
+  void posted_one() {
+    check_hip(hipEventRecord(ctx->ev_status[posted & 1], st), "status event");
+    ++posted;
+  }
+  // waits for the status of queued iteration k (0-based since the last now()); true if halted
+  bool halted_at(int64_t k) {
+    if (k == seen) return false;
+    check_hip(hipEventSynchronize(ctx->ev_status[k & 1]), "status wait");
+    const CgStatus& s = reinterpret_cast<const CgStatus*>(ctx->host_scalar + 4)[k & 1];
+    if (s.halt != CG_RUNNING) return true;
+    const double drop = seen == k - 1 && s.margin > 0.0 ? std::max(margin / s.margin, 1.0) : HUGE_VAL;
+    near = s.margin < kSafety * drop;
+    seen = k;
+    margin = s.margin;
+    return false;
+  }
+  // true when the recurrence has halted (queue nothing more)
+  bool halted() {
+    if (posted >= 2 && halted_at(posted - 2)) return true;
+    return near && halted_at(posted - 1);
+  }
+  // all queued work done: the record as the device holds it now; the next post starts anew
+  CgScalars now() {
+    CgScalars* whole = reinterpret_cast<CgScalars*>(ctx->host_scalar + 12);
+    check_hip(launch_cg_copy(S, reinterpret_cast<CgScalars*>(ctx->host_scalar_dev + 12), st), "record copy");
+    check_hip(hipStreamSynchronize(st), "record sync");
+    posted = 0;
+    seen = -1;
+    near = true;
+    return *whole;
+  }
+};
+
+[[noreturn]] void raise_halt(const CgScalars& w) {
+  const int code = w.err, why = w.why;
+  if (why == CG_WHY_PAP_NAN) throw Error{code, "non-finite p^T A p"};
+  if (why == CG_WHY_PAP_NOT_POSITIVE) throw Error{code, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
+  if (why == CG_WHY_RESIDUAL_NAN) throw Error{code, "non-finite residual"};
+  throw Error{code, "conjugate gradients stopped with status " + std::to_string(code)};
+}
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -67,7 +144,8 @@ bool finite(double v) { return std::isfinite(v); }
 lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, double e0, const double* v,
                        double* x, lcc_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t st = env.ctx->stream;
+  Context* ctx = env.ctx;
+  hipStream_t st = ctx->stream;
   const int64_t n = env.n_elements;
   const int prec = o.precision;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
@@ -80,7 +158,14 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
   if (!finite(e0)) throw Error{LCC_ERR_NAN, "e0 is not finite"};
   const bool jacobi = o.preconditioner == 1;
 
-  Ops ops{env, st, n, e0, v, nullptr};
+  if (!env.cg.p) env.cg.alloc(sizeof(CgScalars));
+  CgScalars* S = env.cg.as<CgScalars>();
+  for (int k = 0; k < 2; ++k)
+    if (!ctx->ev_status[k]) check_hip(hipEventCreateWithFlags(&ctx->ev_status[k], hipEventDisableTiming), "event");
+  StatusPoll poll{st, ctx, S};
+  check_hip(launch_cg_reset(S, st), "cg reset");
+
+  Ops ops{env, st, n, e0, v, nullptr, S};
   double* bq = env.w64[0].as<double>();
   double* r = env.w64[1].as<double>();
   double* p = env.w64[2].as<double>();
@@ -127,9 +212,13 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
   const double bn = std::sqrt(ops.dot64(bq, bq));
   lcc_solve_info inf{};
   lcc_status status = LCC_OK;
-  auto residual64 = [&]() {  // r = bq - A x, returns ||r||
+  // r = bq - A x (queued only)
+  auto residual64_queue = [&]() {
     ops.A64(x, r);
     check_hip(launch_axpby_f64(n, 1.0, bq, -1.0, r, st), "residual");
+  };
+  auto residual64 = [&]() {  // r = bq - A x, returns ||r||
+    residual64_queue();
     return std::sqrt(ops.dot64(r, r));
   };
   if (bn == 0.0) {
@@ -137,38 +226,40 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
     check_hip(launch_fill_f64(r, n, 0.0, st), "zero r");
   } else if (prec == LCC_FP64) {
     // (preconditioned) conjugate gradients: rho = r^T z with z = Q M^-1 r (z = r without M)
-    double rnorm = residual64();
+    const double rnorm = residual64();
     precondition64();
     check_hip(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st), "p = z");
-    double rr = rnorm * rnorm;
-    double rho = jacobi ? ops.dot64(r, z) : rr;
-    int it = 0;
-    while (std::sqrt(rr) > tol * bn) {
-      if (it >= max_iter) { status = LCC_NOT_CONVERGED; break; }
-      ops.A64(p, Ap);
-      const double pAp = ops.dot64(p, Ap);
-      if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
-      if (pAp <= 0.0) throw Error{LCC_ERR_NOT_SPD, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
-      const double alpha = rho / pAp;
-      check_hip(launch_axpby_f64(n, alpha, p, 1.0, x, st), "x update");
-      ++it;
-      double rr_new;
-      if (it % replace_every == 0) {
-        const double rn = residual64();
-        rr_new = rn * rn;
-      } else {
-        check_hip(launch_axpby_f64(n, -alpha, Ap, 1.0, r, st), "r update");
-        rr_new = ops.dot64(r, r);
+    const double rr = rnorm * rnorm;
+    const double rho = jacobi ? ops.dot64(r, z) : rr;
+    if (std::sqrt(rr) > tol * bn) {
+      check_hip(launch_cg_set(S, rho, rr, 0.0, 1.0, tol * bn, 0.0, st), "cg set");
+      for (int it = 0; it < max_iter; ++it) {
+        ops.Ap64(p, Ap);
+        if ((it + 1) % replace_every == 0) {
+          // x += alpha p, then the true residual replaces the recurrence one (after a halt the
+          // recomputed r is discarded: the final residual is formed again below)
+          check_hip(launch_cg_solution<double>(n, p, x, S, st), "x update");
+          ops.A64(x, r, true);
+          check_hip(launch_axpby_f64(n, 1.0, bq, -1.0, r, st), "residual");
+          check_hip(launch_dot_f64(r, r, n, ops.partial(), &S->rr_new, st), "dot");
+          check_hip(launch_cg_after_r(S, false, jacobi, st), "after r");
+        } else {
+          check_hip(launch_cg_update<double>(n, p, x, Ap, r, S, ops.partial(), false, jacobi, st), "x, r update");
+        }
+        if (jacobi) {
+          precondition64();
+          check_hip(launch_dot_f64(r, z, n, ops.partial(), &S->rho_new, st), "dot");
+          check_hip(launch_cg_beta(S, st), "beta");
+        }
+        check_hip(launch_cg_direction<double>(n, z, p, S, poll.slot_dev(), st), "p update");
+        poll.posted_one();
+        if (poll.halted()) break;
       }
-      if (!finite(rr_new)) throw Error{LCC_ERR_NAN, "non-finite residual"};
-      precondition64();
-      const double rho_new = jacobi ? ops.dot64(r, z) : rr_new;
-      const double beta = rho_new / rho;
-      check_hip(launch_axpby_f64(n, 1.0, z, beta, p, st), "p update");
-      rr = rr_new;
-      rho = rho_new;
+      const CgScalars w = poll.now();
+      if (w.halt == CG_HALT_ERROR) raise_halt(w);
+      if (w.halt != CG_STOP) status = LCC_NOT_CONVERGED;
+      inf.iterations = w.iters;
     }
-    inf.iterations = it;
     inf.outer = 1;
     residual64();
   } else {
@@ -207,49 +298,48 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
       check_hip(hipMemcpyAsync(p32, z32, sizeof(float) * n, hipMemcpyDeviceToDevice, st), "p = z");
       double rr = ops.dot32(r32, r32);
       double rho = jacobi ? ops.dot32(r32, z32) : rr;
-      double rmax = std::sqrt(rr);
+      check_hip(launch_cg_set(S, rho, rr, std::sqrt(rr), sc, tol * bn, inner_tol, st), "cg set");
       while (true) {
-        if (total_it >= max_iter || outer >= max_outer) { status = LCC_NOT_CONVERGED; break; }
-        ops.A32(prec, p32, Ap32);
-        const double pAp = ops.dot32(p32, Ap32);
-        if (!finite(pAp)) throw Error{LCC_ERR_NAN, "non-finite p^T A p"};
-        if (pAp <= 0.0) throw Error{LCC_ERR_NOT_SPD, "p^T A p <= 0: Q (H_eff - e0) Q is not positive definite"};
-        const double alpha = rho / pAp;
-        check_hip(launch_axpby_f32(n, alpha, p32, 1.0, d32, st), "d update");
-        check_hip(launch_axpby_f32(n, -alpha, Ap32, 1.0, r32, st), "r update");
-        double rr_new = ops.dot32(r32, r32);
-        if (!finite(rr_new)) throw Error{LCC_ERR_NAN, "non-finite residual"};
-        ++total_it;
-        const double rn = std::sqrt(rr_new) * sc;
-        double p_scale = 1.0;
-        if (rn < inner_tol * rmax * sc || rn <= tol * bn) {
-          // refresh: x += sc d (FP64), true residual in FP64, continue in the new units
-          check_hip(launch_axpy_f32_into_f64(n, sc, d32, x, st), "x += d");
-          ops.project64(x);
-          check_hip(launch_fill_f32(d32, n, 0.0f, st), "d = 0");
-          rnorm = residual64();
-          ++outer;
-          if (rnorm <= tol * bn) break;
-          const double sc_new = rnorm;
-          check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
-          check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / sc_new, r32, st), "scale r32");
-          // beta from the refreshed residual (rho in true units); p rescaled to the new units
-          precondition32();
-          const double rho_new_units = jacobi ? ops.dot32(r32, z32) : ops.dot32(r32, r32);
-          const double beta = (rho_new_units * sc_new * sc_new) / (rho * sc * sc);
-          p_scale = beta * sc / sc_new;
-          check_hip(launch_axpby_f32(n, 1.0, z32, p_scale, p32, st), "p update");
-          sc = sc_new;
-          rr = ops.dot32(r32, r32);
-          rho = rho_new_units;
-          rmax = std::sqrt(rr);
-          continue;
+        // low-precision iterations, until the device halts the recurrence (refresh due,
+        // converged, error) or max_iter iterations have run
+        for (; total_it < max_iter; ++total_it) {
+          ops.Ap32(prec, p32, Ap32);
+          check_hip(launch_cg_update<float>(n, p32, d32, Ap32, r32, S, ops.partial(), true, jacobi, st),
+                    "d, r update");
+          if (jacobi) {
+            precondition32();
+            check_hip(launch_dot_f32(r32, z32, n, ops.partial(), &S->rho_new, st), "dot");
+            check_hip(launch_cg_beta(S, st), "beta");
+          }
+          check_hip(launch_cg_direction<float>(n, z32, p32, S, poll.slot_dev(), st), "p update");
+          poll.posted_one();
+          if (poll.halted()) break;
         }
+        const CgScalars w = poll.now();
+        if (w.halt == CG_HALT_ERROR) raise_halt(w);
+        total_it = w.iters;  // iterations the device performed (a queued one behind a halt does nothing)
+        rho = w.rho;         // rho of the last completed iteration
+        if (w.halt != CG_STOP) { status = LCC_NOT_CONVERGED; break; }
+        // refresh: x += sc d (FP64), true residual in FP64, continue in the new units
+        check_hip(launch_axpy_f32_into_f64(n, sc, d32, x, st), "x += d");
+        ops.project64(x);
+        check_hip(launch_fill_f32(d32, n, 0.0f, st), "d = 0");
+        rnorm = residual64();
+        ++outer;
+        if (rnorm <= tol * bn) break;
+        if (total_it >= max_iter || outer >= max_outer) { status = LCC_NOT_CONVERGED; break; }
+        const double sc_new = rnorm;
+        check_hip(launch_convert_f64_f32(n, r, r32, st), "r32");
+        check_hip(launch_axpby_f32(n, 0.0, r32, 1.0 / sc_new, r32, st), "scale r32");
+        // beta from the refreshed residual (rho in true units); p rescaled to the new units
         precondition32();
-        const double rho_new = jacobi ? ops.dot32(r32, z32) : rr_new;
-        check_hip(launch_axpby_f32(n, 1.0, z32, rho_new / rho, p32, st), "p update");
-        rr = rr_new;
-        rho = rho_new;
+        rr = ops.dot32(r32, r32);
+        const double rho_new_units = jacobi ? ops.dot32(r32, z32) : rr;
+        const double beta = (rho_new_units * sc_new * sc_new) / (rho * sc * sc);
+        check_hip(launch_axpby_f32(n, 1.0, z32, beta * sc / sc_new, p32, st), "p update");
+        sc = sc_new;
+        rho = rho_new_units;
+        check_hip(launch_cg_set(S, rho, rr, std::sqrt(rr), sc, tol * bn, inner_tol, st), "cg set");
       }
       if (status == LCC_NOT_CONVERGED) {
         check_hip(launch_axpy_f32_into_f64(n, sc, d32, x, st), "x += d");

@@ -58,6 +58,59 @@ struct PlanParams {
   int t_colmajor = 2;             // 0 / 1: left operator first, T row- / column-major; 2: right operator first
 };
 
+// Scalars of the single solve's conjugate-gradient recurrence, kept in device memory
+// (cg.hip).  The last four words are the status the host reads back.
+enum : int32_t { CG_RUNNING = 0, CG_STOP = 1, CG_HALT_ERROR = 2 };
+enum : int32_t { CG_WHY_PAP_NAN = 1, CG_WHY_PAP_NOT_POSITIVE = 2, CG_WHY_RESIDUAL_NAN = 3 };
+struct CgScalars {
+  double pAp, rr_new, rho_new, c;                      // dot-product outputs
+  double alpha, beta, rho, rr, rmax, sc, tol_bn, delta;  // recurrence
+  double margin;  // last residual over the threshold that stops the recurrence (< 1: stopped)
+  int32_t run;      // 1 while halt is CG_RUNNING: the operator products skip their work at 0
+  uint32_t ticket;  // arrival count of the blocks of a fused launch (0 between launches)
+  int32_t halt;   // CG_RUNNING, CG_STOP (converged or refresh due), CG_HALT_ERROR
+  int32_t err;    // lcc_status of an error
+  int32_t why;    // CG_WHY_*
+  int32_t iters;  // iterations performed
+};
+// Launchers of cg.hip.  `partial` holds at least kDotBlocks doubles.
+// Status words a direction update posts to the host.
+struct CgStatus {
+  int32_t halt, err, why, iters;
+  double margin;
+  double pad;
+};
+hipError_t launch_cg_set(CgScalars* S, double rho, double rr, double rmax, double sc, double tol_bn, double delta,
+                         hipStream_t s);
+hipError_t launch_cg_reset(CgScalars* S, hipStream_t s);
+// the stop test and beta from S->rr_new (after an unfused |r|^2)
+hipError_t launch_cg_after_r(CgScalars* S, bool mixed, bool preconditioned, hipStream_t s);
+// beta = rho_new / rho (preconditioned: after the dot r^T z into S->rho_new)
+hipError_t launch_cg_beta(CgScalars* S, hipStream_t s);
+// *out = *S (out: mapped host memory)
+hipError_t launch_cg_copy(const CgScalars* S, CgScalars* out, hipStream_t s);
+// Ap <- Q (Ap - e0 p) (Q = 1 - v v^T when v is given), then alpha = rho / p^T Ap
+template <class T>
+hipError_t launch_cg_shift(int64_t n, double e0, const T* p, T* Ap, const T* v, CgScalars* S, double* partial,
+                           hipStream_t s);
+// s += alpha p, r -= alpha Ap, then |r|^2, the stop test and (unpreconditioned) beta
+template <class T>
+hipError_t launch_cg_update(int64_t n, const T* p, T* s_, const T* Ap, T* r, CgScalars* S, double* partial, bool mixed,
+                            bool preconditioned, hipStream_t s);
+// s += alpha p
+template <class T>
+hipError_t launch_cg_solution(int64_t n, const T* p, T* s_, const CgScalars* S, hipStream_t s);
+// p <- z + beta p; post (may be null) receives the status
+template <class T>
+hipError_t launch_cg_direction(int64_t n, const T* z, T* p, const CgScalars* S, CgStatus* post, hipStream_t s);
+// y <- y - (*c) v
+template <class T>
+hipError_t launch_cg_deflate(int64_t n, const double* c, const T* v, T* y, hipStream_t s);
+
+constexpr int kHostScalars = 32;
+static_assert(sizeof(CgScalars) <= 16 * sizeof(double), "CG record does not fit its pinned slot");
+static_assert(sizeof(CgStatus) == 4 * sizeof(double), "CG status slot size");
+
 struct Context {
   void* handle = nullptr;  // the owning lcc_context_s
   int device = -1;
@@ -66,7 +119,10 @@ struct Context {
   std::string err;
   // scratch for reductions
   DevBuf dot_partial, dot_out;
-  double* host_scalar = nullptr;  // pinned
+  // pinned and mapped, kHostScalars doubles: [0] dot read-back, [4, 12) two CgStatus slots,
+  // [12, 28) a copy of the CG record; host_scalar_dev is the device's address of it
+  double* host_scalar = nullptr;
+  double* host_scalar_dev = nullptr;
   int64_t t_budget_elems = (int64_t)1 << 31;  // intermediate (phase-1 output) elements per environment
   PlanParams plan_params;                      // defaults for new environments
   std::string tune_cache;                      // autotuner cache file ("" = none)
@@ -75,6 +131,8 @@ struct Context {
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> ev_join;
   hipEvent_t ev_fork = nullptr;
+  // the single solve's status copies, one iteration behind (see solver.cpp)
+  hipEvent_t ev_status[2] = {nullptr, nullptr};
 };
 
 struct Bond {
@@ -203,6 +261,7 @@ struct Env {
   // CG workspace
   DevBuf w64[6], w32[6];
   DevBuf flag;
+  DevBuf cg;  // CgScalars of the single solve
   bool have32 = false;
   // diagonal of H_eff (FP64, built on first use) and the Jacobi preconditioner 1 / (diag - e0)
   DevBuf diag64, minv64, minv32;
@@ -262,7 +321,7 @@ Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, in
 void ensure_fp32(Env& env);
 // diag(H_eff) into env.diag64 (once)
 void compute_diagonal(Env& env);
-void apply_heff(Env& env, int precision, const void* x, void* y);
+void apply_heff(Env& env, int precision, const void* x, void* y, const int* active = nullptr);
 // one launch at a time: after_each(phase, kind, launch) runs after each launch is queued
 struct LaunchRef {
   int phase, kind;
