@@ -429,6 +429,53 @@ def run_sweep(args):
 
 
 
+def run_small(args):
+    """Local solves at a reduced bond dimension (--m-max) of --workload, where the small
+    launches of the CG iteration weigh most: FP64 and mixed solves (one warm-up each, then
+    --steps timed), with the operator product timed alone for comparison."""
+    import torch
+    from paper_1509_00216_amd import lcc
+    from workloads import configs as C
+    from workloads import mps as M
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    spec, mps = C.make(args.workload, m_max=args.m_max)
+    ctx = lcc.Context(0)
+    ctx.set_tune_cache(working_tune_cache(args.tune_cache))
+    env = ctx.build_environments(ctx.create_hamiltonian(spec), mps)
+    e0, rule = shift_for(spec, env, args.workload)
+    b = torch.tensor(env.pack(M.random_two_site_vector(mps, 2025)), dtype=torch.float64, device=dev)
+    x = torch.zeros_like(b)
+    out = {"mode": "small", "workload": args.workload, "m_max": args.m_max, "n": env.n, "e0_rule": rule}
+    for prec in ("fp64", args.precision):
+        xx = b if prec == "fp64" else b.float()
+        yy = torch.empty_like(xx)
+        env.apply_heff(xx, yy, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            env.apply_heff(xx, yy, prec)
+        torch.cuda.synchronize()
+        ms_apply = (time.perf_counter() - t0) * 1e3 / 20
+        times, info = [], None
+        for rep in range(1 + max(1, args.steps)):
+            x.zero_()
+            torch.cuda.synchronize()
+            time.sleep(0.05)  # idle gap: the solves stand apart in a kernel trace
+            t0 = time.perf_counter()
+            info = env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-10, max_iter=5000, inner_tol=args.inner_tol,
+                                       max_outer=200)
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append((time.perf_counter() - t0) * 1e3)
+        out[prec] = {"ms_apply": ms_apply, "ms_solve": sum(times) / len(times), "iterations": info["iterations"],
+                     "applies_fp64": info["applies_fp64"], "applies_low": info["applies_low"],
+                     "J": info["hylleraas"], "rel_residual": info["rel_residual"]}
+        log(f"[small] {prec}: {out[prec]}")
+    env.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,10 +490,12 @@ def main():
                     help="profiling mode: build, run N plain H_eff x products of --apply-precision and a "
                          "256 MiB device copy (counter calibration), print timings, skip the solves")
     ap.add_argument("--apply-precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "sweep", "tune"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "batch", "sweep", "tune", "small"],
                     help="solve: the headline local solve (default); batch: 64 independent problems, batched "
                          "mixed vs sequential FP64; sweep: one sweep of the 4x4 Hubbard model; tune: autotune "
-                         "--tune-workloads into --tune-cache")
+                         "--tune-workloads into --tune-cache; small: local solves of --workload at bond "
+                         "dimension --m-max")
+    ap.add_argument("--m-max", type=int, default=128, help="bond dimension of --mode small")
     ap.add_argument("--tune-cache", default=SHIPPED_TUNE_CACHE)
     ap.add_argument("--tune-workloads", default="abinitio_k24_m1000,threeband_4x2_m2000,hubbard2d_4x4_m500")
     ap.add_argument("--no-tune", action="store_true", help="plan with the default planner parameters")
@@ -482,6 +531,8 @@ def main():
         return run_batch(args)
     if args.mode == "sweep":
         return run_sweep(args)
+    if args.mode == "small":
+        return run_small(args)
 
     # the oracle's timing runs in a child process on the host cores beside the GPU measurements
     baseline = None

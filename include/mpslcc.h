@@ -159,6 +159,19 @@ typedef struct {
  * Synchronous.  The environment keeps its own copies of everything it needs. */
 lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps,
                                   int32_t site, lcc_env* out);
+/* The one-site local problem (Implementation section, local-derivative figure and the sweep: one
+ * site tensor A^{n_l} with 4 M^2 elements is the unknown): left environment of the sites < site,
+ * right environment of the sites > site, and the same H_eff x plan, with the enlarged right
+ * operator equal to the right environment itself.  0 <= site < K; sites left of `site` must be
+ * left-canonical and sites right of it right-canonical (checked as for lcc_build_environments,
+ * LCC_ERR_ARG otherwise); the tensor at `site` is ignored.  The environment's vectors are
+ * one-site tensors x[a, s, b] with a a sector of bond site, b a sector of bond site+1 and
+ * qn(a) + qn(s) = qn(b): lcc_env_layout lists their blocks as (left = a, s1 = s, s2 = 0,
+ * right = b), rows over a and columns over b.  Every call that takes an environment of
+ * lcc_build_environments takes this one (apply, flops, layout, diagonal, local solve,
+ * eigensolvers, tuner, batches).  Synchronous.  The environment keeps its own copies. */
+lcc_status lcc_build_environments_one_site(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps,
+                                           int32_t site, lcc_env* out);
 void lcc_env_destroy(lcc_env env);
 
 /* Transition operator between two MPS (Implementation section: the transition element <Psi|H|Phi>,
@@ -179,7 +192,8 @@ lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ha
 
 /* Layout of two-site vectors x, y, b (the unknown tensor of the local problem).
  * Blocks are (left sector a of bond site, s1, s2, right sector b of bond site+2) with
- * qn(a) + qn(s1) + qn(s2) = qn(b).  Element (i, j) of a block sits at
+ * qn(a) + qn(s1) + qn(s2) = qn(b); for a one-site environment (left sector a of bond site, s1,
+ * s2 = 0, right sector b of bond site+1).  Element (i, j) of a block sits at
  * offset + i * ld + j. */
 typedef struct {
   int64_t n_elements;   /* length of a two-site vector */

@@ -326,6 +326,44 @@ def two_site_template(mps: dict, blocks: list) -> dict:
     return {k: np.zeros((bl[k[0]][2], br[k[3]][2])) for k in blocks}
 
 
+def one_site_embed(mps: dict, x1: dict, two_site_keys: list) -> dict:
+    """E x1: the two-site tensor of the block (c, c+1), c = mps['center'], that a one-site tensor
+    x1 at c represents with the right-canonical site c+1 of mps fixed,
+        x2[a, s1, s2, b'] = sum_b x1[a, s1, b] B^{s2}[b, b'],
+    so that the one-site isometry is the two-site one times E (P1 = P2 E).  x1 is keyed
+    (a, s1, 0, b)."""
+    c = mps["center"]
+    bl, br = mps["bonds"][c], mps["bonds"][c + 2]
+    x2 = {k: np.zeros((bl[k[0]][2], br[k[3]][2])) for k in two_site_keys}
+    for (a, s1, _, b), blk in x1.items():
+        for (il, s2, ir, B) in mps["sites"][c + 1]:
+            if il == b and (a, s1, s2, ir) in x2:
+                x2[(a, s1, s2, ir)] += blk @ B
+    return x2
+
+
+def one_site_contract(mps: dict, y2: dict, one_site_keys: list) -> dict:
+    """E^T y2: y1[a, s1, b] = sum_{s2, b'} y2[a, s1, s2, b'] B^{s2}[b, b']^T."""
+    c = mps["center"]
+    bl, bm = mps["bonds"][c], mps["bonds"][c + 1]
+    y1 = {k: np.zeros((bl[k[0]][2], bm[k[3]][2])) for k in one_site_keys}
+    for (il, s2, ir, B) in mps["sites"][c + 1]:
+        for (a, s1, _, b) in one_site_keys:
+            if b == il and (a, s1, s2, ir) in y2:
+                y1[(a, s1, 0, b)] += y2[(a, s1, s2, ir)] @ B.T
+    return y1
+
+
+def one_site_apply(spec: dict, mps: dict, mpo: dict, x1: dict) -> dict:
+    """y = H1 x1 for the site tensor at mps['center'] (sites left of it left-canonical, right of
+    it right-canonical): H1 = P1^T H P1 = E^T (P2^T H P2) E, the two-site H_eff of (c, c+1) of
+    `Environments` between the embedding and its transpose.  Needs c + 1 < K."""
+    from workloads import mps as M  # block enumeration of the generator (inputs only)
+    keys2 = M.two_site_blocks(mps)
+    y2 = Environments(spec, mps, mpo).apply(one_site_embed(mps, x1, keys2))
+    return one_site_contract(mps, y2, sorted(x1))
+
+
 __all__ = ["Environments", "MiddleBondEnvironments", "left_environments", "right_environments", "two_site_w",
            "check_left_canonical", "check_right_canonical", "flatten", "unflatten", "dot",
-           "two_site_template", "LOCAL_QN"]
+           "two_site_template", "one_site_embed", "one_site_contract", "one_site_apply", "LOCAL_QN"]

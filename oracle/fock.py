@@ -227,6 +227,49 @@ def effective_hamiltonian(spec: dict, mps: dict, blocks: list) -> np.ndarray:
     return P.T @ HP
 
 
+def one_site_isometry(mps: dict, basis: np.ndarray, blocks: list) -> np.ndarray:
+    """P1: (sector dim, one-site dim) for the site tensor at mps['center'] (Implementation
+    section, local-derivative figure: the derivative with respect to the one tensor A^{n_l});
+    column (a, s, b) is |a>_L |s> |b>_R, with |a>_L from the sites left of the center and |b>_R
+    from the sites right of it.  Columns ordered by `blocks` ((ia, s, ib) or (ia, s, 0, ib)),
+    row-major inside a block."""
+    K = mps["n_sites"]
+    l = mps["center"]
+    bl, br = mps["bonds"][l], mps["bonds"][l + 1]
+    offl = np.concatenate([[0], np.cumsum([d for _, _, d in bl])])
+    offr = np.concatenate([[0], np.cumsum([d for _, _, d in br])])
+    LB = left_basis(mps, l)
+    RB = right_basis(mps, l + 1)
+    lmask = _config_masks(0, l)
+    rmask = _config_masks(l + 1, K - l - 1)
+    keys = [(k[0], k[1], k[-1]) for k in blocks]
+    ncols = sum(bl[a][2] * br[b][2] for a, _, b in keys)
+    P = np.zeros((basis.size, ncols))
+    col = 0
+    for ia, s, ib in keys:
+        m = (_LOCAL_OCC[s][0] << (2 * l)) | (_LOCAL_OCC[s][1] << (2 * l + 1))
+        full = (lmask[:, None] | rmask[None, :]) | m
+        pos = np.searchsorted(basis, full.reshape(-1))
+        pos = np.minimum(pos, basis.size - 1)
+        hit = basis[pos] == full.reshape(-1)
+        for a in range(bl[ia][2]):
+            la = LB[:, offl[ia] + a]
+            for b in range(br[ib][2]):
+                amp = np.outer(la, RB[offr[ib] + b, :]).reshape(-1)
+                nz = hit & (amp != 0.0)
+                P[pos[nz], col] += amp[nz]
+                col += 1
+    return P
+
+
+def effective_hamiltonian_one_site(spec: dict, mps: dict, blocks: list) -> np.ndarray:
+    """Dense one-site H_eff = P1^T H P1 of the site tensor at mps['center']."""
+    basis = sector_basis(spec["n_orb"], spec["n_elec"], spec["two_sz"])
+    H = hamiltonian_matrix(spec, basis)
+    P = one_site_isometry(mps, basis, blocks)
+    return P.T @ (H @ P)
+
+
 def ground_energy(spec: dict, k: int = 1) -> np.ndarray:
     """Lowest k eigenvalues of H in its sector (exact diagonalisation)."""
     H = hamiltonian_matrix(spec)

@@ -268,6 +268,20 @@ lcc_status lcc_build_environments(lcc_context ctx, lcc_hamiltonian ham, const lc
   });
 }
 
+lcc_status lcc_build_environments_one_site(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* mps,
+                                           int32_t site, lcc_env* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    if (!ham || !mps) throw Error{LCC_ERR_ARG, "NULL argument"};
+    std::unique_ptr<lcc_env_s> e(new lcc_env_s());
+    e->e = build_env(&ctx->c, ham->h, *mps, site, true);
+    *out = e.release();
+    return LCC_OK;
+  });
+}
+
 lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* bra,
                                              const lcc_mps_desc* ket, int32_t site, lcc_env* out) {
   if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");

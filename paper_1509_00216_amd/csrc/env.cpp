@@ -562,25 +562,32 @@ int channel_of_kind(const Mpo& mpo, int bond, int kind) {
 // ---------------------------------------------------------------------------------------
 // build_env: environments, enlarged operators, vector layout, and the apply plan
 // ---------------------------------------------------------------------------------------
-Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int site) {
+Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& md, int site, bool one_site) {
   hipStream_t st = ctx->stream;
   const Mpo& mpo = ham.mpo;
   const int K = mpo.K;
   if (md.n_sites != K) throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
-  if (site < 0 || site + 1 >= K) throw Error{LCC_ERR_ARG, "two-site block must satisfy 0 <= site < K-1"};
+  if (one_site) {
+    if (site < 0 || site >= K) throw Error{LCC_ERR_ARG, "one-site problem must satisfy 0 <= site < K"};
+  } else if (site < 0 || site + 1 >= K) {
+    throw Error{LCC_ERR_ARG, "two-site block must satisfy 0 <= site < K-1"};
+  }
   DeviceMps mps;
   load_mps(md, ham.desc.N, ham.desc.two_sz, st, mps);
 
-  // left environment at MPS bond `site`, right environment at MPS bond `site + 2`
+  // left environment at MPS bond `site`, right environment at MPS bond `site + 2` (two sites) or
+  // `site + 1` (one site)
+  const int rb = one_site ? site + 1 : site + 2;
   Environment L = unit_env(st);
   for (int j = 0; j < site; ++j) L = left_step(L, mps, j, mpo, st);
   Environment R = unit_env(st);
-  for (int j = K - 1; j >= site + 2; --j) R = right_step(R, mps, j, mpo, st);
+  for (int j = K - 1; j >= rb; --j) R = right_step(R, mps, j, mpo, st);
   // the identity channel of each environment certifies the canonical form of its sites
-  const int w_left_id = channel_of_kind(mpo, site, 0), w_right_id = channel_of_kind(mpo, site + 2, 1);
+  const int w_left_id = channel_of_kind(mpo, site, 0), w_right_id = channel_of_kind(mpo, rb, 1);
   if (site > 0 && w_left_id >= 0) check_identity(L, w_left_id, mps.bonds[site], st, "left");
-  if (site + 2 < K && w_right_id >= 0) check_identity(R, w_right_id, mps.bonds[site + 2], st, "right");
-  return make_env(ctx, mpo, site, mps.bonds[site], mps.bonds[site + 2], L, R);
+  if (rb < K && w_right_id >= 0) check_identity(R, w_right_id, mps.bonds[rb], st, "right");
+  return make_env(ctx, mpo, site, mps.bonds[site], mps.bonds[rb], mps.bonds[site], mps.bonds[rb], L, R, false,
+                  one_site);
 }
 
 // The MPO of the identity operator: one channel on every bond, the identity on every site.
@@ -1014,11 +1021,12 @@ namespace {
 int64_t middle_sectors(const Bond& bl, const Bond& br, std::vector<MiddleSector>& sectors, std::map<QN, int>& sec_index,
                        std::vector<lcc_block_entry>& layout,
                        std::map<std::pair<int, int>, std::pair<int, int>>& row_at,
-                       std::map<std::pair<int, int>, std::pair<int, int>>& col_at) {
+                       std::map<std::pair<int, int>, std::pair<int, int>>& col_at, bool one_site) {
   std::map<QN, MiddleSector> secs;
   for (size_t a = 0; a < bl.q.size(); ++a)
     for (int s1 = 0; s1 < 4; ++s1) secs[bl.q[a] + local_qn(s1)].rows.push_back({(int)a, s1});
-  for (int s2 = 0; s2 < 4; ++s2)
+  // one site: the columns are the right bond alone (one trivial local state, s2 = 0, no charge)
+  for (int s2 = 0; s2 < (one_site ? 1 : 4); ++s2)
     for (size_t b = 0; b < br.q.size(); ++b) {
       auto it = secs.find(br.q[b] - local_qn(s2));
       if (it != secs.end()) it->second.cols.push_back({s2, (int)b});
@@ -1064,7 +1072,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
 }
 
 Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const Bond& bond_r, const Bond& ket_l,
-              const Bond& ket_r, const Environment& L, const Environment& R, bool transition) {
+              const Bond& ket_r, const Environment& L, const Environment& R, bool transition, bool one_site) {
   hipStream_t st = ctx->stream;
   const int K = mpo.K;
   std::unique_ptr<Env> env(new Env());
@@ -1076,7 +1084,8 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
   env->bl_in = ket_l;
   env->br_in = ket_r;
   env->transition = transition;
-  const int mid = site + 1;  // MPO bond between the two sites
+  env->one_site = one_site;
+  const int mid = site + 1;  // MPO bond between the two sites (one site: between the site and R)
   env->D_mid = (int)mpo.dq[mid].size();
 
   // ---- middle-bond sectors and the vector layouts (output: bra; input: ket)
@@ -1084,9 +1093,10 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
   auto& col_at = env->in.col_at;
   auto& row_at_in = env->in.row_at_in;
   auto& col_at_in = env->in.col_at_in;
-  env->n_elements = middle_sectors(env->bl, env->br, env->sectors, env->in.sec_index, env->layout, row_at, col_at);
+  env->n_elements =
+      middle_sectors(env->bl, env->br, env->sectors, env->in.sec_index, env->layout, row_at, col_at, one_site);
   env->n_in = middle_sectors(env->bl_in, env->br_in, env->sectors_in, env->in.sec_index_in, env->layout_in, row_at_in,
-                             col_at_in);
+                             col_at_in, one_site);
 
   // ---- environment data on the device: [L | R]
   env->env_elems = L.size + R.size;
@@ -1113,19 +1123,27 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
         }
     }
   std::map<std::tuple<int, int, int, int, int>, std::vector<std::pair<int, double>>> rt_terms;
-  std::vector<std::vector<int>> R_by_w(mpo.dq[site + 2].size());
-  for (size_t i = 0; i < R.blocks.size(); ++i) R_by_w[R.blocks[i].w].push_back((int)i);
-  for (const MpoEntry& e : mpo.W[site + 1])
-    for (int bi : R_by_w[e.wout]) {
+  if (one_site) {  // Rt^{w1} = R^{w1}: the right environment itself, on the trivial local state
+    for (size_t bi = 0; bi < R.blocks.size(); ++bi) {
       const EnvBlock& rb = R.blocks[bi];
-      for (int sp = 0; sp < 4; ++sp)
-        for (int s = 0; s < 4; ++s) {
-          const double c = e.m[sp * 4 + s];
-          if (c == 0.0) continue;
-          if (!col_at.count({sp, rb.r}) || !col_at_in.count({s, rb.c})) continue;
-          rt_terms[std::make_tuple(e.win, sp, rb.r, s, rb.c)].push_back({bi, c});
-        }
+      if (!col_at.count({0, rb.r}) || !col_at_in.count({0, rb.c})) continue;
+      rt_terms[std::make_tuple(rb.w, 0, rb.r, 0, rb.c)].push_back({(int)bi, 1.0});
     }
+  } else {
+    std::vector<std::vector<int>> R_by_w(mpo.dq[site + 2].size());
+    for (size_t i = 0; i < R.blocks.size(); ++i) R_by_w[R.blocks[i].w].push_back((int)i);
+    for (const MpoEntry& e : mpo.W[site + 1])
+      for (int bi : R_by_w[e.wout]) {
+        const EnvBlock& rb = R.blocks[bi];
+        for (int sp = 0; sp < 4; ++sp)
+          for (int s = 0; s < 4; ++s) {
+            const double c = e.m[sp * 4 + s];
+            if (c == 0.0) continue;
+            if (!col_at.count({sp, rb.r}) || !col_at_in.count({s, rb.c})) continue;
+            rt_terms[std::make_tuple(e.win, sp, rb.r, s, rb.c)].push_back({bi, c});
+          }
+      }
+  }
   // references, merging multi-term entries
   MixBuilder merge;
   int64_t merged = 0;

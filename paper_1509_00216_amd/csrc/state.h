@@ -239,7 +239,9 @@ struct Env {
   Context* ctx = nullptr;
   int site = 0, K = 0;
   int D_mid = 0;
-  Bond bl, br;  // MPS bonds site and site+2 (of the bra: rows of the operator, the output vector)
+  Bond bl, br;  // MPS bonds site and site+2 (of the bra: rows of the operator, the output vector);
+                // site and site+1 for the one-site problem
+  bool one_site = false;  // vectors are one-site tensors x[a, s, b] (columns: one trivial state)
   std::vector<MiddleSector> sectors;
   std::vector<lcc_block_entry> layout;
   int64_t n_elements = 0;
@@ -309,7 +311,7 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
               const Environment& L, const Environment& R);
 // the transition operator between a bra (bonds bra_l, bra_r; rows of L and R) and a ket
 Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bra_l, const Bond& bra_r, const Bond& ket_l,
-              const Bond& ket_r, const Environment& L, const Environment& R, bool transition);
+              const Bond& ket_r, const Environment& L, const Environment& R, bool transition, bool one_site = false);
 Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& bra, const lcc_mps_desc& ket,
                           int site);
 // x0 of a transition operator from the ket's site tensors (site from t1, site + 1 from t2)
@@ -317,7 +319,8 @@ void build_ket_tensor(Env& env, const DeviceMps& t1, const DeviceMps& t2, hipStr
 Mpo identity_mpo(int K);
 
 // env.cpp
-Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site);
+// two-site block (site, site+1), or with one_site the one-site tensor at `site`
+Env* build_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& mps, int site, bool one_site = false);
 void ensure_fp32(Env& env);
 // diag(H_eff) into env.diag64 (once)
 void compute_diagonal(Env& env);

@@ -23,7 +23,7 @@ STATUS = {0: "LCC_OK", 1: "LCC_NOT_CONVERGED", -1: "LCC_ERR_ARG", -2: "LCC_ERR_Q
 EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_context_synchronize",
            "lcc_create_hamiltonian", "lcc_hamiltonian_destroy", "lcc_hamiltonian_bond_dims",
            "lcc_hamiltonian_channels", "lcc_hamiltonian_site_mpo", "lcc_build_environments",
-           "lcc_env_destroy", "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
+           "lcc_build_environments_one_site", "lcc_env_destroy", "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
            "lcc_env_profile_apply", "lcc_lowest_eigenvalue", "lcc_env_profile_launches", "lcc_batch_create",
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
@@ -130,6 +130,7 @@ def library() -> C.CDLL:
         "lcc_hamiltonian_site_mpo": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "lcc_build_environments": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
+        "lcc_build_environments_one_site": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
         "lcc_env_destroy": (None, [P]),
         "lcc_env_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
         "lcc_env_input_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
@@ -259,6 +260,9 @@ class Context:
 
     def build_environments(self, ham: "Hamiltonian", mps: dict, site: int | None = None) -> "Env":
         return build_environments(self, ham, mps, site)
+
+    def build_environments_one_site(self, ham: "Hamiltonian", mps: dict, site: int | None = None) -> "Env":
+        return build_environments_one_site(self, ham, mps, site)
 
 
 def context_create(device: int = 0, stream=None) -> Context:
@@ -514,6 +518,19 @@ def build_environments(ctx: Context, ham: Hamiltonian, mps: dict, site: int | No
     desc, keep = _mps_desc(mps)
     out = C.c_void_p()
     _check(library().lcc_build_environments(ctx.handle, ham.handle, C.byref(desc), site, C.byref(out)), ctx.handle)
+    del keep
+    return Env(out, ctx)
+
+
+def build_environments_one_site(ctx: Context, ham: Hamiltonian, mps: dict, site: int | None = None) -> Env:
+    """lcc_build_environments_one_site: the local problem of the one site tensor at `site`
+    (default mps['center']); vector blocks are keyed (a, s, 0, b)."""
+    if site is None:
+        site = mps["center"]
+    desc, keep = _mps_desc(mps)
+    out = C.c_void_p()
+    _check(library().lcc_build_environments_one_site(ctx.handle, ham.handle, C.byref(desc), site, C.byref(out)),
+           ctx.handle)
     del keep
     return Env(out, ctx)
 

@@ -1,0 +1,131 @@
+"""The one-site local problem on the device (lcc_build_environments_one_site: the unknown is one
+site tensor, Implementation section, local-derivative figure and sweep) against the oracle's
+one-site effective Hamiltonian (oracle.fock.effective_hamiltonian_one_site, pinned in
+test_oracle_one_site.py) and, at full size, its block-sparse route through the two-site
+environments (oracle.blocksparse.one_site_apply).
+
+* H1 x in FP64 / FP32 / BF16x3 at the first, a middle and the last site (bars 1e-12 / 1e-5 /
+  1e-4 relative, as for the two-site product), and at the 4x4 Hubbard model with M = 500;
+* the exact ground state: its site tensor is mapped to E0 times itself;
+* the local solve (FP64 and mixed) against the dense solution of the same system, and the
+  lowest eigenpair against dense diagonalisation.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import need_gpu, rel, say, to_dev
+from oracle import blocksparse as BS
+from oracle import fock
+from oracle import mpo as OM
+from workloads import configs as C
+from workloads import hamiltonians as H
+from workloads import mps as M
+
+pytestmark = pytest.mark.gpu
+
+SYSTEMS = {
+    "abinitio_k6_m10": lambda: (H.random_ab_initio(6, 6, seed=21), M.random_mps(6, 6, 0, 10, seed=22, center=2)),
+    "hubbard_4x2_m16": lambda: (H.hubbard_2d(4, 2, U=4.0, n_elec=7, two_sz=1),
+                                M.random_mps(8, 7, 1, 16, seed=8, center=3)),
+}
+
+
+def _keys(m1):
+    return [(a, s, 0, b) for a, s, b in M.one_site_blocks(m1)]
+
+
+def _apply(torch, env, xf, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    x = to_dev(torch, xf, dt)
+    y = torch.empty_like(x)
+    env.apply_heff(x, y, prec)
+    return y.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", sorted(SYSTEMS))
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_apply_vs_dense(name, where):
+    torch, lcc = need_gpu()
+    spec, mps = SYSTEMS[name]()
+    K = spec["n_orb"]
+    site = {"first": 0, "middle": mps["center"], "last": K - 1}[where]
+    m1 = M.canonical_at(mps, site)
+    keys = _keys(m1)
+    H1 = fock.effective_hamiltonian_one_site(spec, m1, keys)
+    ctx = lcc.Context(0)
+    env = ctx.build_environments_one_site(ctx.create_hamiltonian(spec), m1, site)
+    assert env.n == H1.shape[0]
+    x = M.random_one_site_vector(m1, 3)
+    xf = env.pack(x)
+    yref = env.pack(BS.unflatten(H1 @ BS.flatten(x, keys), x, keys))
+    err = {p: rel(_apply(torch, env, xf, p), yref) for p in ("fp64", "fp32", "bf16x3")}
+    say(f"[one-site] {name} site {site} n={env.n}: {err}")
+    assert err["fp64"] <= 1e-12
+    assert err["fp32"] <= 1e-5
+    assert err["bf16x3"] <= 1e-4
+
+
+def test_apply_full_size_vs_blocksparse():
+    torch, lcc = need_gpu()
+    spec, mps = C.make("hubbard2d_4x4_m500")
+    site = mps["center"]
+    m1 = M.canonical_at(mps, site)
+    ctx = lcc.Context(0)
+    say("[one-site] hubbard2d 4x4 M=500: build")
+    env = ctx.build_environments_one_site(ctx.create_hamiltonian(spec), m1, site)
+    x = M.random_one_site_vector(m1, 4)
+    say(f"[one-site] n={env.n}: oracle")
+    yref = env.pack(BS.one_site_apply(spec, m1, OM.build_mpo(spec), x))
+    xf = env.pack(x)
+    err = {p: rel(_apply(torch, env, xf, p), yref) for p in ("fp64", "fp32", "bf16x3")}
+    say(f"[one-site] full size errors {err}")
+    assert err["fp64"] <= 1e-12
+    assert err["fp32"] <= 1e-5
+    assert err["bf16x3"] <= 1e-4
+
+
+@pytest.mark.parametrize("site", [0, 3, 5])
+def test_exact_ground_state_site_tensor(site):
+    torch, lcc = need_gpu()
+    spec = dict(H.random_ab_initio(6, 6, two_sz=0, seed=11), e_const=0.3)
+    basis = fock.sector_basis(6, 6, 0)
+    w, V = np.linalg.eigh(fock.hamiltonian_matrix(spec, basis).toarray())
+    full = np.zeros(4 ** 6)
+    full[fock.config_index(basis, 6)] = V[:, 0]
+    m1 = M.canonical_at(M.mps_from_amplitudes(full, 6, 6, 0), site)
+    ctx = lcc.Context(0)
+    env = ctx.build_environments_one_site(ctx.create_hamiltonian(spec), m1, site)
+    a = env.pack({(il, s, 0, ir): A for il, s, ir, A in m1["sites"][site]})
+    y = _apply(torch, env, a, "fp64")
+    say(f"[one-site] exact ground state, site {site}: |H1 a - E0 a| = {np.abs(y - w[0] * a).max():.2e}")
+    assert np.abs(y - w[0] * a).max() <= 1e-11 * abs(w[0])
+
+
+def test_solve_and_eigenpair_vs_dense():
+    torch, lcc = need_gpu()
+    spec, mps = SYSTEMS["hubbard_4x2_m16"]()
+    site = mps["center"]
+    m1 = M.canonical_at(mps, site)
+    keys = _keys(m1)
+    H1 = fock.effective_hamiltonian_one_site(spec, m1, keys)
+    w = np.linalg.eigvalsh(H1)
+    e0 = w[0] - 0.5
+    bvec = M.random_one_site_vector(m1, 9)
+    bflat = BS.flatten(bvec, keys)
+    xstar = np.linalg.solve(H1 - e0 * np.eye(H1.shape[0]), bflat)
+    jstar = -float(bflat @ xstar)
+    ctx = lcc.Context(0)
+    env = ctx.build_environments_one_site(ctx.create_hamiltonian(spec), m1, site)
+    b = to_dev(torch, env.pack(bvec), torch.float64)
+    for prec in ("fp64", "fp32"):
+        x = torch.zeros_like(b)
+        info = env.solve_local_lcc(b, e0, x, precision=prec, tol=1e-11, max_iter=2000, inner_tol=1e-4, max_outer=50)
+        say(f"[one-site] solve {prec}: J {info['hylleraas']:.14f} (dense {jstar:.14f}), {info['iterations']} it")
+        assert info["status"] == "LCC_OK"
+        assert abs(info["hylleraas"] - jstar) <= 1e-10 * abs(jstar)
+        assert rel(x.cpu().numpy(), env.pack(BS.unflatten(xstar, bvec, keys))) <= 1e-9
+    x = torch.zeros_like(b)
+    info = env.lowest_eigenpair(x, steps=40, max_restarts=40, tol=1e-11, seed=3)
+    say(f"[one-site] eigenpair {info['theta']:.14f} (dense {w[0]:.14f})")
+    assert info["status"] == "LCC_OK"
+    assert abs(info["theta"] - w[0]) <= 1e-10

@@ -116,6 +116,77 @@ def _site_blocks(bond_l, bond_r):
     return out
 
 
+def _left_canonical_site(sites: list, j: int) -> None:
+    """Gauge step: site j becomes left-canonical (a QR per right sector, diag(R) >= 0), the
+    triangular factor moves into site j+1.  The state is unchanged."""
+    by_right = {}
+    for blk in sites[j]:
+        by_right.setdefault(blk[2], []).append(blk)
+    for ir, blks in by_right.items():
+        blks.sort(key=lambda b: (b[1], b[0]))
+        stacked = np.concatenate([b[3] for b in blks], axis=0)
+        q, r = np.linalg.qr(stacked)
+        sgn = np.sign(np.diag(r))
+        sgn[sgn == 0] = 1.0
+        q = q * sgn
+        r = sgn[:, None] * r
+        off = 0
+        for b in blks:
+            rows = b[3].shape[0]
+            b[3] = np.ascontiguousarray(q[off:off + rows])
+            off += rows
+        for nb in sites[j + 1]:
+            if nb[0] == ir:
+                nb[3] = r @ nb[3]
+
+
+def _right_canonical_site(sites: list, j: int) -> None:
+    """Gauge step: site j becomes right-canonical (an LQ per left sector, diag(L) >= 0), the
+    triangular factor moves into site j-1.  The state is unchanged."""
+    by_left = {}
+    for blk in sites[j]:
+        by_left.setdefault(blk[0], []).append(blk)
+    for il, blks in by_left.items():
+        blks.sort(key=lambda b: (b[1], b[2]))
+        stacked = np.concatenate([b[3] for b in blks], axis=1)
+        q, r = np.linalg.qr(stacked.T)
+        sgn = np.sign(np.diag(r))
+        sgn[sgn == 0] = 1.0
+        q = q * sgn
+        r = sgn[:, None] * r
+        qt = q.T
+        off = 0
+        for b in blks:
+            cols = b[3].shape[1]
+            b[3] = np.ascontiguousarray(qt[:, off:off + cols])
+            off += cols
+        for pb in sites[j - 1]:
+            if pb[2] == il:
+                pb[3] = pb[3] @ r.T
+
+
+def canonical_at(mps: dict, l: int) -> dict:
+    """The same state in the gauge of the one-site problem at site l: sites 0..l-1
+    left-canonical, sites l+1..K-1 right-canonical, center l."""
+    sites = [[list(b) for b in blks] for blks in mps["sites"]]
+    for j in range(l):
+        _left_canonical_site(sites, j)
+    for j in range(mps["n_sites"] - 1, l, -1):
+        _right_canonical_site(sites, j)
+    return dict(mps, center=l, sites=[[tuple(b) for b in blks] for blks in sites])
+
+
+def one_site_gauge(mps: dict) -> dict:
+    """The same state with site center+1 made right-canonical as well (its factor moves into the
+    site at the center): the gauge of the one-site problem at mps['center'], whose left sites are
+    left-canonical and right sites right-canonical."""
+    l = mps["center"]
+    sites = [[list(b) for b in blks] for blks in mps["sites"]]
+    if l + 1 < mps["n_sites"]:
+        _right_canonical_site(sites, l + 1)
+    return dict(mps, sites=[[tuple(b) for b in blks] for blks in sites])
+
+
 def random_mps(n_sites: int, n_elec: int, two_sz: int, m_max: int, seed: int,
                center: int | None = None, jitter_sigma: float = 0.0) -> dict:
     """Gaussian random MPS, left-canonical left of `center`, right-canonical right of center+1."""
@@ -135,47 +206,10 @@ def random_mps(n_sites: int, n_elec: int, two_sz: int, m_max: int, seed: int,
         sites.append(blocks)
     # left-canonical sweep over sites 0..center-1
     for j in range(center):
-        by_right = {}
-        for blk in sites[j]:
-            by_right.setdefault(blk[2], []).append(blk)
-        for ir, blks in by_right.items():
-            blks.sort(key=lambda b: (b[1], b[0]))
-            stacked = np.concatenate([b[3] for b in blks], axis=0)
-            q, r = np.linalg.qr(stacked)
-            sgn = np.sign(np.diag(r))
-            sgn[sgn == 0] = 1.0
-            q = q * sgn
-            r = sgn[:, None] * r
-            off = 0
-            for b in blks:
-                rows = b[3].shape[0]
-                b[3] = np.ascontiguousarray(q[off:off + rows])
-                off += rows
-            for nb in sites[j + 1]:
-                if nb[0] == ir:
-                    nb[3] = r @ nb[3]
+        _left_canonical_site(sites, j)
     # right-canonical sweep over sites K-1..center+2
     for j in range(n_sites - 1, center + 1, -1):
-        by_left = {}
-        for blk in sites[j]:
-            by_left.setdefault(blk[0], []).append(blk)
-        for il, blks in by_left.items():
-            blks.sort(key=lambda b: (b[1], b[2]))
-            stacked = np.concatenate([b[3] for b in blks], axis=1)
-            q, r = np.linalg.qr(stacked.T)
-            sgn = np.sign(np.diag(r))
-            sgn[sgn == 0] = 1.0
-            q = q * sgn
-            r = sgn[:, None] * r
-            qt = q.T
-            off = 0
-            for b in blks:
-                cols = b[3].shape[1]
-                b[3] = np.ascontiguousarray(qt[:, off:off + cols])
-                off += cols
-            for pb in sites[j - 1]:
-                if pb[2] == il:
-                    pb[3] = pb[3] @ r.T
+        _right_canonical_site(sites, j)
     return {
         "n_sites": n_sites,
         "n_elec": n_elec,
@@ -199,6 +233,33 @@ def two_site_blocks(mps: dict) -> list:
                 if ib is not None:
                     out.append((ia, s1, s2, ib))
     return sorted(out)
+
+
+def one_site_blocks(mps: dict) -> list:
+    """Allowed (left_sector, s, right_sector) blocks of the one-site tensor at the center."""
+    l = mps["center"]
+    bl, br = mps["bonds"][l], mps["bonds"][l + 1]
+    index_r = {(n, sz): i for i, (n, sz, _) in enumerate(br)}
+    out = []
+    for ia, (n, sz, _) in enumerate(bl):
+        for s, (d, z) in enumerate(LOCAL_QN):
+            ib = index_r.get((n + d, sz + z))
+            if ib is not None:
+                out.append((ia, s, ib))
+    return sorted(out)
+
+
+def random_one_site_vector(mps: dict, seed: int) -> dict:
+    """Gaussian one-site tensor, normalised to unit 2-norm, as {(ia, s, 0, ib): array} (the key
+    form of the library's one-site layout, whose second local index is the trivial 0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    l = mps["center"]
+    bl, br = mps["bonds"][l], mps["bonds"][l + 1]
+    vec = {}
+    for ia, s, ib in one_site_blocks(mps):
+        vec[(ia, s, 0, ib)] = rng.standard_normal((bl[ia][2], br[ib][2]))
+    nrm = np.sqrt(sum(float(np.sum(v * v)) for v in vec.values()))
+    return {k: v / nrm for k, v in vec.items()}
 
 
 def random_two_site_vector(mps: dict, seed: int) -> dict:
