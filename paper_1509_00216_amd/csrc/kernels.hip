@@ -647,21 +647,26 @@ struct BLoader {
   }
 };
 
-// LDS tiles [k][r] of the term-walk kernel: row pitch r + 2 words (FP32) or r + 1 doubles.
-// A wider pitch (16 mod 64 words) makes the operand reads conflict-free but puts the 32 k of
-// a staging store on 4 banks, and an XOR swizzle that fixes both costs address registers and
-// a wave of occupancy; both measured slower.
+// LDS tiles [k][r] of the term-walk kernel: row pitch r + 1 words for the FP32 kernel, r + 2
+// words for the BF16x3 kernel (whose lanes read eight consecutive k rows), r + 1 doubles for
+// FP64.  The bank-conflict counter behaves as if the LDS served a wave in halves of 32 lanes
+// over 32 four-byte banks; in that model, with pitch r + 1
+// the 32 k of a staging store (32 lanes, one row r) fall on 32 banks, and the operand reads of
+// full chunks below are spread so that the two lane groups of a half read rows 16 apart
+// (16 pitches = 16 banks apart).  The FP32 kernel's bank-conflict cycles are a third of those
+// of pitch r + 2, whose stores put the 32 k on 16 banks.
 template <class T>
 struct KPitch {
   static constexpr int of(int r) { return r + (sizeof(T) == 8 ? 1 : 2); }
 };
 
 // MFMAs of one staged chunk of the term-walk kernel (LDS tiles [k][m], [k][n]); ni, nj, arow,
-// bcol as for packed_chunk.  A full chunk is walked in BK/4 steps where step s gives lane group
-// g = lane/16 the k index s + (BK/4) g: the four groups then read LDS rows BK/4 apart, which the
-// row pitch (r + 2 words for FP32) puts on disjoint banks.  A partial chunk (the last chunk of a
-// short term) takes k = 4 s + g instead, so that steps wholly past the term's end are skipped.
-// The sum over k is the same for any assignment that A and B share.
+// bcol as for packed_chunk.  A full FP32 chunk is walked in BK/4 steps where step s gives lane
+// group g = lane/16 the k index s + (BK/2)(g & 1) + (BK/4)(g >> 1): groups 0 and 1 (one half of
+// the wave) read rows BK/2 = 16 apart, as do groups 2 and 3, which the row pitch r + 1 puts 16
+// banks apart.  A partial chunk (the last chunk of a short term) takes k = 4 s + g instead, so
+// that steps wholly past the term's end are skipped.  The sum over k is the same for any
+// assignment that A and B share.
 template <int MODE, int BK, int TM, int TN, class TA_, class TB_>
 __device__ __forceinline__ void terms_chunk(const TA_& As, const TB_& Bs, int arow, int bcol, int kmax, int ni,
                                             int nj, typename Mfma<MODE>::Acc (&acc)[TM][TN]) {
@@ -669,7 +674,8 @@ __device__ __forceinline__ void terms_chunk(const TA_& As, const TB_& Bs, int ar
   const int lane = threadIdx.x & 63;
   // FP32 full chunk: row of step st = st + (BK/4) g; otherwise 4 st + g
   const bool spread = MODE == 1 && kmax >= BK;
-  const int r0 = spread ? (BK / 4) * (lane >> 4) : (lane >> 4);
+  const int g = lane >> 4;
+  const int r0 = spread ? (BK / 2) * (g & 1) + (BK / 4) * (g >> 1) : g;
   const int rs = spread ? 1 : 4;
 #pragma unroll
   for (int st = 0; st < BK / 4; ++st) {
@@ -765,8 +771,10 @@ __device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ ter
   constexpr int NT = 64 * WM * WN;
   typedef ALoader<T, TA, BM, BK, NT> LA;
   typedef BLoader<T, TB, BN, BK, NT> LB;
-  __shared__ T As[BK][KPitch<T>::of(BM)];
-  __shared__ T Bs[BK][KPitch<T>::of(BN)];
+  constexpr int PA = MODE == 1 ? BM + 1 : KPitch<T>::of(BM);  // see KPitch
+  constexpr int PB = MODE == 1 ? BN + 1 : KPitch<T>::of(BN);
+  __shared__ T As[BK][PA];
+  __shared__ T Bs[BK][PB];
 
   __shared__ BaseTable<T> bt;
   const int tid = threadIdx.x;
