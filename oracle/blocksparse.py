@@ -179,15 +179,17 @@ class MiddleBondEnvironments:
     The two-site vector is one matrix X_q per middle-bond sector q (rows (a, s1), columns
     (s2, b)), so that y is Y_{q'} = sum_{w1} Lt^{w1} X_q Rt^{w1 T} with q' = q + dq(w1)."""
 
-    def __init__(self, spec: dict, mps: dict, mpo: dict):
+    def __init__(self, spec: dict, mps: dict, mpo: dict, one_site: bool = False):
+        """one_site: the problem of the site tensor at the center (columns b of the next bond,
+        written (0, b); Rt^{w1} = R^{w1}, the right environment of the sites right of it)."""
         from .flops import middle_sectors
         self.mps = mps
         l = self.l = mps["center"]
-        self.bl, self.br = mps["bonds"][l], mps["bonds"][l + 2]
+        self.bl, self.br = mps["bonds"][l], mps["bonds"][l + (1 if one_site else 2)]
         self.dq = mpo["dq"][l + 1]
         L = left_environments(mps, mpo, l)
-        R = right_environments(mps, mpo, l + 2)
-        self.secs = middle_sectors(mps)
+        R = right_environments(mps, mpo, l + (1 if one_site else 2))
+        self.secs = middle_sectors(mps, one_site)
         self.row_at, self.col_at = {}, {}
         for i, S in enumerate(self.secs):
             off = 0
@@ -207,6 +209,12 @@ class MiddleBondEnvironments:
                             key = ((ap, sp), (a, s))
                             d = self.lt.setdefault(w1, {})
                             d[key] = d.get(key, 0.0) + m[sp, s] * blk
+        if one_site:
+            for w1, blocks in R.items():
+                for (bp, b), blk in blocks.items():
+                    if (0, bp) in self.col_at and (0, b) in self.col_at:
+                        self.rt.setdefault(w1, {})[((0, bp), (0, b))] = blk
+            return
         for (w1, w2), m in mpo["W"][l + 1].items():
             for (bp, b), blk in R.get(w2, {}).items():
                 for sp in range(4):

@@ -185,17 +185,19 @@ def canonical_flops(mps: dict, mpo: dict) -> dict:
     return {"k1": k1, "k2": k2, "k3": k3, "total": k1 + k2 + k3}
 
 
-def middle_sectors(mps: dict) -> list:
+def middle_sectors(mps: dict, one_site: bool = False) -> list:
     """Middle-bond sectors q of the two-site block with their rows (a, s1) and columns (s2, b),
-    in (N, 2Sz) order; rows by (a, s1), columns by (s2, b)."""
+    in (N, 2Sz) order; rows by (a, s1), columns by (s2, b).  one_site: the site tensor at the
+    center, rows (a, s1) and columns b of the next bond, written (0, b) (the empty local state,
+    no charge)."""
     l = mps["center"]
-    bl, br = mps["bonds"][l], mps["bonds"][l + 2]
+    bl, br = mps["bonds"][l], mps["bonds"][l + (1 if one_site else 2)]
     rows, cols = {}, {}
     for ia in range(len(bl)):
         n, z = _qn(bl, ia)
         for s1, (d1, z1) in enumerate(LOCAL_QN):
             rows.setdefault((n + d1, z + z1), []).append((ia, s1))
-    for s2, (d2, z2) in enumerate(LOCAL_QN):
+    for s2, (d2, z2) in enumerate(LOCAL_QN[:1] if one_site else LOCAL_QN):
         for ib in range(len(br)):
             n, z = _qn(br, ib)
             cols.setdefault((n - d2, z - z2), []).append((s2, ib))
@@ -209,14 +211,15 @@ def middle_sectors(mps: dict) -> list:
     return out
 
 
-def enlarged_structure(mps: dict, mpo: dict):
+def enlarged_structure(mps: dict, mpo: dict, one_site: bool = False):
     """Nonzero blocks of the enlarged operators of the middle bond:
     lt[w1] = set of ((a', s1'), (a, s1)),  rt[w1] = set of ((s2', b'), (s2, b)),
-    restricted to rows and columns of the block's middle sectors."""
+    restricted to rows and columns of the block's middle sectors.  one_site: rt[w1] is the right
+    environment R^{w1} of the sites right of the center itself, on columns (0, b)."""
     l = mps["center"]
     L = left_structure(mps, mpo, l)
-    R = right_structure(mps, mpo, l + 2)
-    secs = middle_sectors(mps)
+    R = right_structure(mps, mpo, l + (1 if one_site else 2))
+    secs = middle_sectors(mps, one_site)
     row_ok = {r for S in secs for r in S["rows"]}
     col_ok = {c for S in secs for c in S["cols"]}
     lt, rt = {}, {}
@@ -226,6 +229,12 @@ def enlarged_structure(mps: dict, mpo: dict):
                 for s in range(4):
                     if m[sp, s] != 0.0 and (ap, sp) in row_ok and (a, s) in row_ok:
                         lt.setdefault(w1, set()).add(((ap, sp), (a, s)))
+    if one_site:
+        for w1, blocks in R.items():
+            for (bp, b) in blocks:
+                if (0, bp) in col_ok and (0, b) in col_ok:
+                    rt.setdefault(w1, set()).add(((0, bp), (0, b)))
+        return secs, lt, rt
     for (w1, w2), m in mpo["W"][l + 1].items():
         for (bp, b) in R.get(w2, ()):
             for sp in range(4):
@@ -235,14 +244,15 @@ def enlarged_structure(mps: dict, mpo: dict):
     return secs, lt, rt
 
 
-def factorised_flops(mps: dict, mpo: dict, order: str = "left") -> dict:
+def factorised_flops(mps: dict, mpo: dict, order: str = "left", one_site: bool = False) -> dict:
     """Counts of the middle-bond factorisation, {'left', 'right', 'total'} (integers), with the
-    left (order "left") or the right (order "right") enlarged operator applied first."""
+    left (order "left") or the right (order "right") enlarged operator applied first; one_site:
+    of the one-site problem at the center (right enlarged operator = R)."""
     if order not in ("left", "right"):
         raise ValueError(order)
     l = mps["center"]
-    bl, br = mps["bonds"][l], mps["bonds"][l + 2]
-    secs, lt, rt = enlarged_structure(mps, mpo)
+    bl, br = mps["bonds"][l], mps["bonds"][l + (1 if one_site else 2)]
+    secs, lt, rt = enlarged_structure(mps, mpo, one_site)
     sec_of_row = {r: i for i, S in enumerate(secs) for r in S["rows"]}
     sec_of_col = {c: i for i, S in enumerate(secs) for c in S["cols"]}
     index = {S["q"]: i for i, S in enumerate(secs)}

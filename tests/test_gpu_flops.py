@@ -36,3 +36,21 @@ def test_planner_flops_equal_oracle_count(label, make, order):
     say(f"  planner {f1:.0f} + {f2:.0f}   oracle {ref['left']} + {ref['right']}")
     assert (int(f1), int(f2)) == (ref["left"], ref["right"])
     assert env.flops_per_apply == float(ref["total"])
+
+
+@pytest.mark.parametrize("order", ["left", "right"])
+@pytest.mark.parametrize("name", ["hubbard2d_4x4_m500", "threeband_4x2_m2000"])
+def test_one_site_planner_flops_equal_oracle_count(name, order):
+    torch, lcc = need_gpu()
+    spec, mps = C.make(name)
+    m1 = M.canonical_at(mps, mps["center"])
+    ctx = lcc.Context(0)
+    ctx.set_plan(2048.0, 2048, 0, 0 if order == "left" else 2)
+    ham = ctx.create_hamiltonian(spec)
+    say(f"[flops] one site, {name}, {order} operator first: build")
+    env = ctx.build_environments_one_site(ham, m1, m1["center"])
+    f1, f2 = env.flops()
+    ref = OF.factorised_flops(m1, product_mpo(ham), order, one_site=True)
+    say(f"  planner {f1:.0f} + {f2:.0f}   oracle {ref['left']} + {ref['right']}")
+    assert (int(f1), int(f2)) == (ref["left"], ref["right"])
+    assert env.flops_per_apply == float(ref["total"])

@@ -82,3 +82,22 @@ def test_count_is_independent_of_vector_values():
         BS.MiddleBondEnvironments(spec, mps, mpo).apply(x, counter=cnt, order=order)
         fac = OF.factorised_flops(mps, mpo, order)
         assert (fac["left"], fac["right"]) == (cnt["left"], cnt["right"])
+
+
+@pytest.mark.parametrize("name", ["abinitio_k6_m12", "hubbard_4x2_m16_offcentre", "chain8_complete"])
+def test_one_site_counts_equal_the_work_of_the_contraction(name):
+    # the one-site problem (right enlarged operator = R): the factorised contraction equals the
+    # dense one-site H_eff of O1, and its counted work equals the integer count, in both orders
+    spec, mps = CASES[name]()
+    m1 = M.canonical_at(mps, mps["center"])
+    mpo = OM.build_mpo(spec)
+    keys = [(a, s, 0, b) for a, s, b in M.one_site_blocks(m1)]
+    yd = fock.effective_hamiltonian_one_site(spec, m1, keys) @ BS.flatten(M.random_one_site_vector(m1, 5), keys)
+    x = M.random_one_site_vector(m1, 5)
+    for order in ("left", "right"):
+        cnt = {}
+        y = BS.MiddleBondEnvironments(spec, m1, mpo, one_site=True).apply(x, counter=cnt, order=order)
+        assert np.linalg.norm(BS.flatten(y, keys) - yd) <= 1e-13 * np.linalg.norm(yd)
+        fac = OF.factorised_flops(m1, mpo, order, one_site=True)
+        assert (fac["left"], fac["right"]) == (cnt["left"], cnt["right"])
+        assert fac["left"] > 0 and fac["right"] > 0
