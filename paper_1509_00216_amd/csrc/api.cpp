@@ -93,6 +93,11 @@ void lcc_context_destroy(lcc_context ctx) {
     if (ctx->c.ev_fork) (void)hipEventDestroy(ctx->c.ev_fork);
     for (hipEvent_t e : ctx->c.ev_status)
       if (e) (void)hipEventDestroy(e);
+    if (ctx->c.ev_gate) (void)hipEventDestroy(ctx->c.ev_gate);
+    if (ctx->c.graph_stream) {
+      (void)hipStreamSynchronize(ctx->c.graph_stream);
+      (void)hipStreamDestroy(ctx->c.graph_stream);
+    }
     if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
   }
   delete ctx;

@@ -674,6 +674,7 @@ void build_ket_tensor(Env& E, const DeviceMps& t1, const DeviceMps& t2, hipStrea
 // the intermediate layout, the phase-1 and phase-2 grouped GEMMs, the split-K reduction and
 // the workspaces.  Replaces any previous plan.
 void plan_env(Env& E, const PlanParams& pp) {
+  ++E.plan_epoch;
   Env* env = &E;
   Context* ctx = E.ctx;
   hipStream_t st = ctx->stream;

@@ -6,7 +6,8 @@
 //
 // Inside an iteration nothing returns to the host.  The scalars live in a CgScalars record in
 // device memory, and each vector update is fused with the dot product after it and the scalar
-// step that uses it (cg.hip): an iteration is the operator product plus three small launches.
+// step that uses it (cg.hip): an iteration is the operator product plus three small launches,
+// and the low-precision iteration is replayed from a captured graph.
 // The last of them writes the status words to mapped host memory; after queueing iteration
 // i the host waits for the status of iteration i-1, so the device has the next iteration
 // queued (near the end of the recurrence it waits for iteration i itself).  The device halts the recurrence itself (converged, refresh due, error),
@@ -16,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <string>
 
 #include "state.h"
@@ -71,11 +73,6 @@ struct Ops {
     apply_heff(env, LCC_FP64, p, Ap, &S->run);
     ++applies64;
     check_hip(launch_cg_shift<double>(n, e0, p, Ap, v64, S, partial(), st), "shift, p^T A p");
-  }
-  void Ap32(int prec, const float* p, float* Ap) {
-    apply_heff(env, prec, p, Ap, &S->run);
-    ++applies_low;
-    check_hip(launch_cg_shift<float>(n, e0, p, Ap, v32, S, partial(), st), "shift, p^T A p");
   }
 };
 
@@ -299,19 +296,74 @@ lcc_status solve_local(Env& env, const lcc_solve_opts& o, const double* b, doubl
       double rr = ops.dot32(r32, r32);
       double rho = jacobi ? ops.dot32(r32, z32) : rr;
       check_hip(launch_cg_set(S, rho, rr, std::sqrt(rr), sc, tol * bn, inner_tol, st), "cg set");
+      // One low-precision iteration (operator product, update, direction), posting its status to
+      // slot k.  It reads and writes only the environment's own buffers and CG record, so it is
+      // captured as a graph once per slot and replayed, in this and later solves, until
+      // something it baked in changes.
+      // recorded on the graph stream gs: the context stream may be the legacy default stream,
+      // which cannot be captured; launches inside go to ctx->stream, pointed at gs meanwhile
+      if (!ctx->graph_stream) check_hip(hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking), "stream");
+      if (!ctx->ev_gate) check_hip(hipEventCreateWithFlags(&ctx->ev_gate, hipEventDisableTiming), "event");
+      hipStream_t gs = ctx->graph_stream;
+      poll.st = gs;  // status events, record copies and waits follow the iterations onto gs
+      auto iteration = [&](int k) {
+        apply_heff(env, prec, p32, Ap32, &S->run);
+        check_hip(launch_cg_shift<float>(n, e0, p32, Ap32, v32, S, ops.partial(), gs), "shift, p^T A p");
+        check_hip(launch_cg_update<float>(n, p32, d32, Ap32, r32, S, ops.partial(), true, jacobi, gs),
+                  "d, r update");
+        if (jacobi) {  // z = Q M^-1 r, rho_new = r^T z
+          check_hip(launch_mul_f32(n, env.minv32.as<float>(), r32, z32, gs), "precondition");
+          if (v32) {
+            check_hip(launch_dot_f32(v32, z32, n, ops.partial(), &S->c, gs), "dot");
+            check_hip(launch_cg_deflate<float>(n, &S->c, v32, z32, gs), "project");
+          }
+          check_hip(launch_dot_f32(r32, z32, n, ops.partial(), &S->rho_new, gs), "dot");
+          check_hip(launch_cg_beta(S, gs), "beta");
+        }
+        check_hip(launch_cg_direction<float>(n, z32, p32, S, reinterpret_cast<CgStatus*>(ctx->host_scalar_dev + 4) + k,
+                                             gs),
+                  "p update");
+      };
+      CgGraph& G = env.cg_graph;
+      uint64_t e0_bits;
+      std::memcpy(&e0_bits, &e0, sizeof e0_bits);  // e0 is an argument of the shift launch
+      const std::vector<uintptr_t> key = {
+          (uintptr_t)e0_bits, (uintptr_t)n, (uintptr_t)prec, (uintptr_t)jacobi, (uintptr_t)env.plan_epoch, (uintptr_t)ctx->overlap, (uintptr_t)gs,
+          (uintptr_t)p32, (uintptr_t)Ap32, (uintptr_t)d32, (uintptr_t)r32, (uintptr_t)z32, (uintptr_t)v32,
+          (uintptr_t)env.minv32.p, (uintptr_t)env.env32.p, (uintptr_t)env.merged32.p, (uintptr_t)env.tbuf.p,
+          (uintptr_t)env.work.p, (uintptr_t)S, (uintptr_t)ctx->host_scalar_dev, (uintptr_t)ops.partial()};
+      if (G.key != key) {
+        G.release();
+        for (int k = 0; k < 2; ++k) {
+          check_hip(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal), "begin capture");
+          hipGraph_t graph = nullptr;
+          ctx->stream = gs;
+          try {
+            iteration(k);
+          } catch (...) {
+            ctx->stream = st;
+            (void)hipStreamEndCapture(gs, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            throw;
+          }
+          ctx->stream = st;
+          check_hip(hipStreamEndCapture(gs, &graph), "end capture");
+          const hipError_t e = hipGraphInstantiate(&G.exec[k], graph, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(graph);
+          check_hip(e, "instantiate");
+        }
+        G.key = key;
+      }
       while (true) {
         // low-precision iterations, until the device halts the recurrence (refresh due,
         // converged, error) or max_iter iterations have run
+        // the iterations run on gs, after the work queued on the context stream
+        check_hip(hipEventRecord(ctx->ev_gate, st), "gate");
+        check_hip(hipStreamWaitEvent(gs, ctx->ev_gate, 0), "gate wait");
         for (; total_it < max_iter; ++total_it) {
-          ops.Ap32(prec, p32, Ap32);
-          check_hip(launch_cg_update<float>(n, p32, d32, Ap32, r32, S, ops.partial(), true, jacobi, st),
-                    "d, r update");
-          if (jacobi) {
-            precondition32();
-            check_hip(launch_dot_f32(r32, z32, n, ops.partial(), &S->rho_new, st), "dot");
-            check_hip(launch_cg_beta(S, st), "beta");
-          }
-          check_hip(launch_cg_direction<float>(n, z32, p32, S, poll.slot_dev(), st), "p update");
+          check_hip(hipGraphLaunch(G.exec[poll.posted & 1], gs), "iteration");
+          ++ops.applies_low;
           poll.posted_one();
           if (poll.halted()) break;
         }

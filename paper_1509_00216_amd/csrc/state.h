@@ -131,8 +131,11 @@ struct Context {
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> ev_join;
   hipEvent_t ev_fork = nullptr;
-  // the single solve's status copies, one iteration behind (see solver.cpp)
+  // the single solve's status copies, one iteration behind (see solver.cpp), and the stream its
+  // captured iterations are recorded and replayed on (a capture needs a stream of its own)
   hipEvent_t ev_status[2] = {nullptr, nullptr};
+  hipStream_t graph_stream = nullptr;
+  hipEvent_t ev_gate = nullptr;
 };
 
 struct Bond {
@@ -235,6 +238,25 @@ struct PlanInputs {
   std::vector<QN> dq_mid;
 };
 
+// The single solve's low-precision iteration captured as a graph, once per status slot, with
+// the key of everything the capture baked in (precision, options, buffers, plan).
+struct CgGraph {
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<uintptr_t> key;
+  CgGraph() = default;
+  CgGraph(const CgGraph&) = delete;
+  CgGraph& operator=(const CgGraph&) = delete;
+  void release() {
+    for (hipGraphExec_t& e : exec)
+      if (e) {
+        (void)hipGraphExecDestroy(e);
+        e = nullptr;
+      }
+    key.clear();
+  }
+  ~CgGraph() { release(); }
+};
+
 struct Env {
   Context* ctx = nullptr;
   int site = 0, K = 0;
@@ -258,12 +280,14 @@ struct Env {
   DevBuf env64, env32, merged64, merged32, tbuf, work;
   int64_t env_elems = 0, merged_elems = 0, t_elems = 0, work_elems = 0;
   Plan plan;
+  int64_t plan_epoch = 0;  // incremented by every (re)plan
   PlanParams params;
   PlanInputs in;
   // CG workspace
   DevBuf w64[6], w32[6];
   DevBuf flag;
   DevBuf cg;  // CgScalars of the single solve
+  CgGraph cg_graph;
   bool have32 = false;
   // diagonal of H_eff (FP64, built on first use) and the Jacobi preconditioner 1 / (diag - e0)
   DevBuf diag64, minv64, minv32;

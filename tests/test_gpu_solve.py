@@ -115,6 +115,37 @@ def test_nan_input_is_reported(chain):
     assert e.value.code == -4
 
 
+def test_mixed_solve_graph_replays(chain):
+    """The low-precision CG iteration is replayed from a graph kept with the environment: a second
+    identical solve (replays of the first solve's graph, with the refreshes' eager work and
+    synchronisations between them) repeats the first bit for bit; a different shift, another
+    projector and the other low precision each need a new capture, and each such solve matches
+    the plain FP64 solve of its own system (which runs no graph)."""
+    torch, lcc = need_gpu()
+    env = chain["env"]
+    b = to_dev(torch, chain["b"], torch.float64)
+    v = to_dev(torch, chain["v"], torch.float64)
+    runs = []
+    for _ in range(2):
+        x = torch.zeros_like(b)
+        info = env.solve_local_lcc(b, chain["e0"], x, v=v, precision="fp32", tol=1e-10, inner_tol=1e-2)
+        runs.append((x.cpu().numpy(), info))
+    assert runs[0][1]["status"] == "LCC_OK" and runs[0][1]["iterations"] > 4
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1]["hylleraas"] == runs[1][1]["hylleraas"]
+    assert abs(runs[0][1]["hylleraas"] - chain["jstar"]) <= 1e-8
+    for e0, vv, prec in ((chain["e0"] - 0.3, v, "fp32"), (chain["e0"] - 0.3, None, "fp32"),
+                         (chain["e0"] - 0.3, None, "bf16x3"), (chain["e0"] - 0.7, None, "fp32")):
+        x = torch.zeros_like(b)
+        info = env.solve_local_lcc(b, e0, x, v=vv, precision=prec, tol=1e-10, inner_tol=1e-2)
+        x64 = torch.zeros_like(b)
+        ref = env.solve_local_lcc(b, e0, x64, v=vv, precision="fp64", tol=1e-10)
+        say(f"[solve] graph replay e0 {e0:.4f} v={vv is not None} {prec}: J {info['hylleraas']:.14f} "
+            f"fp64 {ref['hylleraas']:.14f}, {info['iterations']} it")
+        assert info["status"] == "LCC_OK"
+        assert abs(info["hylleraas"] - ref["hylleraas"]) <= 1e-10 * abs(ref["hylleraas"])
+
+
 def test_max_iter_returns_not_converged(chain):
     torch, lcc = need_gpu()
     env = chain["env"]
