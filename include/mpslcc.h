@@ -336,8 +336,12 @@ lcc_status lcc_lowest_eigenpair(lcc_env env, int32_t steps, int32_t max_restarts
  * dropped by inner_tol since the last refresh, the accumulated correction is added to the
  * FP64 solution and the true residual r = Q b - A x is recomputed with the FP64 operator
  * (FP64 iterative refinement that keeps the search direction).  Dot products, scalars, the
- * refreshed residuals and the energy are FP64.
- * Synchronous.
+ * refreshed residuals and the energy are FP64.  The recurrence's scalars stay in device memory
+ * (no host round trip inside an iteration); the low-precision iteration is captured once as a
+ * graph on a stream the context creates for it and kept with the environment (recaptured when
+ * e0, the precision, v, the preconditioner or the plan change).
+ * Synchronous: the call returns after its device work, on the context stream and the graph
+ * stream, has finished.  One environment serves one solve at a time.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
   lcc_precision precision;
