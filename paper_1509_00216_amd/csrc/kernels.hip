@@ -481,6 +481,33 @@ __device__ __forceinline__ void bf16x3_chunk(const TA_& Ah, const TA_& Al, const
     }
 }
 
+// bf16x3_chunk with the sub-tiles outside the block (i >= ni, j >= nj) issuing no MFMA
+template <int TM, int TN, class TA_, class TB_>
+__device__ __forceinline__ void bf16x3_chunk_live(const TA_& Ah, const TA_& Al, const TB_& Bh, const TB_& Bl, int arow,
+                                                  int bcol, int ni, int nj, f4 (&acc)[TM][TN]) {
+  const int lane = threadIdx.x & 63;
+  bf8 ah[TM], al[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    ah[i] = *reinterpret_cast<const bf8*>(&Ah[arow + i * 16][8 * (lane >> 4)]);
+    al[i] = *reinterpret_cast<const bf8*>(&Al[arow + i * 16][8 * (lane >> 4)]);
+  }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    if (j < nj) {
+      const bf8 bh = *reinterpret_cast<const bf8*>(&Bh[bcol + j * 16][8 * (lane >> 4)]);
+      const bf8 bl = *reinterpret_cast<const bf8*>(&Bl[bcol + j * 16][8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        if (i < ni) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+}
+
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_bf16x3_packed_kernel(const SlotRec* __restrict__ slots, const GemmGroup* __restrict__ groups,
@@ -695,67 +722,25 @@ __device__ __forceinline__ void terms_chunk(const TA_& As, const TB_& Bs, int ar
   }
 }
 
-// hi = bf16(v), lo = bf16(v - hi) of the eight k values of a lane's row
-template <class TS>
-__device__ __forceinline__ void split8(const TS& S, int k0, int col, bf8& hi, bf8& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const float v = S[k0 + e][col];
-    const __bf16 h = (__bf16)v;
-    hi[e] = h;
-    lo[e] = (__bf16)(v - (float)h);
-  }
-}
-
-// BF16x3 MFMAs of one staged 32-k chunk of FP32 operands (LDS tiles [k][m], [k][n]): lane l takes
-// the eight k values 8 (l/16) .. 8 (l/16) + 7 of its row and column (rows 8 apart between lane
-// groups: disjoint banks), splits them into bf16 hi + lo and accumulates hi*hi + hi*lo + lo*hi with
-// v_mfma_f32_16x16x32_bf16 (the lo*lo term is below the representation error of the split).
-template <int TM, int TN, class TA_, class TB_>
-__device__ __forceinline__ void terms_chunk_bf16x3(const TA_& As, const TB_& Bs, int arow, int bcol, int ni, int nj,
-                                                   f4 (&acc)[TM][TN]) {
-  const int lane = threadIdx.x & 63;
-  const int k0 = 8 * (lane >> 4);
-  // the operand with fewer sub-tiles is split once and held; the other is split one sub-tile
-  // at a time (fewer live registers)
-  if constexpr (TN <= TM) {
-    bf8 bh[TN], bl[TN];
-#pragma unroll
-    for (int j = 0; j < TN; ++j) split8(Bs, k0, bcol + j * 16, bh[j], bl[j]);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      if (i < ni) {
-        bf8 ah, al;
-        split8(As, k0, arow + i * 16, ah, al);
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          if (j < nj) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
-          }
-      }
-    }
-  } else {
-    bf8 ah[TM], al[TM];
-#pragma unroll
-    for (int i = 0; i < TM; ++i) split8(As, k0, arow + i * 16, ah[i], al[i]);
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      if (j < nj) {
-        bf8 bh, bl;
-        split8(Bs, k0, bcol + j * 16, bh, bl);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-          if (i < ni) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
-          }
-      }
-    }
-  }
-}
+// LDS of the term-walk kernel: FP64 / FP32 operands as [k][r] tiles (pitches in KPitch); the
+// BF16x3 kernel splits each operand once, as it is staged, into bf16 hi and lo tiles [r][k] whose
+// rows are 40 elements (80 bytes) apart, so that a lane reads its eight k values of a row with one
+// 16-byte access and eight consecutive rows fall on eight different 16-byte bank groups.
+template <int MODE, class T, int BM, int BN, int BK>
+struct TermsLds {
+  static constexpr int PA = MODE == 1 ? BM + 1 : KPitch<T>::of(BM);  // see KPitch
+  static constexpr int PB = MODE == 1 ? BN + 1 : KPitch<T>::of(BN);
+  T As[BK][PA];
+  T Bs[BK][PB];
+};
+template <class T, int BM, int BN, int BK>
+struct TermsLds<2, T, BM, BN, BK> {
+  static constexpr int KP = BK + 8;
+  __attribute__((aligned(16))) __bf16 Ah[BM][KP];
+  __attribute__((aligned(16))) __bf16 Al[BM][KP];
+  __attribute__((aligned(16))) __bf16 Bh[BN][KP];
+  __attribute__((aligned(16))) __bf16 Bl[BN][KP];
+};
 
 template <int MODE, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
@@ -771,10 +756,7 @@ __device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ ter
   constexpr int NT = 64 * WM * WN;
   typedef ALoader<T, TA, BM, BK, NT> LA;
   typedef BLoader<T, TB, BN, BK, NT> LB;
-  constexpr int PA = MODE == 1 ? BM + 1 : KPitch<T>::of(BM);  // see KPitch
-  constexpr int PB = MODE == 1 ? BN + 1 : KPitch<T>::of(BN);
-  __shared__ T As[BK][PA];
-  __shared__ T Bs[BK][PB];
+  __shared__ TermsLds<MODE, T, BM, BN, BK> lds;
 
   __shared__ BaseTable<T> bt;
   const int tid = threadIdx.x;
@@ -816,17 +798,38 @@ __device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ ter
     const T alpha = (T)term.alpha;
     const int kmax = min(BK, term.k - k0);
     __syncthreads();
+    if constexpr (MODE == 2) {
 #pragma unroll
-    for (int i = 0; i < LA::N; ++i) {
-      int mm, kk;
-      LA::coords(i, mm, kk);
-      As[kk][mm] = alpha * ra[i];
-    }
+      for (int i = 0; i < LA::N; ++i) {
+        int mm, kk;
+        LA::coords(i, mm, kk);
+        const float x = alpha * ra[i];
+        const __bf16 h = (__bf16)x;
+        lds.Ah[mm][kk] = h;
+        lds.Al[mm][kk] = (__bf16)(x - (float)h);
+      }
 #pragma unroll
-    for (int i = 0; i < LB::N; ++i) {
-      int nn, kk;
-      LB::coords(i, nn, kk);
-      Bs[kk][nn] = rb[i];
+      for (int i = 0; i < LB::N; ++i) {
+        int nn, kk;
+        LB::coords(i, nn, kk);
+        const float x = rb[i];
+        const __bf16 h = (__bf16)x;
+        lds.Bh[nn][kk] = h;
+        lds.Bl[nn][kk] = (__bf16)(x - (float)h);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < LA::N; ++i) {
+        int mm, kk;
+        LA::coords(i, mm, kk);
+        lds.As[kk][mm] = alpha * ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < LB::N; ++i) {
+        int nn, kk;
+        LB::coords(i, nn, kk);
+        lds.Bs[kk][nn] = rb[i];
+      }
     }
     __syncthreads();
     k0 += BK;
@@ -840,9 +843,9 @@ __device__ __forceinline__ void gemm_terms_body(const GemmTerm* __restrict__ ter
       LB::load(rb, bt.get(term.b_base) + term.b_off, term.ldb, col0, g.n, k0, term.k);
     }
     if constexpr (MODE == 2)
-      terms_chunk_bf16x3<TM, TN>(As, Bs, arow, bcol, ni, nj, acc);
+      bf16x3_chunk_live<TM, TN>(lds.Ah, lds.Al, lds.Bh, lds.Bl, arow, bcol, ni, nj, acc);
     else
-      terms_chunk<MODE, BK, TM, TN>(As, Bs, arow, bcol, kmax, ni, nj, acc);
+      terms_chunk<MODE, BK, TM, TN>(lds.As, lds.Bs, arow, bcol, kmax, ni, nj, acc);
   }
 
   const gmut<T> C = global_mut(bt.get(g.c_base) + g.c_off);
@@ -869,8 +872,9 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
   gemm_terms_body<MODE, TA, TB, BM, BN, WM, WN>(terms, groups, tiles, n_tiles, bases, table, active);
 }
 
-// The BF16x3 term walk: the split of each operand read into hi and lo needs registers; the bound
-// of four waves per SIMD keeps the kernel at that occupancy.
+// The BF16x3 term walk: each operand element is split into bf16 hi and lo once, as it is staged
+// (TermsLds), and the chunk runs bf16x3_chunk_live; the bound of four waves per SIMD keeps the
+// register budget of that occupancy.
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(4)))
 gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
