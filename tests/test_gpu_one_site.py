@@ -129,3 +129,48 @@ def test_solve_and_eigenpair_vs_dense():
     say(f"[one-site] eigenpair {info['theta']:.14f} (dense {w[0]:.14f})")
     assert info["status"] == "LCC_OK"
     assert abs(info["theta"] - w[0]) <= 1e-10
+
+
+def test_tuner_and_batches_take_one_site_environments():
+    """A one-site environment goes through every entry point that takes an environment: the
+    autotuner (tuned plan = oracle), a batch with a two-site member and the one-shot batched solve
+    (energies = the dense solution of each system)."""
+    torch, lcc = need_gpu()
+    spec, mps = SYSTEMS["hubbard_4x2_m16"]()
+    site = mps["center"]
+    m1 = M.canonical_at(mps, site)
+    keys = _keys(m1)
+    H1 = fock.effective_hamiltonian_one_site(spec, m1, keys)
+    ctx = lcc.Context(0)
+    ham = ctx.create_hamiltonian(spec)
+    env = ctx.build_environments_one_site(ham, m1, site)
+    info = env.autotune("fp32", reps=2)
+    say(f"[one-site] autotune {info}")
+    x = M.random_one_site_vector(m1, 6)
+    yref = env.pack(BS.unflatten(H1 @ BS.flatten(x, keys), x, keys))
+    assert rel(_apply(torch, env, env.pack(x), "fp64"), yref) <= 1e-12
+    assert rel(_apply(torch, env, env.pack(x), "fp32"), yref) <= 1e-5
+    # a batch of the one-site problem and the two-site problem of the same MPS
+    blocks2 = M.two_site_blocks(mps)
+    H2 = fock.effective_hamiltonian(spec, mps, blocks2)
+    env2 = ctx.build_environments(ham, mps)
+    probs = []
+    for e, Hm, vec in ((env, H1, M.random_one_site_vector(m1, 7)), (env2, H2, M.random_two_site_vector(mps, 8))):
+        k = keys if e is env else blocks2
+        e0 = np.linalg.eigvalsh(Hm)[0] - 0.5
+        bflat = BS.flatten(vec, k)
+        jstar = -float(bflat @ np.linalg.solve(Hm - e0 * np.eye(Hm.shape[0]), bflat))
+        probs.append((e, e0, to_dev(torch, e.pack(vec), torch.float64), jstar))
+    for runner in ("batch", "one-shot"):
+        xs = [torch.zeros_like(b) for _, _, b, _ in probs]
+        args = ([b for _, _, b, _ in probs], [e0 for _, e0, _, _ in probs], xs)
+        if runner == "batch":
+            status, infos = lcc.Batch(ctx, [e for e, _, _, _ in probs]).solve(*args, precision="fp32", tol=1e-10,
+                                                                               max_iter=2000)
+        else:
+            status, infos = lcc.solve_local_lcc_batched([e for e, _, _, _ in probs], *args, precision="fp32",
+                                                        tol=1e-10, max_iter=2000)
+        say(f"[one-site] {runner}: {[i['hylleraas'] for i in infos]} vs {[j for _, _, _, j in probs]}")
+        assert status == "LCC_OK"
+        for (_, _, _, jstar), inf in zip(probs, infos):
+            assert abs(inf["hylleraas"] - jstar) <= 1e-8 * abs(jstar)
