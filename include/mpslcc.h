@@ -189,6 +189,15 @@ void lcc_env_destroy(lcc_env env);
  * environment (LCC_ERR_STATE).  Synchronous.  The environment keeps its own copies. */
 lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* bra,
                                              const lcc_mps_desc* ket, int32_t site, lcc_env* out);
+/* The same transition operator with the bra's one site tensor at `site` removed (the derivative
+ * of <Psi|H|Phi> with respect to that tensor, local-derivative figure): the right environment
+ * covers the sites > site, vectors are one-site tensors as for
+ * lcc_build_environments_one_site, and lcc_env_ket_tensor gives the ket's own site tensor at
+ * `site`.  0 <= site < K; the bra must be left-canonical left of `site` and right-canonical right
+ * of it (checked to 1e-10, LCC_ERR_ARG otherwise).  Synchronous.  The environment keeps its own
+ * copies. */
+lcc_status lcc_build_transition_environments_one_site(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* bra,
+                                                      const lcc_mps_desc* ket, int32_t site, lcc_env* out);
 
 /* Layout of two-site vectors x, y, b (the unknown tensor of the local problem).
  * Blocks are (left sector a of bond site, s1, s2, right sector b of bond site+2) with

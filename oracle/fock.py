@@ -296,16 +296,17 @@ def mps_state(mps: dict, basis: np.ndarray) -> np.ndarray:
     return full[config_index(basis, K)]
 
 
-def first_order_vectors(spec: dict, bra: dict, ket: dict, blocks: list):
+def first_order_vectors(spec: dict, bra: dict, ket: dict, blocks: list, one_site: bool = False):
     """Local vectors of the first-order equation at the bra's two-site block (Theory section,
     first-order equation; Implementation section, its local form): with P the bra's two-site
     isometry and Phi0 the ket state,
         u = P^T H Phi0,   v = P^T Phi0,   e1 = <Phi0|H|Phi0> / <Phi0|Phi0>,
     so that P^T Q H Phi0 = u - e1 v for Q = 1 - |Phi0><Phi0| / <Phi0|Phi0>.  Columns of P in
-    `blocks` order, row-major inside a block."""
+    `blocks` order, row-major inside a block; one_site: P is the one-site isometry of the bra's
+    center tensor."""
     basis = sector_basis(spec["n_orb"], spec["n_elec"], spec["two_sz"])
     H = hamiltonian_matrix(spec, basis)
     phi0 = mps_state(ket, basis)
-    P = two_site_isometry(bra, basis, blocks)
+    P = one_site_isometry(bra, basis, blocks) if one_site else two_site_isometry(bra, basis, blocks)
     hphi = H @ phi0
     return P.T @ hphi, P.T @ phi0, float(phi0 @ hphi) / float(phi0 @ phi0)

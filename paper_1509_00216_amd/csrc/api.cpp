@@ -301,6 +301,20 @@ lcc_status lcc_build_transition_environments(lcc_context ctx, lcc_hamiltonian ha
   });
 }
 
+lcc_status lcc_build_transition_environments_one_site(lcc_context ctx, lcc_hamiltonian ham, const lcc_mps_desc* bra,
+                                                      const lcc_mps_desc* ket, int32_t site, lcc_env* out) {
+  if (!out) return fail(ctx, LCC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  return guarded(ctx, [&]() -> lcc_status {
+    require_device(ctx);
+    if (!ham || !bra || !ket) throw Error{LCC_ERR_ARG, "NULL argument"};
+    std::unique_ptr<lcc_env_s> e(new lcc_env_s());
+    e->e = build_transition_env(&ctx->c, ham->h, *bra, *ket, site, true);
+    *out = e.release();
+    return LCC_OK;
+  });
+}
+
 // The destroy calls do not touch the context: objects may be destroyed in any order (a garbage
 // collector may finalise a context before the environments made on it).  Device memory is
 // released with hipFree, which waits for the device work in flight.

@@ -613,13 +613,18 @@ Mpo identity_mpo(int K) {
 // the bra's.  The bra must be canonical around the block (its two-site space is the one of the
 // local problem); the ket may be in any gauge.
 Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& bra_d, const lcc_mps_desc& ket_d,
-                          int site) {
+                          int site, bool one_site) {
   hipStream_t st = ctx->stream;
   const Mpo& mpo = ham.mpo;
   const int K = mpo.K;
   if (bra_d.n_sites != K || ket_d.n_sites != K)
     throw Error{LCC_ERR_ARG, "MPS length differs from the Hamiltonian's orbital count"};
-  if (site < 0 || site + 1 >= K) throw Error{LCC_ERR_ARG, "two-site block must satisfy 0 <= site < K-1"};
+  if (one_site) {
+    if (site < 0 || site >= K) throw Error{LCC_ERR_ARG, "one-site problem must satisfy 0 <= site < K"};
+  } else if (site < 0 || site + 1 >= K) {
+    throw Error{LCC_ERR_ARG, "two-site block must satisfy 0 <= site < K-1"};
+  }
+  const int rb = one_site ? site + 1 : site + 2;  // bond of the right environment
   DeviceMps bra, ket;
   load_mps(bra_d, ham.desc.N, ham.desc.two_sz, st, bra);
   load_mps(ket_d, ham.desc.N, ham.desc.two_sz, st, ket);
@@ -629,17 +634,39 @@ Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_de
     for (int j = 0; j < site; ++j) L = left_step(L, bra, j, id, st);
     if (site > 0) check_identity(L, 0, bra.bonds[site], st, "left");
     Environment R = unit_env(st);
-    for (int j = K - 1; j >= site + 2; --j) R = right_step(R, bra, j, id, st);
-    if (site + 2 < K) check_identity(R, 0, bra.bonds[site + 2], st, "right");
+    for (int j = K - 1; j >= rb; --j) R = right_step(R, bra, j, id, st);
+    if (rb < K) check_identity(R, 0, bra.bonds[rb], st, "right");
   }
   Environment L = unit_env(st);
   for (int j = 0; j < site; ++j) L = left_step(L, bra, ket, j, mpo, st);
   Environment R = unit_env(st);
-  for (int j = K - 1; j >= site + 2; --j) R = right_step(R, bra, ket, j, mpo, st);
-  std::unique_ptr<Env> env(make_env(ctx, mpo, site, bra.bonds[site], bra.bonds[site + 2], ket.bonds[site],
-                                    ket.bonds[site + 2], L, R, true));
-  build_ket_tensor(*env, ket, ket, st);
+  for (int j = K - 1; j >= rb; --j) R = right_step(R, bra, ket, j, mpo, st);
+  std::unique_ptr<Env> env(make_env(ctx, mpo, site, bra.bonds[site], bra.bonds[rb], ket.bonds[site], ket.bonds[rb],
+                                    L, R, true, one_site));
+  if (one_site)
+    build_ket_site_tensor(*env, ket, st);
+  else
+    build_ket_tensor(*env, ket, ket, st);
   return env.release();
+}
+
+// The ket's own one-site tensor at the site of a one-site transition operator (input layout):
+// its site tensor's blocks, copied into the (a, s, 0, b) blocks of the layout.
+void build_ket_site_tensor(Env& E, const DeviceMps& ket, hipStream_t st) {
+  std::map<std::pair<int, int>, const SiteBlock*> A;
+  for (const SiteBlock& b : ket.sites[E.site]) A[{b.l, b.s}] = &b;
+  E.x0.alloc(sizeof(double) * std::max<int64_t>(E.n_in, 1));
+  check_hip(launch_fill_f64(E.x0.as<double>(), E.n_in, 0.0, st), "zero ket tensor");
+  for (const lcc_block_entry& blk : E.layout_in) {
+    auto it = A.find({blk.left, blk.s1});
+    if (it == A.end() || it->second->r != blk.right) continue;
+    const SiteBlock& sb = *it->second;
+    check_hip(hipMemcpy2DAsync(E.x0.as<double>() + blk.offset, sizeof(double) * blk.ld,
+                               ket.data.as<double>() + sb.off, sizeof(double) * sb.cols, sizeof(double) * sb.cols,
+                               sb.rows, hipMemcpyDeviceToDevice, st),
+              "ket site tensor");
+  }
+  check_hip(hipStreamSynchronize(st), "ket tensor");
 }
 
 // The ket's own two-site tensor at the block of a transition operator (input layout):

@@ -337,9 +337,11 @@ Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bond_l, const 
 Env* make_env(Context* ctx, const Mpo& mpo, int site, const Bond& bra_l, const Bond& bra_r, const Bond& ket_l,
               const Bond& ket_r, const Environment& L, const Environment& R, bool transition, bool one_site = false);
 Env* build_transition_env(Context* ctx, const Hamiltonian& ham, const lcc_mps_desc& bra, const lcc_mps_desc& ket,
-                          int site);
+                          int site, bool one_site = false);
 // x0 of a transition operator from the ket's site tensors (site from t1, site + 1 from t2)
 void build_ket_tensor(Env& env, const DeviceMps& t1, const DeviceMps& t2, hipStream_t st);
+// x0 of a one-site transition operator: the ket's site tensor
+void build_ket_site_tensor(Env& env, const DeviceMps& ket, hipStream_t st);
 Mpo identity_mpo(int K);
 
 // env.cpp

@@ -23,7 +23,8 @@ STATUS = {0: "LCC_OK", 1: "LCC_NOT_CONVERGED", -1: "LCC_ERR_ARG", -2: "LCC_ERR_Q
 EXPORTS = ["lcc_context_create", "lcc_context_destroy", "lcc_last_error", "lcc_context_synchronize",
            "lcc_create_hamiltonian", "lcc_hamiltonian_destroy", "lcc_hamiltonian_bond_dims",
            "lcc_hamiltonian_channels", "lcc_hamiltonian_site_mpo", "lcc_build_environments",
-           "lcc_build_environments_one_site", "lcc_env_destroy", "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
+           "lcc_build_environments_one_site", "lcc_build_transition_environments_one_site", "lcc_env_destroy",
+           "lcc_env_layout", "lcc_env_flops", "lcc_apply_heff", "lcc_solve_local_lcc",
            "lcc_env_profile_apply", "lcc_lowest_eigenvalue", "lcc_env_profile_launches", "lcc_batch_create",
            "lcc_batch_destroy", "lcc_batch_solve", "lcc_solve_local_lcc_batched",
            "lcc_context_set_intermediate_limit", "lcc_sweep_create", "lcc_sweep_destroy", "lcc_sweep_env",
@@ -131,6 +132,8 @@ def library() -> C.CDLL:
                                                  C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
         "lcc_build_environments": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
         "lcc_build_environments_one_site": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.c_int32, C.POINTER(P)]),
+        "lcc_build_transition_environments_one_site": (C.c_int32, [P, P, C.POINTER(MpsDesc), C.POINTER(MpsDesc),
+                                                                   C.c_int32, C.POINTER(P)]),
         "lcc_env_destroy": (None, [P]),
         "lcc_env_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
         "lcc_env_input_layout": (C.c_int32, [P, C.POINTER(LayoutInfo), C.POINTER(BlockEntry)]),
@@ -544,6 +547,21 @@ def build_transition_environments(ctx: Context, ham: Hamiltonian, bra: dict, ket
     out = C.c_void_p()
     _check(library().lcc_build_transition_environments(ctx.handle, ham.handle, C.byref(bd), C.byref(kd), site,
                                                        C.byref(out)), ctx.handle)
+    del keep_b, keep_k
+    return Env(out, ctx)
+
+
+def build_transition_environments_one_site(ctx: Context, ham: Hamiltonian, bra: dict, ket: dict,
+                                           site: int | None = None) -> Env:
+    """lcc_build_transition_environments_one_site: <bra| H |ket> with the bra's site tensor at
+    `site` (default bra['center']) cut out; vector blocks keyed (a, s, 0, b)."""
+    if site is None:
+        site = bra["center"]
+    bd, keep_b = _mps_desc(bra)
+    kd, keep_k = _mps_desc(ket)
+    out = C.c_void_p()
+    _check(library().lcc_build_transition_environments_one_site(ctx.handle, ham.handle, C.byref(bd), C.byref(kd), site,
+                                                                C.byref(out)), ctx.handle)
     del keep_b, keep_k
     return Env(out, ctx)
 

@@ -174,3 +174,43 @@ def test_tuner_and_batches_take_one_site_environments():
         assert status == "LCC_OK"
         for (_, _, _, jstar), inf in zip(probs, infos):
             assert abs(inf["hylleraas"] - jstar) <= 1e-8 * abs(jstar)
+
+
+def _identity_spec(spec):
+    n = spec["n_orb"]
+    return {"name": "identity", "n_orb": n, "h": np.zeros((n, n)), "eri": None, "u": None, "e_const": 1.0,
+            "n_elec": spec["n_elec"], "two_sz": spec["two_sz"]}
+
+
+@pytest.mark.parametrize("site", [0, 2, 5])
+def test_one_site_transition_rhs_vs_fock(site):
+    """One-site transition environments (lcc_build_transition_environments_one_site): applied to
+    the ket's own site tensor they give u = P1^T H Phi0 and, with H = 1, v = P1^T Phi0, where P1 is
+    the bra's one-site isometry (the first-order right-hand side of the one-site problem); the
+    ket has other bond dimensions and its own gauge.  Bars: 1e-12 relative (FP64), 1e-5 (FP32)."""
+    torch, lcc = need_gpu()
+    spec = H.random_ab_initio(6, 6, seed=21)
+    bra = M.canonical_at(M.random_mps(6, 6, 0, 10, seed=22, center=2), site)
+    ket = M.random_mps(6, 6, 0, 6, seed=23, center=1)
+    keys = _keys(bra)
+    u_ref, v_ref, _ = fock.first_order_vectors(spec, bra, ket, keys, one_site=True)
+    ctx = lcc.Context(0)
+    tenv = lcc.build_transition_environments_one_site(ctx, ctx.create_hamiltonian(spec), bra, ket, site)
+    ienv = lcc.build_transition_environments_one_site(ctx, ctx.create_hamiltonian(_identity_spec(spec)), bra, ket,
+                                                      site)
+    assert tenv.transition
+    x0 = torch.zeros(tenv.n_in, dtype=torch.float64, device="cuda:0")
+    tenv.ket_tensor(x0)
+    u = torch.empty(tenv.n, dtype=torch.float64, device="cuda:0")
+    v = torch.empty(tenv.n, dtype=torch.float64, device="cuda:0")
+    tenv.apply_heff(x0, u, "fp64")
+    ienv.apply_heff(x0, v, "fp64")
+    u32 = torch.empty(tenv.n, dtype=torch.float32, device="cuda:0")
+    tenv.apply_heff(x0.float(), u32, "fp32")
+    torch.cuda.synchronize()
+    tmpl = {k: np.zeros((bra["bonds"][site][k[0]][2], bra["bonds"][site + 1][k[3]][2])) for k in keys}
+    pk = lambda flat: tenv.pack(BS.unflatten(flat, tmpl, keys))
+    eu, ev = rel(u.cpu().numpy(), pk(u_ref)), rel(v.cpu().numpy(), pk(v_ref))
+    say(f"[one-site] transition at site {site}: u rel {eu:.2e}, v rel {ev:.2e}, |v| {np.linalg.norm(v_ref):.4f}")
+    assert eu <= 1e-12 and ev <= 1e-12
+    assert rel(u32.double().cpu().numpy(), pk(u_ref)) <= 1e-5
