@@ -17,6 +17,7 @@ from gpu_common import need_gpu, rel, say, to_dev
 from oracle import blocksparse as BS
 from oracle import fock
 from oracle import mpo as OM
+from oracle import solve as OS
 from workloads import configs as C
 from workloads import hamiltonians as H
 from workloads import mps as M
@@ -214,3 +215,45 @@ def test_one_site_transition_rhs_vs_fock(site):
     say(f"[one-site] transition at site {site}: u rel {eu:.2e}, v rel {ev:.2e}, |v| {np.linalg.norm(v_ref):.4f}")
     assert eu <= 1e-12 and ev <= 1e-12
     assert rel(u32.double().cpu().numpy(), pk(u_ref)) <= 1e-5
+
+
+def test_one_site_first_order_local_solve():
+    """The first-order local problem of one site tensor end to end: b = -(u - e1 v) and v from the
+    one-site transition environments, then Q(H1 - E0)Q x = Q b with Q = 1 - v v^T / |v|^2 on the
+    one-site environment, in FP64 and mixed precision, against the dense solution of the same
+    equation built from the oracle's u, v, e1 and one-site H_eff (J within 1e-9, x orthogonal to v)."""
+    torch, lcc = need_gpu()
+    spec = H.random_ab_initio(6, 6, seed=21)
+    site = 2
+    bra = M.canonical_at(M.random_mps(6, 6, 0, 10, seed=22, center=2), site)
+    ket = M.random_mps(6, 6, 0, 6, seed=23, center=1)
+    keys = _keys(bra)
+    u_ref, v_ref, e1 = fock.first_order_vectors(spec, bra, ket, keys, one_site=True)
+    H1 = fock.effective_hamiltonian_one_site(spec, bra, keys)
+    e0 = float(np.linalg.eigvalsh(H1)[0]) - 0.5
+    bref = -(u_ref - e1 * v_ref)
+    vh = v_ref / np.linalg.norm(v_ref)
+    xs = OS.dense_solution(H1, bref, e0, vh)
+    jstar = OS.hylleraas(OS.make_operator(lambda z: H1 @ z, e0, vh), xs, OS.project(vh, bref))
+    ctx = lcc.Context(0)
+    ham = ctx.create_hamiltonian(spec)
+    tenv = lcc.build_transition_environments_one_site(ctx, ham, bra, ket, site)
+    ienv = lcc.build_transition_environments_one_site(ctx, ctx.create_hamiltonian(_identity_spec(spec)), bra, ket,
+                                                      site)
+    x0 = torch.zeros(tenv.n_in, dtype=torch.float64, device="cuda:0")
+    tenv.ket_tensor(x0)
+    u = torch.empty(tenv.n, dtype=torch.float64, device="cuda:0")
+    v = torch.empty(tenv.n, dtype=torch.float64, device="cuda:0")
+    tenv.apply_heff(x0, u, "fp64")
+    ienv.apply_heff(x0, v, "fp64")
+    b = -(u - e1 * v)
+    vhat = v / v.norm()
+    env = ctx.build_environments_one_site(ham, bra, site)
+    for prec in ("fp64", "fp32"):
+        x = torch.zeros_like(b)
+        info = env.solve_local_lcc(b, e0, x, v=vhat, precision=prec, tol=1e-12, max_iter=2000, inner_tol=1e-4,
+                                   max_outer=100)
+        say(f"[one-site] first-order solve {prec}: J {info['hylleraas']:.15f} dense {jstar:.15f}")
+        assert info["status"] == "LCC_OK"
+        assert abs(info["hylleraas"] - jstar) <= 1e-9
+        assert abs(float(vhat @ x)) <= 1e-10 * float(x.norm())
