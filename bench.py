@@ -71,6 +71,8 @@ def kernel_name(precision: str, launch: dict) -> str:
              (64, 128): (2, 2), (32, 64): (2, 2), (64, 32): (2, 2), (128, 128): (4, 2)}[(bm, bn)]
     kind = "packed" if launch.get("packed") else "terms"
     if precision == "bf16x3":
+        if (bm, bn) == (128, 128):
+            waves = (2, 2)  # the BF16x3 launcher runs this tile as four waves of 64x64
         return f"gemm_bf16x3_{kind}_kernel<{ta}, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"
     mode = 0 if precision == "fp64" else 1
     return f"gemm_{kind}_kernel<{mode}, {ta}, {tb}, {bm}, {bn}, {waves[0]}, {waves[1]}>"

@@ -873,10 +873,17 @@ gemm_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restric
 }
 
 // The BF16x3 term walk: each operand element is split into bf16 hi and lo once, as it is staged
-// (TermsLds), and the chunk runs bf16x3_chunk_live; the bound of four waves per SIMD keeps the
-// register budget of that occupancy.
+// (TermsLds), and the chunk runs bf16x3_chunk_live.  Its chunks are bound by LDS reads (per 32 k,
+// a wave reads hi and lo of all its rows and columns for three MFMAs per 16x16 sub-tile), so the
+// 128x128 tile runs four waves of 64x64 (the launcher maps it), whose reads per MFMA are two
+// thirds of those of eight waves of 32x64, at three waves per SIMD (about 155 registers); the
+// other shapes keep four waves per SIMD.
+template <int BM, int BN, int WM, int WN>
+struct Bf16x3Waves {
+  static constexpr int value = (BM == 128 && BN == 128 && WM * WN == 4) ? 3 : 4;
+};
 template <bool TA, bool TB, int BM, int BN, int WM, int WN>
-__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(Bf16x3Waves<BM, BN, WM, WN>::value)))
 gemm_bf16x3_terms_kernel(const GemmTerm* __restrict__ terms, const GemmGroup* __restrict__ groups,
                          const GemmTile* __restrict__ tiles, int n_tiles, Bases<float> bases,
                          const Bases<float>* __restrict__ table, const int* __restrict__ active) {
@@ -922,11 +929,15 @@ template <int BM, int BN, int WM, int WN>
 static hipError_t launch_bf_shape(const GemmDesc& d, const Bases<float>& b, hipStream_t s, const Bases<float>* table,
                                   const int* active) {
   if (d.n_tiles <= 0) return hipSuccess;
-  if (!d.ta && !d.tb) fire_bf<false, false, BM, BN, WM, WN>(d, b, s, table, active);
-  else if (!d.ta && d.tb) fire_bf<false, true, BM, BN, WM, WN>(d, b, s, table, active);
-  else if (d.ta && !d.tb) fire_bf<true, false, BM, BN, WM, WN>(d, b, s, table, active);
-  else fire_bf<true, true, BM, BN, WM, WN>(d, b, s, table, active);
-  return hipGetLastError();
+  if constexpr (BM == 128 && BN == 128 && WM * WN != 4) {
+    return launch_bf_shape<128, 128, 2, 2>(d, b, s, table, active);  // four waves of 64x64 (see above)
+  } else {
+    if (!d.ta && !d.tb) fire_bf<false, false, BM, BN, WM, WN>(d, b, s, table, active);
+    else if (!d.ta && d.tb) fire_bf<false, true, BM, BN, WM, WN>(d, b, s, table, active);
+    else if (d.ta && !d.tb) fire_bf<true, false, BM, BN, WM, WN>(d, b, s, table, active);
+    else fire_bf<true, true, BM, BN, WM, WN>(d, b, s, table, active);
+    return hipGetLastError();
+  }
 }
 
 #define LCC_SHAPE_SWITCH(FN, ...)                                          \
