@@ -25,6 +25,11 @@ def test_kernel_name_follows_layouts_and_variant():
         "gemm_packed_kernel<1, true, false, 16, 64, 1, 4>"
     assert bench.kernel_name("bf16x3", _launch(tile=(64, 16))) == "gemm_bf16x3_terms_kernel<true, true, 64, 16, 4, 1>"
     assert bench.kernel_name("fp32", {"kind": "reduce"}) == "reduce_kernel<float>"
+    # 128x128 tiles: eight waves of 32x64 in FP32/FP64, four waves of 64x64 in BF16x3
+    assert bench.kernel_name("fp32", _launch(tile=(128, 128), a_kmajor=False)) == \
+        "gemm_terms_kernel<1, false, true, 128, 128, 4, 2>"
+    assert bench.kernel_name("bf16x3", _launch(tile=(128, 128), a_kmajor=False)) == \
+        "gemm_bf16x3_terms_kernel<false, true, 128, 128, 2, 2>"
 
 
 def test_traffic_lookup_is_per_launch_size_and_source_digest():
