@@ -501,8 +501,9 @@ def main():
     ap.add_argument("--tune-cache", default=SHIPPED_TUNE_CACHE)
     ap.add_argument("--tune-workloads", default="abinitio_k24_m1000,threeband_4x2_m2000,hubbard2d_4x4_m500")
     ap.add_argument("--no-tune", action="store_true", help="plan with the default planner parameters")
-    ap.add_argument("--inner-tol", type=float, default=1e-4,
-                    help="mixed precision: residual reduction between FP64 refreshes")
+    ap.add_argument("--inner-tol", type=float, default=1e-5,
+                    help="mixed precision: residual reduction between FP64 refreshes (1e-5: two refreshes "
+                         "to 1e-10 at K=24, M=1000; 1e-4 needs three, 3e-6 more FP32 iterations)")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--batch-intermediate-mib", type=int, default=1024)
     ap.add_argument("--no-extra", action="store_true",
