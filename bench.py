@@ -525,7 +525,7 @@ def main():
         print(json.dumps({"mode": "pmc-summary", "kernels": len(rec["kernels"]), "scale": rec["scale"]}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     if args.mode == "tune":

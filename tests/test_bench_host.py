@@ -44,3 +44,12 @@ def test_traffic_lookup_is_per_launch_size_and_source_digest():
     else:  # counters taken on other kernel sources are not reported
         assert got is None
     assert bench.measured_traffic(name, int(tiles), "no_such_workload") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
