@@ -1,7 +1,7 @@
 """Plain FP64 CPU oracle for the two-site effective Hamiltonian and the local LCC solve.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product (the HIP library and its Python
-binding) imports, links or runs this package; only the tests, the graft entry's smoke
+binding) imports, links or runs this package; only the tests, the `__graft_entry__.smoke()`
 check and the CPU-baseline leg of the benchmark do.  It shares no code with the GPU path:
 the only common module is `workloads`, which generates the seeded inputs.
 
